@@ -1,0 +1,318 @@
+"""Plain, slow CPU oracle for the SLOS strong-simulation hot path.
+
+TEST INFRASTRUCTURE ONLY: imported by tests/, the smoke check and the CPU
+baseline of bench.py, never by the library.  It shares no code with the HIP
+path (it does not import the package, and the package does not import it).
+
+What each function follows (paper = arXiv 2204.00602):
+  * amplitudes / probabilities: Section 4.2.1, Eq. eqperm -- a(S) is the
+    permanent of U_{T,S} over sqrt(prod s! prod t!), P(S) = |a(S)|^2;
+    the permanent itself is computed by the C library (definition, Ryser,
+    Glynn; Section 3.2.3 names the latter two).
+  * fock_states: the output set S_{m,n} of Section 4.2.1 (all m-tuples of
+    non-negative integers summing to n), enumerated by plain recursion.
+  * partial_certificate: Eq. eqpk.  haar_pk_mean: Eq. eqhaarpk.
+  * beam_splitter_rx: Eq. eq:bs; phase_shifter: the scalar e^{i phi} of
+    Section 2; mzi: the BS, PS(phi_a) on mode 0, BS, PS(phi_b) on mode 1
+    composition of the Appendix B.2 boson-sampling code.
+  * clements_unitary: a rectangular ("square", Section 2) mesh of MZIs; the
+    column layout is this project's reading (the paper only cites the mesh).
+  * grad_U: d Perm(A)/d A[r][c] is the permanent of the (r, c) minor.
+Parity status: every function here is pinned by tests/test_oracle_pins.py
+(closed forms, brute force, the paper's worked examples); none is unpinned.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+RYSER, GLYNN, BRUTE = 0, 1, 2
+_METHODS = {"ryser": RYSER, "glynn": GLYNN, "brute": BRUTE}
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        from . import build as _b
+        _b.build()
+    lib = ctypes.CDLL(_LIB_PATH)
+    dp = ctypes.POINTER(ctypes.c_double)
+    ip = ctypes.POINTER(ctypes.c_int32)
+    lib.oracle_perm.argtypes = [ctypes.c_int, dp, ctypes.c_int, dp]
+    lib.oracle_perm.restype = ctypes.c_int
+    lib.oracle_amplitudes.argtypes = [ctypes.c_int, ctypes.c_int, dp, ip, ctypes.c_int64,
+                                      ip, ctypes.c_int, ctypes.c_int, dp]
+    lib.oracle_amplitudes.restype = ctypes.c_int
+    lib.oracle_grad_U.argtypes = [ctypes.c_int, ctypes.c_int, dp, ip, ctypes.c_int64,
+                                  ip, dp, ctypes.c_int, dp]
+    lib.oracle_grad_U.restype = ctypes.c_int
+    lib.oracle_num_threads.argtypes = []
+    lib.oracle_num_threads.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _dptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _iptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+
+def num_threads() -> int:
+    """Threads the oracle's OpenMP loops use on this host."""
+    return int(_load().oracle_num_threads())
+
+
+def perm(A, method: str = "ryser") -> complex:
+    """Permanent of a square complex matrix (brute force = the definition)."""
+    A = np.ascontiguousarray(np.asarray(A, dtype=np.complex128))
+    n = A.shape[0]
+    assert A.shape == (n, n)
+    out = np.zeros(2, dtype=np.float64)
+    rc = _load().oracle_perm(n, _dptr(A.view(np.float64)), _METHODS[method], _dptr(out))
+    if rc != 0:
+        raise ValueError(f"oracle_perm failed ({rc}) for n={n}, method={method}")
+    return complex(out[0], out[1])
+
+
+def fock_states(m: int, n: int) -> np.ndarray:
+    """All m-tuples of non-negative ints summing to n (the set S_{m,n}).
+
+    Plain recursion, first mode varying slowest; the order carries no meaning.
+    """
+    out = []
+
+    def rec(prefix, left, modes_left):
+        if modes_left == 1:
+            out.append(prefix + [left])
+            return
+        for v in range(left, -1, -1):
+            rec(prefix + [v], left - v, modes_left - 1)
+
+    if m == 0:
+        return np.zeros((1 if n == 0 else 0, 0), dtype=np.int32)
+    rec([], n, m)
+    return np.asarray(out, dtype=np.int32).reshape(-1, m)
+
+
+def amplitudes(U, T, states, method: str = "ryser", threads: int = 0) -> np.ndarray:
+    """a(S) = Perm(U_{T,S}) / sqrt(prod s! prod t!) for each row S of `states`.
+
+    U[j, i] is the amplitude from input mode i to output mode j (Eq. eqperm:
+    rows of U_{T,S} are rows of U repeated s_j times, columns are columns of U
+    repeated t_i times).
+    """
+    U = np.ascontiguousarray(np.asarray(U, dtype=np.complex128))
+    m = U.shape[0]
+    assert U.shape == (m, m)
+    T = np.ascontiguousarray(np.asarray(T, dtype=np.int32).reshape(m))
+    S = np.ascontiguousarray(np.asarray(states, dtype=np.int32).reshape(-1, m))
+    n = int(T.sum())
+    out = np.zeros(2 * S.shape[0], dtype=np.float64)
+    rc = _load().oracle_amplitudes(m, n, _dptr(U.view(np.float64)), _iptr(T), S.shape[0],
+                                   _iptr(S), _METHODS[method], int(threads), _dptr(out))
+    if rc != 0:
+        raise ValueError(f"oracle_amplitudes failed ({rc})")
+    return out.view(np.complex128)
+
+
+def probabilities(U, T, states, method: str = "ryser", threads: int = 0) -> np.ndarray:
+    """P(S) = |a(S)|^2 (Eq. eqperm)."""
+    a = amplitudes(U, T, states, method, threads)
+    return a.real ** 2 + a.imag ** 2
+
+
+def partial_certificate(probs, states, K: int) -> float:
+    """P(K): total probability that modes K+1..m (1-based) are empty (Eq. eqpk)."""
+    states = np.asarray(states)
+    mask = np.all(states[:, K:] == 0, axis=1)
+    return float(np.sum(np.asarray(probs)[mask]))
+
+
+def haar_pk_mean(K: int, m: int, n: int) -> float:
+    """Haar average of P(K): K(K+1)..(K+n-1) / (m(m+1)..(m+n-1)) (Eq. eqhaarpk)."""
+    num = 1.0
+    den = 1.0
+    for r in range(n):
+        num *= K + r
+        den *= m + r
+    return num / den
+
+
+def beam_splitter_rx(theta: float) -> np.ndarray:
+    """Eq. eq:bs: [[cos(theta/2), i sin(theta/2)], [i sin(theta/2), cos(theta/2)]]."""
+    c = math.cos(theta / 2.0)
+    s = math.sin(theta / 2.0)
+    return np.array([[c, 1j * s], [1j * s, c]], dtype=np.complex128)
+
+
+def phase_shifter(phi: float) -> complex:
+    """Section 2: a phase shifter acts on one mode as the scalar e^{i phi}."""
+    return complex(math.cos(phi), math.sin(phi))
+
+
+def mzi(phi_a: float, phi_b: float) -> np.ndarray:
+    """BS, then PS(phi_a) on mode 0, then BS, then PS(phi_b) on mode 1.
+
+    Components later in the circuit multiply on the left; BS is Eq. eq:bs at
+    theta = pi/2 (a 50:50 splitter).
+    """
+    bs = beam_splitter_rx(math.pi / 2.0)
+    ps0 = np.diag([phase_shifter(phi_a), 1.0]).astype(np.complex128)
+    ps1 = np.diag([1.0, phase_shifter(phi_b)]).astype(np.complex128)
+    return ps1 @ bs @ ps0 @ bs
+
+
+def clements_layout(m: int):
+    """MZI positions (column, top mode p) of the rectangular mesh, in order.
+
+    Column c (0..m-1) holds MZIs on modes (p, p+1) with p = c mod 2, c mod 2 + 2, ...
+    and p + 1 < m: m(m-1)/2 MZIs in total.
+    """
+    return [(c, p) for c in range(m) for p in range(c % 2, m - 1, 2)]
+
+
+def clements_unitary(m: int, phases) -> np.ndarray:
+    """U of the mesh: phases[2k], phases[2k+1] = (phi_a, phi_b) of MZI k.
+
+    Each MZI is embedded on its mode pair and applied in layout order, so the
+    first MZI is the right-most factor.
+    """
+    layout = clements_layout(m)
+    phases = np.asarray(phases, dtype=np.float64).reshape(-1)
+    assert phases.size == 2 * len(layout)
+    U = np.eye(m, dtype=np.complex128)
+    for k, (_, p) in enumerate(layout):
+        B = mzi(phases[2 * k], phases[2 * k + 1])
+        E = np.eye(m, dtype=np.complex128)
+        E[p:p + 2, p:p + 2] = B
+        U = E @ U
+    return U
+
+
+def grad_U(U, T, states, w, threads: int = 0) -> np.ndarray:
+    """G[j, i] = sum_S w_S * conj(d a(S)/d U[j, i]) via minor permanents.
+
+    With w_S the PyTorch-convention gradient of a real loss with respect to
+    a(S), G is the PyTorch-convention gradient with respect to U.
+    """
+    U = np.ascontiguousarray(np.asarray(U, dtype=np.complex128))
+    m = U.shape[0]
+    T = np.ascontiguousarray(np.asarray(T, dtype=np.int32).reshape(m))
+    S = np.ascontiguousarray(np.asarray(states, dtype=np.int32).reshape(-1, m))
+    w = np.ascontiguousarray(np.asarray(w, dtype=np.complex128).reshape(-1))
+    assert w.shape[0] == S.shape[0]
+    n = int(T.sum())
+    G = np.zeros(2 * m * m, dtype=np.float64)
+    rc = _load().oracle_grad_U(m, n, _dptr(U.view(np.float64)), _iptr(T), S.shape[0],
+                               _iptr(S), _dptr(w.view(np.float64)), int(threads), _dptr(G))
+    if rc != 0:
+        raise ValueError(f"oracle_grad_U failed ({rc})")
+    return G.view(np.complex128).reshape(m, m)
+
+
+def mesh_loss(phases, m, T, targets, p_target) -> float:
+    """L = sum_S (P(S) - P_target(S))^2 over the target outputs, one phase set."""
+    U = clements_unitary(m, phases)
+    P = probabilities(U, T, targets)
+    return float(np.sum((P - np.asarray(p_target)) ** 2))
+
+
+def mesh_grad_phases(phases, m, T, targets, p_target) -> np.ndarray:
+    """dL/dphases through the minor-permanent gradient and the mesh Jacobian.
+
+    dL/dphi = Re sum_{j,i} conj(G[j,i]) dU[j,i]/dphi, with dU/dphi from the
+    closed form of each MZI factor (d/dphi e^{i phi} = i e^{i phi}).
+    """
+    phases = np.asarray(phases, dtype=np.float64).reshape(-1)
+    U = clements_unitary(m, phases)
+    a = amplitudes(U, T, targets)
+    P = a.real ** 2 + a.imag ** 2
+    dLdP = 2.0 * (P - np.asarray(p_target))
+    w = 2.0 * a * dLdP                    # PyTorch convention for d/d conj(a)
+    G = grad_U(U, T, targets, w)
+    layout = clements_layout(m)
+    factors = []
+    for k, (_, p) in enumerate(layout):
+        E = np.eye(m, dtype=np.complex128)
+        E[p:p + 2, p:p + 2] = mzi(phases[2 * k], phases[2 * k + 1])
+        factors.append(E)
+    # prefix/suffix products: U = F_{K-1} ... F_0
+    K = len(factors)
+    right = [np.eye(m, dtype=np.complex128)]          # right[k] = F_{k-1}..F_0
+    for k in range(K):
+        right.append(factors[k] @ right[-1])
+    left = [np.eye(m, dtype=np.complex128)] * (K + 1)  # left[k] = F_{K-1}..F_{k+1}
+    acc = np.eye(m, dtype=np.complex128)
+    for k in range(K - 1, -1, -1):
+        left[k] = acc
+        acc = acc @ factors[k]
+    grad = np.zeros(2 * K)
+    bs = beam_splitter_rx(math.pi / 2.0)
+    for k, (_, p) in enumerate(layout):
+        pa, pb = phases[2 * k], phases[2 * k + 1]
+        ps0 = np.diag([phase_shifter(pa), 1.0])
+        ps1 = np.diag([1.0, phase_shifter(pb)])
+        dps0 = np.diag([1j * phase_shifter(pa), 0.0])
+        dps1 = np.diag([0.0, 1j * phase_shifter(pb)])
+        for which, dB in ((0, ps1 @ bs @ dps0 @ bs), (1, dps1 @ bs @ ps0 @ bs)):
+            dE = np.zeros((m, m), dtype=np.complex128)
+            dE[p:p + 2, p:p + 2] = dB
+            dU = left[k] @ dE @ right[k]
+            grad[2 * k + which] = float(np.real(np.sum(np.conj(G) * dU)))
+    return grad
+
+
+def mesh_grad_phases_fd(phases, m, T, targets, p_target, h: float = 1e-6) -> np.ndarray:
+    """Central finite differences of mesh_loss in FP64."""
+    phases = np.asarray(phases, dtype=np.float64).reshape(-1).copy()
+    g = np.zeros_like(phases)
+    for k in range(phases.size):
+        old = phases[k]
+        phases[k] = old + h
+        lp = mesh_loss(phases, m, T, targets, p_target)
+        phases[k] = old - h
+        lm = mesh_loss(phases, m, T, targets, p_target)
+        phases[k] = old
+        g[k] = (lp - lm) / (2.0 * h)
+    return g
+
+
+def fock_count(m: int, n: int) -> int:
+    """|S_{m,n}| = C(m+n-1, n) (Section 4.2.2)."""
+    return math.comb(m + n - 1, n)
+
+
+def derangements(n: int) -> int:
+    """!n by the recurrence !n = (n-1)(!(n-1) + !(n-2)), used as a permanent pin."""
+    if n == 0:
+        return 1
+    a, b = 1, 0  # !0, !1
+    for k in range(2, n + 1):
+        a, b = b, (k - 1) * (a + b)
+    return b
+
+
+def fibonacci(n: int) -> int:
+    f0, f1 = 0, 1
+    for _ in range(n):
+        f0, f1 = f1, f0 + f1
+    return f0
+
+
+__all__ = [
+    "perm", "fock_states", "amplitudes", "probabilities", "partial_certificate",
+    "haar_pk_mean", "beam_splitter_rx", "phase_shifter", "mzi", "clements_layout",
+    "clements_unitary", "grad_U", "mesh_loss", "mesh_grad_phases", "mesh_grad_phases_fd",
+    "fock_count", "derangements", "fibonacci", "num_threads",
+]
