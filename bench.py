@@ -1,0 +1,227 @@
+"""Benchmark of the SLOS strong-simulation hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+
+A step is one full-distribution forward pass at m=24 modes, n=12 photons,
+input |1^12 0^12>, on a seeded Haar-random 24x24 unitary: all layers of the
+recurrence, the normalisation and the FP64 sum of P, producing all
+C(35,12) = 834,451,800 amplitudes.  The headline runs in complex64 with
+compensated accumulation on the deep layers; complex64 without compensation
+and complex128 are timed beside it.  Inputs are resident in HBM before the
+timed region.
+
+Prints one JSON line (see `emit`).  The roofline entry covers the dominant
+kernel (the last layer): algorithmic bytes = 8 B x (N_11 read + N_12 written)
+per launch, divided by its average duration from HIP events recorded on the
+launch stream inside the timed region.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+M_MODES, N_PHOTONS, U_SEED, SAMPLE_SEED = 24, 12, 3, 103
+HBM_PEAK_GBPS = 8000.0
+METRIC = "output amplitudes/s + achieved HBM GB/s, c64 vs c128, m=24 n=12, 1 GPU"
+
+
+def layer_sizes(m, n):
+    return [math.comb(m + k - 1, k) for k in range(n + 1)]
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("layer.hip", "slos_internal.h"):
+        with open(os.path.join(ROOT, "paper_2204_00602_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(variant):
+    """HBM bytes per launch of the last layer from a committed rocprofv3 PMC
+    summary, if it was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic_layer12_m24n12.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    v = d.get("variants", {}).get(variant)
+    return None if v is None else v.get("hbm_bytes_per_launch")
+
+
+def time_variant(torch, slos, T, U_np, dtype, compensated, steps, warmup):
+    plan = slos.Plan(T, dtype, compensated=compensated)
+    tdt = torch.complex64 if dtype == "c64" else torch.complex128
+    Ud = torch.from_numpy(U_np).to(tdt).cuda().contiguous()
+    out = torch.empty(plan.num_outputs, dtype=tdt, device="cuda")
+    sum_p = torch.zeros(1, dtype=torch.float64, device="cuda")
+    for _ in range(warmup):
+        plan.amplitudes(Ud, out=out, sum_p=sum_p)
+    torch.cuda.synchronize()
+    plan.set_timing(True)
+    stream = torch.cuda.current_stream()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    layer_ms = []
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(steps):
+        plan.amplitudes(Ud, out=out, sum_p=sum_p, stream=stream)
+        layer_ms.append(plan.layer_ms())   # waits for this step's last event
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    total_ms = ev0.elapsed_time(ev1)
+    plan.set_timing(False)
+    lm = np.asarray(layer_ms)
+    res = {
+        "ms_per_step": total_ms / steps,
+        "layer_ms_mean": lm.mean(axis=0).tolist(),
+        "sum_p": float(sum_p.item()),
+    }
+    del out, Ud
+    plan.close()
+    torch.cuda.empty_cache()
+    return res
+
+
+def cpu_baseline(U_np, T, target_s=15.0):
+    """The oracle, untuned, on a bounded sample of the workload's outputs."""
+    import oracle
+    from paper_2204_00602_amd import inputs
+    cores = oracle.num_threads()
+    calib = inputs.uniform_fock_states(M_MODES, N_PHOTONS, 4 * cores, SAMPLE_SEED)
+    t0 = time.perf_counter()
+    oracle.amplitudes(U_np, T, calib)
+    dt = time.perf_counter() - t0
+    per = dt / len(calib)
+    count = int(min(max(target_s / max(per, 1e-9), 64), 200_000))
+    sample = inputs.uniform_fock_states(M_MODES, N_PHOTONS, count, SAMPLE_SEED + 1)
+    t0 = time.perf_counter()
+    oracle.amplitudes(U_np, T, sample)
+    dt = time.perf_counter() - t0
+    return {
+        "value": len(sample) / dt,
+        "unit": "amplitudes/s",
+        "cores": cores,
+        "kind": "oracle",
+        "sample": (f"{len(sample)} distinct uniformly drawn outputs of the m=24 n=12 workload "
+                   f"(seed {SAMPLE_SEED + 1}), FP64 Ryser permanents with extended-precision "
+                   f"accumulation, OpenMP over outputs, {dt:.1f} s"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only", choices=["c64comp", "c64", "c128"], default=None,
+                    help="time one variant only (for profiling runs)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the multi-GPU sharding is described in DESIGN.md, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py: no HIP device visible", file=sys.stderr)
+        sys.exit(1)
+    from paper_2204_00602_amd import inputs, slos
+    slos.lib()
+
+    m, n = M_MODES, N_PHOTONS
+    T = inputs.first_modes_input(m, n)
+    U = inputs.haar_unitary(m, U_SEED)
+    N = layer_sizes(m, n)
+    M = N[n]
+
+    variants = [("c64comp", "c64", True), ("c64", "c64", False), ("c128", "c128", False)]
+    if args.only:
+        variants = [v for v in variants if v[0] == args.only]
+    results = {}
+    for name, dt, comp in variants:
+        print(f"[bench] timing {name}: {args.warmup} warmup + {args.steps} steps", file=sys.stderr, flush=True)
+        results[name] = time_variant(torch, slos, T, U, dt, comp, args.steps, args.warmup)
+        r = results[name]
+        print(f"[bench] {name}: {r['ms_per_step']:.3f} ms/step, last layer {r['layer_ms_mean'][n - 1]:.3f} ms, "
+              f"sum P = {r['sum_p']:.12f}", file=sys.stderr, flush=True)
+
+    head_name = variants[0][0]
+    head = results[head_name]
+    w = 8 if head_name != "c128" else 16
+    alg_step = slos.algorithmic_bytes(m, n, w)
+    last_bytes = w * (N[n - 1] + N[n])
+    last_ms = head["layer_ms_mean"][n - 1]
+    achieved = last_bytes / (last_ms * 1e-3) / 1e9
+    traffic = load_traffic(head_name)
+
+    line = {
+        "metric": METRIC,
+        "value": M / (head["ms_per_step"] * 1e-3),
+        "unit": "amplitudes/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "complex64" if head_name != "c128" else "complex128",
+        "data": "synthetic: seeded Haar-random 24x24 unitary (QR of complex Gaussian, seed 3), input |1^12 0^12>",
+        "config": {
+            "workload": "SLOS full distribution, m=24 modes, n=12 photons, all 834,451,800 amplitudes"
+                        + (", complex64 with compensated accumulation on layers 11-12" if head_name == "c64comp" else ""),
+            "m": m, "n": n, "outputs": M, "variant": head_name,
+        },
+        "achieved_GBps_step": alg_step / (head["ms_per_step"] * 1e-3) / 1e9,
+        "algorithmic_bytes_step": alg_step,
+        "roofline": {
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBPS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBPS,
+            "traffic": traffic,
+            "kernel": f"layer_kernel (last layer k={n}), {last_bytes} algorithmic bytes per launch, "
+                      f"{last_ms:.4f} ms average over {args.steps} launches",
+        },
+        "sum_p": head["sum_p"],
+        "layer_ms": head["layer_ms_mean"],
+        "variants": {k: {"ms_per_step": v["ms_per_step"],
+                         "amplitudes_per_s": M / (v["ms_per_step"] * 1e-3),
+                         "achieved_GBps_step": slos.algorithmic_bytes(m, n, 16 if k == "c128" else 8)
+                         / (v["ms_per_step"] * 1e-3) / 1e9,
+                         "last_layer_ms": v["layer_ms_mean"][n - 1],
+                         "sum_p": v["sum_p"]} for k, v in results.items()},
+    }
+    if "c128" in results:
+        for k in results:
+            if k != "c128":
+                line["variants"][k]["speedup_over_c128"] = results["c128"]["ms_per_step"] / results[k]["ms_per_step"]
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(U, T)
+    else:
+        line["cpu_baseline"] = None
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,155 @@
+/*
+ * slos.h -- C ABI of the MI355X SLOS strong-simulation library.
+ *
+ * The library computes, for an m-mode linear interferometer U and an n-photon
+ * input Fock state T, the amplitude a(S) of every n-photon output Fock state S
+ * (arXiv 2204.00602, Section 4.2.1, Eq. eqperm):
+ *
+ *     a(S) = Perm(U_{T,S}) / sqrt(s_1!..s_m! t_1!..t_m!),   P(S) = |a(S)|^2,
+ *
+ * by the layered photon-addition recurrence of the SLOS back-end (Section
+ * 3.2.3, "SLOS" paragraph: the whole computation path is unfolded in memory,
+ * time O(n C(m+n-1, n))).  With the photons of T listed as modes
+ * i_1 <= ... <= i_n, A_0 = [1] and, for k = 1..n and every k-photon state t,
+ *
+ *     A_k[t] = sum_{j : t_j > 0} U[j, i_k] * A_{k-1}[t - e_j],
+ *
+ * then a(S) = A_n[S] * sqrt(prod_j s_j!) / sqrt(prod_i t_i!).
+ *
+ * Conventions shared by every entry point
+ *   - U is row-major m x m, U[j*m + i] = amplitude from input mode i to output
+ *     mode j (row = output mode), in the plan's complex type, interleaved
+ *     (re, im).  U is not required to be unitary.
+ *   - Output order: colex rank.  For a k-photon state with photon modes
+ *     d_1 <= ... <= d_k, rank = sum_{r=1..k} C(d_r + r - 1, r); rank 0 holds all
+ *     photons in mode 0.  slos_fock_rank / slos_fock_unrank convert.
+ *   - Device pointers are HIP device allocations owned by the caller; the
+ *     library never frees them.  `stream` is a hipStream_t (NULL = the null
+ *     stream); calls that take one are asynchronous on it.
+ *   - Every function returns SLOS_OK (0) or a negative SLOS_ERR_* code and
+ *     never aborts; slos_last_error() describes the last failure on the
+ *     calling thread.
+ *   - A plan holds scratch memory: use it from one stream at a time.
+ */
+#ifndef SLOS_H
+#define SLOS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------- */
+#define SLOS_OK 0
+#define SLOS_ERR_INVALID_ARG (-1)   /* bad m, n, state, pointer or option        */
+#define SLOS_ERR_SIZE_OVERFLOW (-2) /* C(m+n-1, n) or a buffer size overflows     */
+#define SLOS_ERR_OOM (-3)           /* a device or host allocation failed         */
+#define SLOS_ERR_DTYPE (-4)         /* call does not match the plan's dtype/flags */
+#define SLOS_ERR_HIP (-5)           /* a HIP runtime call or launch failed        */
+#define SLOS_ERR_NOT_KEPT (-6)      /* backward needs a plan with SLOS_KEEP_LAYERS */
+#define SLOS_ERR_NO_DEVICE (-7)     /* no usable HIP device                       */
+
+/* ---- plan flags ---------------------------------------------------------- */
+#define SLOS_C64 0x1          /* complex64 recurrence, fp32 probabilities          */
+#define SLOS_C128 0x2         /* complex128 recurrence, fp64 probabilities         */
+#define SLOS_COMPENSATED 0x100 /* c64 only: error-free (two-sum/two-product)
+                                  accumulation on layers k >= comp_from_layer      */
+#define SLOS_KEEP_LAYERS 0x200 /* keep A_0..A_{n-1} on the device (for backward)   */
+#define SLOS_HOST_ONLY 0x400   /* build the host tables only; no device memory;
+                                  for slos_plan_info / slos_plan_leaf inspection  */
+
+#define SLOS_MAX_MODES 255
+#define SLOS_MAX_PHOTONS 32
+
+typedef struct slos_plan_s *slos_plan_t;
+
+/* Tuning options; a zero field takes its default. */
+typedef struct slos_options {
+    int32_t leaf_max;        /* max states per leaf tile (default 4096, <= 65536)    */
+    int32_t comp_from_layer; /* first compensated layer (default n - 1, min 1)       */
+    int32_t block_threads;   /* threads per workgroup: 64, 128, 256 (default 256)    */
+    int32_t grid_blocks;     /* cap on workgroups per layer launch (default 2048)    */
+    int32_t outputs_per_lane;/* 1, 2 or 4 outputs per lane per tile (default 4)      */
+} slos_options_t;
+
+/* ---- Fock-space arithmetic (host only; no device needed) ------------------ */
+
+/* |S_{m,n}| = C(m+n-1, n) (Section 4.2.2).  SIZE_OVERFLOW if > INT64_MAX. */
+int slos_fock_count(int m, int n, int64_t *count);
+
+/* Colex rank of `state` (m int32 occupations summing to n). */
+int slos_fock_rank(int m, int n, const int32_t *state, int64_t *rank);
+
+/* Inverse of slos_fock_rank: writes m int32 occupations to `state`. */
+int slos_fock_unrank(int m, int n, int64_t rank, int32_t *state);
+
+/* ---- plans ---------------------------------------------------------------- */
+
+/*
+ * Build a plan for m modes (1..255) and the input Fock state `input_state`
+ * (m int32 occupations, all >= 0, summing to n <= 32).  `flags` holds exactly
+ * one of SLOS_C64 / SLOS_C128 plus optional SLOS_COMPENSATED (C64 only),
+ * SLOS_KEEP_LAYERS, SLOS_HOST_ONLY.  Checks that C(m+n-1, n) and all buffers
+ * fit, builds the photon list i_1 <= .. <= i_n (Section 2: photons are
+ * creation operators, so their order does not change the result), the
+ * binomial table, the leaf decomposition of every layer and the inner tables,
+ * and allocates the layer buffers on the current HIP device.  The plan owns all
+ * of this; release it with slos_plan_destroy.  `opts` may be NULL.
+ */
+int slos_plan(int m, int n, const int32_t *input_state, int flags, slos_plan_t *out);
+int slos_plan_ex(int m, int n, const int32_t *input_state, int flags,
+                 const slos_options_t *opts, slos_plan_t *out);
+
+/* Frees everything the plan owns.  NULL is a no-op.  Synchronises the device. */
+void slos_plan_destroy(slos_plan_t plan);
+
+/* Number of outputs M = C(m+n-1, n); -1 for a NULL plan. */
+int64_t slos_num_outputs(slos_plan_t plan);
+
+/* Host-side inspection of the tiling of layer k (1..n): number of states N_k
+ * and number of leaves.  Works on SLOS_HOST_ONLY plans. */
+int slos_plan_info(slos_plan_t plan, int k, int64_t *n_states, int64_t *n_leaves);
+
+/* Leaf `idx` of layer k: rank of its first state, low-mode count q, low photon
+ * count K, and its k-K high photons' modes (descending) in high_modes[0..k-K). */
+int slos_plan_leaf(slos_plan_t plan, int k, int64_t idx, int64_t *out_base,
+                   int32_t *q, int32_t *K, int32_t *high_modes);
+
+/* ---- forward -------------------------------------------------------------- */
+
+/*
+ * All M amplitudes: out[rank(S)] = a(S), M complex values in the plan's type
+ * (device).  U: device, see conventions.  If sum_p (device, one double) is not
+ * NULL it receives sum_S |a(S)|^2 accumulated in FP64 (Section 4.2.1: the P(S)
+ * form a distribution, so this is 1 for unitary U).
+ */
+int slos_amplitudes(slos_plan_t plan, const void *U, void *out, double *sum_p, void *stream);
+
+/*
+ * All M probabilities P(S) = |a(S)|^2 (Eq. eqperm): probs[rank(S)], fp32 for a
+ * C64 plan and fp64 for C128 (device).  sum_p as in slos_amplitudes.
+ */
+int slos_probs(slos_plan_t plan, const void *U, void *probs, double *sum_p, void *stream);
+
+/* ---- timing ----------------------------------------------------------------- */
+
+/*
+ * Turn per-layer timing on (1) or off (0).  While on, each forward call
+ * records a HIP event on its stream before layer 1, after every layer k and
+ * after the final FP64 sum; slos_plan_layer_ms then waits for the last event
+ * and writes ms[k-1] = duration of layer k (k = 1..n) and ms[n] = duration of
+ * the sum reduction (0 if it did not run).  `count` must be >= n + 1.  Events
+ * are owned by the plan.  Leave it off under stream capture.
+ */
+int slos_plan_set_timing(slos_plan_t plan, int on);
+int slos_plan_layer_ms(slos_plan_t plan, float *ms, int count);
+
+/* Last error message on the calling thread ("" if none). */
+const char *slos_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SLOS_H */

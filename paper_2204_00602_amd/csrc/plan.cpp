@@ -1,0 +1,684 @@
+// Host side of the SLOS library: argument checks, Fock-space arithmetic
+// (colex rank / unrank), the leaf tiling of every layer, inner tables, device
+// buffers and the launch sequence of the layer recurrence.
+//
+// Method: arXiv 2204.00602, Section 3.2.3 (SLOS back-end: unfold the whole
+// computation path, time O(n C(m+n-1, n))) and Section 4.2.1 (Eq. eqperm, the
+// amplitude each output must equal).
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "slos_internal.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what)
+{
+    return fail(e == hipErrorOutOfMemory ? SLOS_ERR_OOM : SLOS_ERR_HIP, "%s: %s", what,
+                hipGetErrorString(e));
+}
+
+constexpr uint64_t kSat = ~uint64_t(0);
+
+// Pascal table C(a, b), 0 <= a <= amax, 0 <= b <= bmax; saturates at kSat.
+struct Binom {
+    int amax = 0, bmax = 0, stride = 0;
+    std::vector<uint64_t> t;
+    void build(int amax_, int bmax_)
+    {
+        amax = amax_;
+        bmax = bmax_;
+        stride = bmax + 1;
+        t.assign((size_t)(amax + 1) * stride, 0);
+        for (int a = 0; a <= amax; ++a) {
+            t[(size_t)a * stride] = 1;
+            for (int b = 1; b <= std::min(a, bmax); ++b) {
+                uint64_t x = t[(size_t)(a - 1) * stride + b - 1];
+                uint64_t y = t[(size_t)(a - 1) * stride + b];
+                uint64_t s;
+                t[(size_t)a * stride + b] =
+                    (x == kSat || y == kSat || __builtin_add_overflow(x, y, &s)) ? kSat : s;
+            }
+        }
+    }
+    uint64_t operator()(int a, int b) const
+    {
+        if (a < 0 || b < 0 || b > a) return 0;
+        return t[(size_t)a * stride + b];
+    }
+};
+
+// Exact C(a, b) with overflow detection (for the public count/rank helpers).
+bool binom_exact(int a, int b, uint64_t *out)
+{
+    if (b < 0 || a < 0 || b > a) {
+        *out = 0;
+        return true;
+    }
+    b = std::min(b, a - b);
+    unsigned __int128 r = 1;
+    for (int i = 1; i <= b; ++i) {
+        r = r * (unsigned __int128)(a - b + i) / (unsigned __int128)i;
+        if (r > (unsigned __int128)INT64_MAX) return false;
+    }
+    *out = (uint64_t)r;
+    return true;
+}
+
+int check_state(int m, int n, const int32_t *s, const char *what)
+{
+    if (!s) return fail(SLOS_ERR_INVALID_ARG, "%s is NULL", what);
+    long tot = 0;
+    for (int j = 0; j < m; ++j) {
+        if (s[j] < 0) return fail(SLOS_ERR_INVALID_ARG, "%s[%d] = %d is negative", what, j, s[j]);
+        tot += s[j];
+    }
+    if (tot != n)
+        return fail(SLOS_ERR_INVALID_ARG, "%s holds %ld photons, expected %d", what, tot, n);
+    return SLOS_OK;
+}
+
+// Colex rank of the k-photon state occ (m modes) with a saturating table.
+uint64_t colex_rank(const Binom &B, int m, const int32_t *occ)
+{
+    uint64_t r = 0;
+    int pos = 0;
+    for (int j = 0; j < m; ++j)
+        for (int c = 0; c < occ[j]; ++c) {
+            ++pos;
+            r += B(j + pos - 1, pos);
+        }
+    return r;
+}
+
+// Inverse: photon positions r = k..1 take the largest c_r < c_{r+1} with
+// C(c_r, r) <= remaining rank; the photon's mode is c_r - r + 1.
+void colex_unrank(const Binom &B, int m, int k, uint64_t rank, int32_t *occ)
+{
+    std::fill(occ, occ + m, 0);
+    int c = m + k - 1;  // exclusive upper bound for c_k
+    for (int r = k; r >= 1; --r) {
+        int cc = c - 1;
+        while (cc >= r && B(cc, r) > rank) --cc;
+        if (cc < r - 1) cc = r - 1;
+        rank -= B(cc, r);
+        occ[cc - r + 1] += 1;
+        c = cc;
+    }
+}
+
+} // namespace
+
+struct slos_plan_s {
+    int m = 0, n = 0, flags = 0;
+    bool c64 = true, comp = false, keep = false, host_only = false;
+    slos_options_t opts{};
+    std::vector<int> photons;      // i_1 <= ... <= i_n
+    double norm_t = 1.0;           // 1 / sqrt(prod t!)
+    Binom B;
+    std::vector<uint64_t> Nk;      // N_0 .. N_n
+    std::vector<std::vector<LeafRec>> leaves;  // index k = 1..n
+    std::vector<InnerType> types;
+    std::vector<uint32_t> pred;
+    std::vector<double> lowfac;
+    std::map<std::pair<int, int>, uint32_t> type_of;
+
+    // device
+    int device = -1;
+    uint64_t *d_binom = nullptr;
+    LeafRec *d_leaves = nullptr;
+    std::vector<uint64_t> leaf_off;   // per layer offset into d_leaves
+    InnerType *d_types = nullptr;
+    uint32_t *d_pred = nullptr;
+    double *d_lowfac = nullptr;
+    void *d_vac = nullptr;            // A_0 = [1]
+    void *d_buf[2] = {nullptr, nullptr};
+    void *d_keep = nullptr;           // A_0..A_{n-1} when KEEP_LAYERS
+    std::vector<uint64_t> keep_off;   // element offsets of A_k in d_keep
+    double *d_partials = nullptr;
+    int n_partials = 0;
+    bool timing = false;
+    bool timed_reduce = false;
+    std::vector<hipEvent_t> events;   // n + 2 when timing is on
+
+    size_t elem() const { return c64 ? 8 : 16; }
+
+    uint32_t inner_type(int q, int K)
+    {
+        auto key = std::make_pair(q, K);
+        auto it = type_of.find(key);
+        if (it != type_of.end()) return it->second;
+        InnerType ty{};
+        ty.q = (uint32_t)q;
+        ty.K = (uint32_t)K;
+        ty.size = (uint32_t)B(q + K - 1, K);
+        std::vector<int32_t> occ(q), sub(q);
+        // first pass: cmax
+        uint32_t cmax = 0;
+        for (uint32_t x = 0; x < ty.size; ++x) {
+            colex_unrank(B, q, K, x, occ.data());
+            uint32_t cnt = 0;
+            for (int j = 0; j < q; ++j) cnt += occ[j] > 0;
+            cmax = std::max(cmax, cnt);
+        }
+        ty.cmax = cmax;
+        ty.pred_off = pred.size();
+        ty.fac_off = lowfac.size();
+        pred.resize(pred.size() + (size_t)cmax * ty.size, SLOS_ZERO_MODE << 24);
+        lowfac.resize(lowfac.size() + ty.size, 1.0);
+        for (uint32_t x = 0; x < ty.size; ++x) {
+            colex_unrank(B, q, K, x, occ.data());
+            uint32_t c = 0;
+            double f = 1.0;
+            for (int j = 0; j < q; ++j) {
+                for (int v = 2; v <= occ[j]; ++v) f *= v;
+                if (occ[j] == 0) continue;
+                sub = occ;
+                sub[j] -= 1;
+                uint64_t p = colex_rank(B, q, sub.data());
+                pred[ty.pred_off + (size_t)c * ty.size + x] = ((uint32_t)j << 24) | (uint32_t)p;
+                ++c;
+            }
+            lowfac[ty.fac_off + x] = std::sqrt(f);
+        }
+        uint32_t id = (uint32_t)types.size();
+        types.push_back(ty);
+        type_of[key] = id;
+        return id;
+    }
+
+    // Leaves of layer k: split F(j+1, K) by the occupation of mode j (blocks
+    // t_j = 0, 1, .., K in colex order) until a block holds <= leaf_max states.
+    void gen_leaves(int k, int j, int K, std::vector<uint8_t> &hm, std::vector<LeafRec> &out)
+    {
+        uint64_t size = B(j + K, K);
+        if (K == 0 || j == 0 || size <= (uint64_t)opts.leaf_max) {
+            LeafRec L{};
+            L.q = (uint8_t)(j + 1);
+            L.K = (uint8_t)K;
+            L.nhp = (uint8_t)hm.size();
+            for (size_t i = 0; i < hm.size(); ++i) L.hm[i] = hm[i];
+            L.size = (uint32_t)size;
+            L.tab = inner_type(j + 1, K);
+            // rank of the leaf's first state: low photons all in mode 0 add
+            // C(r-1, r) = 0; high photon at position r = k - idx adds C(d+r-1, r)
+            uint64_t base = 0;
+            for (size_t idx = 0; idx < hm.size(); ++idx) {
+                int r = k - (int)idx;
+                base += B(hm[idx] + r - 1, r);
+            }
+            L.out_base = base;
+            out.push_back(L);
+            return;
+        }
+        for (int s = 0; s <= K; ++s) {
+            for (int c = 0; c < s; ++c) hm.push_back((uint8_t)j);
+            gen_leaves(k, j - 1, K - s, hm, out);
+            for (int c = 0; c < s; ++c) hm.pop_back();
+        }
+    }
+
+    void free_device()
+    {
+        auto f = [](void *p) {
+            if (p) (void)hipFree(p);
+        };
+        f(d_binom);
+        f(d_leaves);
+        f(d_types);
+        f(d_pred);
+        f(d_lowfac);
+        f(d_vac);
+        f(d_buf[0]);
+        f(d_buf[1]);
+        f(d_keep);
+        f(d_partials);
+        d_binom = nullptr;
+        d_leaves = nullptr;
+        d_types = nullptr;
+        d_pred = nullptr;
+        d_lowfac = nullptr;
+        d_vac = nullptr;
+        d_buf[0] = d_buf[1] = nullptr;
+        d_keep = nullptr;
+        d_partials = nullptr;
+        for (hipEvent_t ev : events) (void)hipEventDestroy(ev);
+        events.clear();
+    }
+};
+
+namespace {
+
+template <typename T>
+int dev_upload(T **dst, const T *src, size_t count, const char *what)
+{
+    size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+    hipError_t e = hipMalloc((void **)dst, bytes);
+    if (e != hipSuccess) return hip_fail(e, what);
+    if (count) {
+        e = hipMemcpy(*dst, src, count * sizeof(T), hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_fail(e, what);
+    }
+    return SLOS_OK;
+}
+
+int alloc_dev(void **dst, size_t bytes, const char *what)
+{
+    hipError_t e = hipMalloc(dst, std::max<size_t>(bytes, 1));
+    if (e != hipSuccess) return hip_fail(e, what);
+    return SLOS_OK;
+}
+
+int check_plan(slos_plan_t p)
+{
+    if (!p) return fail(SLOS_ERR_INVALID_ARG, "plan is NULL");
+    if (p->host_only) return fail(SLOS_ERR_INVALID_ARG, "plan was built with SLOS_HOST_ONLY");
+    return SLOS_OK;
+}
+
+} // namespace
+
+extern "C" {
+
+const char *slos_last_error(void) { return g_last_error.c_str(); }
+
+int slos_fock_count(int m, int n, int64_t *count)
+{
+    if (m < 1 || n < 0 || !count) return fail(SLOS_ERR_INVALID_ARG, "need m >= 1, n >= 0, count != NULL");
+    uint64_t c;
+    if (!binom_exact(m + n - 1, n, &c))
+        return fail(SLOS_ERR_SIZE_OVERFLOW, "C(%d, %d) exceeds int64", m + n - 1, n);
+    *count = (int64_t)c;
+    return SLOS_OK;
+}
+
+int slos_fock_rank(int m, int n, const int32_t *state, int64_t *rank)
+{
+    if (m < 1 || n < 0 || !rank) return fail(SLOS_ERR_INVALID_ARG, "need m >= 1, n >= 0, rank != NULL");
+    int rc = check_state(m, n, state, "state");
+    if (rc) return rc;
+    int64_t cnt;
+    if ((rc = slos_fock_count(m, n, &cnt))) return rc;
+    Binom B;
+    B.build(m + n, n);
+    *rank = (int64_t)colex_rank(B, m, state);
+    return SLOS_OK;
+}
+
+int slos_fock_unrank(int m, int n, int64_t rank, int32_t *state)
+{
+    if (m < 1 || n < 0 || !state) return fail(SLOS_ERR_INVALID_ARG, "need m >= 1, n >= 0, state != NULL");
+    int64_t cnt;
+    int rc = slos_fock_count(m, n, &cnt);
+    if (rc) return rc;
+    if (rank < 0 || rank >= cnt)
+        return fail(SLOS_ERR_INVALID_ARG, "rank %lld outside [0, %lld)", (long long)rank, (long long)cnt);
+    Binom B;
+    B.build(m + n, n);
+    colex_unrank(B, m, n, (uint64_t)rank, state);
+    return SLOS_OK;
+}
+
+int slos_plan(int m, int n, const int32_t *input_state, int flags, slos_plan_t *out)
+{
+    return slos_plan_ex(m, n, input_state, flags, nullptr, out);
+}
+
+int slos_plan_ex(int m, int n, const int32_t *input_state, int flags, const slos_options_t *opts,
+                 slos_plan_t *out)
+{
+    if (!out) return fail(SLOS_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (m < 1 || m > SLOS_MAX_MODES)
+        return fail(SLOS_ERR_INVALID_ARG, "m = %d outside [1, %d]", m, SLOS_MAX_MODES);
+    if (n < 0 || n > SLOS_MAX_PHOTONS)
+        return fail(SLOS_ERR_INVALID_ARG, "n = %d outside [0, %d]", n, SLOS_MAX_PHOTONS);
+    int rc = check_state(m, n, input_state, "input_state");
+    if (rc) return rc;
+    const int known = SLOS_C64 | SLOS_C128 | SLOS_COMPENSATED | SLOS_KEEP_LAYERS | SLOS_HOST_ONLY;
+    if (flags & ~known) return fail(SLOS_ERR_INVALID_ARG, "unknown flag bits 0x%x", flags & ~known);
+    int dt = flags & (SLOS_C64 | SLOS_C128);
+    if (dt != SLOS_C64 && dt != SLOS_C128)
+        return fail(SLOS_ERR_DTYPE, "flags must hold exactly one of SLOS_C64, SLOS_C128");
+    if ((flags & SLOS_COMPENSATED) && dt != SLOS_C64)
+        return fail(SLOS_ERR_DTYPE, "SLOS_COMPENSATED applies to SLOS_C64 plans only");
+    int64_t M;
+    if ((rc = slos_fock_count(m, n, &M))) return rc;
+
+    slos_options_t o{};
+    if (opts) o = *opts;
+    if (o.leaf_max == 0) o.leaf_max = 4096;
+    if (o.comp_from_layer == 0) o.comp_from_layer = std::max(1, n - 1);
+    if (o.block_threads == 0) o.block_threads = 256;
+    if (o.grid_blocks == 0) o.grid_blocks = 2048;
+    if (o.outputs_per_lane == 0) o.outputs_per_lane = 4;
+    if (o.leaf_max < 1 || o.leaf_max > 65536)
+        return fail(SLOS_ERR_INVALID_ARG, "leaf_max = %d outside [1, 65536]", o.leaf_max);
+    if (o.block_threads != 64 && o.block_threads != 128 && o.block_threads != 256)
+        return fail(SLOS_ERR_INVALID_ARG, "block_threads must be 64, 128 or 256");
+    if (o.grid_blocks < 1 || o.grid_blocks > (1 << 20))
+        return fail(SLOS_ERR_INVALID_ARG, "grid_blocks = %d outside [1, 2^20]", o.grid_blocks);
+    if (o.outputs_per_lane != 1 && o.outputs_per_lane != 2 && o.outputs_per_lane != 4)
+        return fail(SLOS_ERR_INVALID_ARG, "outputs_per_lane must be 1, 2 or 4");
+    if (o.comp_from_layer < 1)
+        return fail(SLOS_ERR_INVALID_ARG, "comp_from_layer must be >= 1");
+
+    slos_plan_s *p = new (std::nothrow) slos_plan_s;
+    if (!p) return fail(SLOS_ERR_OOM, "host allocation of the plan failed");
+    p->m = m;
+    p->n = n;
+    p->flags = flags;
+    p->c64 = dt == SLOS_C64;
+    p->comp = (flags & SLOS_COMPENSATED) != 0;
+    p->keep = (flags & SLOS_KEEP_LAYERS) != 0;
+    p->host_only = (flags & SLOS_HOST_ONLY) != 0;
+    p->opts = o;
+
+    try {
+        double tf = 1.0;
+        for (int i = 0; i < m; ++i) {
+            for (int c = 0; c < input_state[i]; ++c) p->photons.push_back(i);
+            for (int v = 2; v <= input_state[i]; ++v) tf *= v;
+        }
+        p->norm_t = 1.0 / std::sqrt(tf);
+        p->B.build(m + n, n);
+        p->Nk.resize(n + 1);
+        for (int k = 0; k <= n; ++k) p->Nk[k] = p->B(m + k - 1, k);
+
+        // size checks: every buffer in bytes must fit size_t with room to spare
+        uint64_t maxN = *std::max_element(p->Nk.begin(), p->Nk.end());
+        if (maxN > (uint64_t(1) << 58))
+            throw std::pair<int, std::string>(SLOS_ERR_SIZE_OVERFLOW, "layer too large for a device buffer");
+
+        p->leaves.resize(n + 1);
+        for (int k = 1; k <= n; ++k) {
+            std::vector<uint8_t> hm;
+            p->gen_leaves(k, m - 1, k, hm, p->leaves[k]);
+        }
+    } catch (std::bad_alloc &) {
+        delete p;
+        return fail(SLOS_ERR_OOM, "host allocation failed while building tables");
+    } catch (std::pair<int, std::string> &e) {
+        delete p;
+        return fail(e.first, "%s", e.second.c_str());
+    }
+
+    if (p->host_only) {
+        *out = p;
+        return SLOS_OK;
+    }
+
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess || ndev < 1) {
+        delete p;
+        return fail(SLOS_ERR_NO_DEVICE, "no HIP device (%s)", hipGetErrorString(e));
+    }
+    (void)hipGetDevice(&p->device);
+
+    // upload tables
+    std::vector<LeafRec> all;
+    p->leaf_off.assign(n + 2, 0);
+    for (int k = 1; k <= n; ++k) {
+        p->leaf_off[k] = all.size();
+        all.insert(all.end(), p->leaves[k].begin(), p->leaves[k].end());
+    }
+    p->leaf_off[n + 1] = all.size();
+    if ((rc = dev_upload(&p->d_binom, p->B.t.data(), p->B.t.size(), "binomial table")) ||
+        (rc = dev_upload(&p->d_leaves, all.data(), all.size(), "leaf table")) ||
+        (rc = dev_upload(&p->d_types, p->types.data(), p->types.size(), "inner types")) ||
+        (rc = dev_upload(&p->d_pred, p->pred.data(), p->pred.size(), "inner predecessor table")) ||
+        (rc = dev_upload(&p->d_lowfac, p->lowfac.data(), p->lowfac.size(), "inner factorial table"))) {
+        p->free_device();
+        delete p;
+        return rc;
+    }
+
+    // A_0 = [1]
+    const size_t es = p->elem();
+    {
+        double one_d[2] = {1.0, 0.0};
+        float one_f[2] = {1.0f, 0.0f};
+        if ((rc = alloc_dev(&p->d_vac, es, "vacuum layer"))) {
+            p->free_device();
+            delete p;
+            return rc;
+        }
+        e = hipMemcpy(p->d_vac, p->c64 ? (const void *)one_f : (const void *)one_d, es,
+                      hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            rc = hip_fail(e, "vacuum upload");
+            p->free_device();
+            delete p;
+            return rc;
+        }
+    }
+    // intermediate layers 1..n-1
+    if (p->keep) {
+        p->keep_off.assign(n + 1, 0);
+        uint64_t tot = 0;
+        for (int k = 0; k < n; ++k) {
+            p->keep_off[k] = tot;
+            tot += (p->Nk[k] + 15) / 16 * 16;  // 128-byte aligned layers
+        }
+        p->keep_off[n] = tot;
+        if ((rc = alloc_dev(&p->d_keep, tot * es, "kept layers"))) {
+            p->free_device();
+            delete p;
+            return rc;
+        }
+        e = hipMemcpy(p->d_keep, p->d_vac, es, hipMemcpyDeviceToDevice);
+        if (e != hipSuccess) {
+            rc = hip_fail(e, "kept vacuum layer");
+            p->free_device();
+            delete p;
+            return rc;
+        }
+    } else {
+        uint64_t need[2] = {0, 0};
+        for (int k = 1; k < n; ++k) need[k & 1] = std::max(need[k & 1], p->Nk[k]);
+        for (int b = 0; b < 2; ++b)
+            if (need[b] && (rc = alloc_dev(&p->d_buf[b], need[b] * es, "layer buffer"))) {
+                p->free_device();
+                delete p;
+                return rc;
+            }
+    }
+    p->n_partials = p->opts.grid_blocks * (p->opts.block_threads / 64);
+    if ((rc = alloc_dev((void **)&p->d_partials, (size_t)p->n_partials * sizeof(double), "partial sums"))) {
+        p->free_device();
+        delete p;
+        return rc;
+    }
+    *out = p;
+    return SLOS_OK;
+}
+
+void slos_plan_destroy(slos_plan_t p)
+{
+    if (!p) return;
+    if (!p->host_only) {
+        (void)hipDeviceSynchronize();
+        p->free_device();
+    }
+    delete p;
+}
+
+int64_t slos_num_outputs(slos_plan_t p)
+{
+    if (!p) return -1;
+    return (int64_t)p->Nk[p->n];
+}
+
+int slos_plan_info(slos_plan_t p, int k, int64_t *n_states, int64_t *n_leaves)
+{
+    if (!p) return fail(SLOS_ERR_INVALID_ARG, "plan is NULL");
+    if (k < 1 || k > p->n) return fail(SLOS_ERR_INVALID_ARG, "layer %d outside [1, %d]", k, p->n);
+    if (n_states) *n_states = (int64_t)p->Nk[k];
+    if (n_leaves) *n_leaves = (int64_t)p->leaves[k].size();
+    return SLOS_OK;
+}
+
+int slos_plan_leaf(slos_plan_t p, int k, int64_t idx, int64_t *out_base, int32_t *q, int32_t *K,
+                   int32_t *high_modes)
+{
+    if (!p) return fail(SLOS_ERR_INVALID_ARG, "plan is NULL");
+    if (k < 1 || k > p->n) return fail(SLOS_ERR_INVALID_ARG, "layer %d outside [1, %d]", k, p->n);
+    if (idx < 0 || (size_t)idx >= p->leaves[k].size())
+        return fail(SLOS_ERR_INVALID_ARG, "leaf %lld out of range", (long long)idx);
+    const LeafRec &L = p->leaves[k][idx];
+    if (out_base) *out_base = (int64_t)L.out_base;
+    if (q) *q = L.q;
+    if (K) *K = L.K;
+    if (high_modes)
+        for (int i = 0; i < L.nhp; ++i) high_modes[i] = L.hm[i];
+    return SLOS_OK;
+}
+
+static int run_forward(slos_plan_t p, const void *U, void *out, double *sum_p, void *stream, int last_mode)
+{
+    int rc = check_plan(p);
+    if (rc) return rc;
+    if (!U || !out) return fail(SLOS_ERR_INVALID_ARG, "U and out must be device pointers");
+    const int n = p->n;
+    if (n == 0) {
+        int e = slos_launch_vacuum(out, p->c64, last_mode, sum_p, stream);
+        if (e) return hip_fail((hipError_t)e, "vacuum kernel");
+        return SLOS_OK;
+    }
+    const size_t es = p->elem();
+    const int wpb = p->opts.block_threads / 64;
+    hipStream_t hs = (hipStream_t)stream;
+    if (p->timing) {
+        hipError_t e = hipEventRecord(p->events[0], hs);
+        if (e != hipSuccess) return hip_fail(e, "timing event");
+        p->timed_reduce = false;
+    }
+    for (int k = 1; k <= n; ++k) {
+        LayerParams lp{};
+        if (p->keep) {
+            lp.X = (const char *)p->d_keep + p->keep_off[k - 1] * es;
+            lp.Y = k == n ? out : (void *)((char *)p->d_keep + p->keep_off[k] * es);
+        } else {
+            lp.X = k == 1 ? p->d_vac : p->d_buf[(k - 1) & 1];
+            lp.Y = k == n ? out : p->d_buf[k & 1];
+        }
+        lp.U = U;
+        lp.leaves = p->d_leaves + p->leaf_off[k];
+        lp.nleaves = p->leaves[k].size();
+        lp.types = p->d_types;
+        lp.pred = p->d_pred;
+        lp.lowfac = p->d_lowfac;
+        lp.binom = p->d_binom;
+        lp.bstride = p->B.stride;
+        lp.m = p->m;
+        lp.k = k;
+        lp.col = p->photons[k - 1];
+        lp.norm_t = p->norm_t;
+        lp.partials = p->d_partials;
+        LayerLaunch ll{};
+        ll.c64 = p->c64;
+        ll.mode = k == n ? last_mode : SLOS_MODE_MID;
+        ll.compensated = p->comp && k >= p->opts.comp_from_layer;
+        ll.rr = p->opts.outputs_per_lane;
+        ll.threads = p->opts.block_threads;
+        uint64_t want = (lp.nleaves + wpb - 1) / wpb;
+        ll.grid = (int)std::min<uint64_t>(want, (uint64_t)p->opts.grid_blocks);
+        if (ll.grid < 1) ll.grid = 1;
+        if (k == n) {
+            // every wave of the last launch writes one partial
+            if (ll.grid * wpb > p->n_partials) return fail(SLOS_ERR_INVALID_ARG, "partial buffer too small");
+        }
+        int e = slos_launch_layer(lp, ll, stream);
+        if (e) return hip_fail((hipError_t)e, "layer kernel");
+        if (p->timing && (e = (int)hipEventRecord(p->events[k], hs)))
+            return hip_fail((hipError_t)e, "timing event");
+        if (k == n && sum_p) {
+            e = slos_launch_reduce(p->d_partials, ll.grid * wpb, sum_p, stream);
+            if (e) return hip_fail((hipError_t)e, "sum reduction kernel");
+            if (p->timing) {
+                if ((e = (int)hipEventRecord(p->events[n + 1], hs)))
+                    return hip_fail((hipError_t)e, "timing event");
+                p->timed_reduce = true;
+            }
+        }
+    }
+    return SLOS_OK;
+}
+
+int slos_plan_set_timing(slos_plan_t p, int on)
+{
+    int rc = check_plan(p);
+    if (rc) return rc;
+    if (on && p->events.empty()) {
+        p->events.resize(p->n + 2);
+        for (auto &ev : p->events) {
+            hipError_t e = hipEventCreate(&ev);
+            if (e != hipSuccess) {
+                ev = nullptr;
+                return hip_fail(e, "hipEventCreate");
+            }
+        }
+    }
+    p->timing = on != 0;
+    return SLOS_OK;
+}
+
+int slos_plan_layer_ms(slos_plan_t p, float *ms, int count)
+{
+    int rc = check_plan(p);
+    if (rc) return rc;
+    if (!p->timing) return fail(SLOS_ERR_INVALID_ARG, "timing is off for this plan");
+    if (!ms || count < p->n + 1) return fail(SLOS_ERR_INVALID_ARG, "ms needs n + 1 = %d entries", p->n + 1);
+    if (p->n == 0) {
+        ms[0] = 0.f;
+        return SLOS_OK;
+    }
+    hipEvent_t last = p->timed_reduce ? p->events[p->n + 1] : p->events[p->n];
+    hipError_t e = hipEventSynchronize(last);
+    if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+    for (int k = 1; k <= p->n; ++k) {
+        e = hipEventElapsedTime(&ms[k - 1], p->events[k - 1], p->events[k]);
+        if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+    }
+    ms[p->n] = 0.f;
+    if (p->timed_reduce) {
+        e = hipEventElapsedTime(&ms[p->n], p->events[p->n], p->events[p->n + 1]);
+        if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+    }
+    return SLOS_OK;
+}
+
+int slos_amplitudes(slos_plan_t p, const void *U, void *out, double *sum_p, void *stream)
+{
+    return run_forward(p, U, out, sum_p, stream, SLOS_MODE_AMPL);
+}
+
+int slos_probs(slos_plan_t p, const void *U, void *probs, double *sum_p, void *stream)
+{
+    return run_forward(p, U, probs, sum_p, stream, SLOS_MODE_PROB);
+}
+
+} // extern "C"

@@ -1,0 +1,260 @@
+"""Python binding of the SLOS C ABI (include/slos.h): argument marshalling only.
+
+Every step of the computation runs in the HIP library; torch provides device
+memory and the stream.  The library is loaded from this package directory and
+a missing or unloadable library raises -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libslos.so")
+
+SLOS_OK = 0
+SLOS_C64 = 0x1
+SLOS_C128 = 0x2
+SLOS_COMPENSATED = 0x100
+SLOS_KEEP_LAYERS = 0x200
+SLOS_HOST_ONLY = 0x400
+MAX_MODES = 255
+MAX_PHOTONS = 32
+
+ERRORS = {
+    -1: "INVALID_ARG", -2: "SIZE_OVERFLOW", -3: "OOM", -4: "DTYPE",
+    -5: "HIP_ERROR", -6: "NOT_KEPT", -7: "NO_DEVICE",
+}
+
+
+class SlosError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("leaf_max", ctypes.c_int32), ("comp_from_layer", ctypes.c_int32),
+                ("block_threads", ctypes.c_int32), ("grid_blocks", ctypes.c_int32),
+                ("outputs_per_lane", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libslos.so (raises if it was not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_2204_00602_amd.build` (needs hipcc)")
+    L = ctypes.CDLL(LIB_PATH)
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    vp = ctypes.c_void_p
+    L.slos_fock_count.argtypes = [ctypes.c_int, ctypes.c_int, i64p]
+    L.slos_fock_rank.argtypes = [ctypes.c_int, ctypes.c_int, i32p, i64p]
+    L.slos_fock_unrank.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64, i32p]
+    L.slos_plan.argtypes = [ctypes.c_int, ctypes.c_int, i32p, ctypes.c_int, ctypes.POINTER(vp)]
+    L.slos_plan_ex.argtypes = [ctypes.c_int, ctypes.c_int, i32p, ctypes.c_int,
+                               ctypes.POINTER(Options), ctypes.POINTER(vp)]
+    L.slos_plan_destroy.argtypes = [vp]
+    L.slos_plan_destroy.restype = None
+    L.slos_num_outputs.argtypes = [vp]
+    L.slos_num_outputs.restype = ctypes.c_int64
+    L.slos_plan_info.argtypes = [vp, ctypes.c_int, i64p, i64p]
+    L.slos_plan_leaf.argtypes = [vp, ctypes.c_int, ctypes.c_int64, i64p, i32p, i32p, i32p]
+    L.slos_amplitudes.argtypes = [vp, vp, vp, vp, vp]
+    L.slos_probs.argtypes = [vp, vp, vp, vp, vp]
+    L.slos_plan_set_timing.argtypes = [vp, ctypes.c_int]
+    L.slos_plan_layer_ms.argtypes = [vp, ctypes.POINTER(ctypes.c_float), ctypes.c_int]
+    L.slos_last_error.argtypes = []
+    L.slos_last_error.restype = ctypes.c_char_p
+    for name in ("slos_fock_count", "slos_fock_rank", "slos_fock_unrank", "slos_plan",
+                 "slos_plan_ex", "slos_plan_info", "slos_plan_leaf", "slos_amplitudes",
+                 "slos_probs", "slos_plan_set_timing", "slos_plan_layer_ms"):
+        getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(rc: int):
+    if rc != SLOS_OK:
+        raise SlosError(rc, lib().slos_last_error().decode(errors="replace"))
+
+
+def _state_arr(state, m=None):
+    a = np.ascontiguousarray(np.asarray(state, dtype=np.int32).reshape(-1))
+    if m is not None and a.size != m:
+        raise ValueError(f"state has {a.size} modes, expected {m}")
+    return a
+
+
+def fock_count(m: int, n: int) -> int:
+    out = ctypes.c_int64()
+    _check(lib().slos_fock_count(m, n, ctypes.byref(out)))
+    return out.value
+
+
+def fock_rank(state) -> int:
+    s = _state_arr(state)
+    out = ctypes.c_int64()
+    _check(lib().slos_fock_rank(s.size, int(s.sum()), s.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                ctypes.byref(out)))
+    return out.value
+
+
+def fock_unrank(m: int, n: int, rank: int) -> np.ndarray:
+    s = np.zeros(m, dtype=np.int32)
+    _check(lib().slos_fock_unrank(m, n, int(rank), s.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+    return s
+
+
+def _stream_ptr(stream) -> int:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream)
+
+
+class Plan:
+    """Compile-once plan for (m, input_state, dtype); run for many U.
+
+    Mirrors the paper's `backend(U).compile(input_state)` then `all_prob`
+    usage (Appendix B.6) with the output order fixed to colex rank.
+    """
+
+    def __init__(self, input_state: Sequence[int], dtype: str = "c64", compensated: bool = False,
+                 keep_layers: bool = False, host_only: bool = False,
+                 options: Optional[dict] = None):
+        self.input_state = _state_arr(input_state)
+        self.m = int(self.input_state.size)
+        self.n = int(self.input_state.sum())
+        if dtype not in ("c64", "c128"):
+            raise ValueError("dtype must be 'c64' or 'c128'")
+        self.dtype = dtype
+        flags = SLOS_C64 if dtype == "c64" else SLOS_C128
+        if compensated:
+            flags |= SLOS_COMPENSATED
+        if keep_layers:
+            flags |= SLOS_KEEP_LAYERS
+        if host_only:
+            flags |= SLOS_HOST_ONLY
+        self.flags = flags
+        self.host_only = host_only
+        opts = Options()
+        for k, v in (options or {}).items():
+            setattr(opts, k, int(v))
+        self.options = dict(options or {})
+        handle = ctypes.c_void_p()
+        self._lib = lib()
+        _check(self._lib.slos_plan_ex(self.m, self.n,
+                                      self.input_state.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                      flags, ctypes.byref(opts), ctypes.byref(handle)))
+        self._h = handle
+        self.num_outputs = int(self._lib.slos_num_outputs(handle))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.slos_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- inspection -----------------------------------------------------
+    def layer_info(self, k: int):
+        ns, nl = ctypes.c_int64(), ctypes.c_int64()
+        _check(self._lib.slos_plan_info(self._h, k, ctypes.byref(ns), ctypes.byref(nl)))
+        return ns.value, nl.value
+
+    def leaf(self, k: int, idx: int):
+        ob = ctypes.c_int64()
+        q, K = ctypes.c_int32(), ctypes.c_int32()
+        hm = (ctypes.c_int32 * MAX_PHOTONS)()
+        _check(self._lib.slos_plan_leaf(self._h, k, idx, ctypes.byref(ob), ctypes.byref(q),
+                                        ctypes.byref(K), hm))
+        return ob.value, q.value, K.value, [hm[i] for i in range(k - K.value)]
+
+    # ---- timing -------------------------------------------------------------
+    def set_timing(self, on: bool = True):
+        """Record HIP events around every layer launch of later calls."""
+        _check(self._lib.slos_plan_set_timing(self._h, 1 if on else 0))
+
+    def layer_ms(self):
+        """Per-layer kernel durations (ms) of the last call; last entry = FP64 sum."""
+        buf = (ctypes.c_float * (self.n + 1))()
+        _check(self._lib.slos_plan_layer_ms(self._h, buf, self.n + 1))
+        return [buf[i] for i in range(self.n + 1)]
+
+    # ---- device calls -----------------------------------------------------
+    def _complex_dtype(self):
+        import torch
+        return torch.complex64 if self.dtype == "c64" else torch.complex128
+
+    def _check_U(self, U):
+        import torch
+        if not isinstance(U, torch.Tensor) or U.device.type != "cuda":
+            raise TypeError("U must be a CUDA (HIP) torch tensor")
+        if U.dtype != self._complex_dtype():
+            raise TypeError(f"U must be {self._complex_dtype()} for a {self.dtype} plan")
+        if tuple(U.shape) != (self.m, self.m) or not U.is_contiguous():
+            raise ValueError(f"U must be a contiguous {self.m}x{self.m} tensor")
+
+    def amplitudes(self, U, out=None, sum_p=None, stream=None):
+        """out[rank(S)] = a(S) for all S; returns out (and fills sum_p[0] = sum P if given)."""
+        import torch
+        self._check_U(U)
+        if out is None:
+            out = torch.empty(self.num_outputs, dtype=self._complex_dtype(), device=U.device)
+        elif out.dtype != self._complex_dtype() or out.numel() != self.num_outputs or not out.is_contiguous():
+            raise ValueError("out has the wrong dtype, size or layout")
+        sp = None
+        if sum_p is not None:
+            if sum_p.dtype != torch.float64 or sum_p.device != U.device:
+                raise TypeError("sum_p must be a float64 tensor on the same device")
+            sp = sum_p.data_ptr()
+        _check(self._lib.slos_amplitudes(self._h, U.data_ptr(), out.data_ptr(), sp, _stream_ptr(stream)))
+        return out
+
+    def probs(self, U, out=None, sum_p=None, stream=None):
+        """out[rank(S)] = P(S) (float32 for c64, float64 for c128)."""
+        import torch
+        self._check_U(U)
+        rdt = torch.float32 if self.dtype == "c64" else torch.float64
+        if out is None:
+            out = torch.empty(self.num_outputs, dtype=rdt, device=U.device)
+        elif out.dtype != rdt or out.numel() != self.num_outputs or not out.is_contiguous():
+            raise ValueError("out has the wrong dtype, size or layout")
+        sp = None
+        if sum_p is not None:
+            if sum_p.dtype != torch.float64 or sum_p.device != U.device:
+                raise TypeError("sum_p must be a float64 tensor on the same device")
+            sp = sum_p.data_ptr()
+        _check(self._lib.slos_probs(self._h, U.data_ptr(), out.data_ptr(), sp, _stream_ptr(stream)))
+        return out
+
+    def rank(self, state) -> int:
+        s = _state_arr(state, self.m)
+        if int(s.sum()) != self.n:
+            raise ValueError("state has the wrong photon number")
+        return fock_rank(s)
+
+    def unrank(self, r: int) -> np.ndarray:
+        return fock_unrank(self.m, self.n, r)
+
+
+def algorithmic_bytes(m: int, n: int, elem_bytes: int, last_write_bytes: Optional[int] = None) -> int:
+    """Bytes the recurrence must move: every layer A_0..A_{n-1} read once, A_1..A_n written once."""
+    import math
+    N = [math.comb(m + k - 1, k) for k in range(n + 1)]
+    lw = elem_bytes if last_write_bytes is None else last_write_bytes
+    return elem_bytes * sum(N[:n]) + elem_bytes * sum(N[1:n]) + lw * N[n]

@@ -1,0 +1,157 @@
+"""CPU tests of the C ABI's host logic: exports, Fock ranking, leaf tiling, errors.
+
+No GPU is touched: plans here use SLOS_HOST_ONLY, and device calls are only
+checked for their argument validation.
+"""
+import itertools
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2204_00602_amd import slos
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    txt = open(os.path.join(ROOT, "include", "slos.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(slos_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = header_functions()
+    assert "slos_amplitudes" in names and "slos_plan" in names
+    L = slos.lib()
+    for name in names:
+        assert hasattr(L, name), name
+
+
+@pytest.mark.parametrize("m,n", [(1, 0), (1, 7), (6, 3), (12, 6), (24, 12), (255, 3)])
+def test_fock_count(m, n):
+    assert slos.fock_count(m, n) == math.comb(m + n - 1, n)
+
+
+def test_fock_count_overflow_detected():
+    with pytest.raises(slos.SlosError) as e:
+        slos.fock_count(255, 32)
+    assert e.value.code == -2
+
+
+def rev_lex_key(s):
+    return tuple(reversed(list(s)))
+
+
+@pytest.mark.parametrize("m,n", [(1, 4), (2, 3), (3, 3), (5, 4), (6, 3), (4, 6), (8, 2)])
+def test_rank_unrank_bijection_and_colex_order(m, n):
+    M = math.comb(m + n - 1, n)
+    states = [slos.fock_unrank(m, n, r) for r in range(M)]
+    assert all(s.sum() == n and s.min() >= 0 for s in states)
+    assert len({s.tobytes() for s in states}) == M
+    for r, s in enumerate(states):
+        assert slos.fock_rank(s) == r
+    # colex = lexicographic on the occupation vector read from the last mode
+    keys = [rev_lex_key(s) for s in states]
+    assert keys == sorted(keys)
+    assert np.array_equal(states[0], np.eye(m, dtype=np.int32)[0] * n)
+
+
+def test_rank_spot_checks_24_12():
+    rng = np.random.default_rng(3)
+    M = math.comb(35, 12)
+    for r in list(rng.integers(0, M, 200)) + [0, M - 1]:
+        s = slos.fock_unrank(24, 12, int(r))
+        assert slos.fock_rank(s) == r
+    top = np.zeros(24, np.int32)
+    top[-1] = 12
+    assert slos.fock_rank(top) == M - 1
+
+
+def test_rank_rejects_bad_states():
+    with pytest.raises(slos.SlosError):
+        slos.fock_rank([1, -1, 2])
+    with pytest.raises(slos.SlosError):
+        slos.fock_unrank(3, 2, 6)  # only 6 states: ranks 0..5
+
+
+@pytest.mark.parametrize("m,T,leaf_max", [
+    (6, [1, 1, 1, 0, 0, 0], 4096), (6, [1, 1, 1, 0, 0, 0], 3), (12, [1] * 6 + [0] * 6, 64),
+    (9, [2, 0, 1, 0, 0, 2, 0, 0, 1], 17), (3, [4, 0, 2], 1), (14, [1, 2, 0, 1, 0, 0, 2, 0, 1, 0, 0, 0, 0, 0], 256),
+    (20, [1] * 5 + [0] * 15, 128),
+])
+def test_leaf_tiling_covers_each_layer_once(m, T, leaf_max):
+    p = slos.Plan(T, "c64", host_only=True, options={"leaf_max": leaf_max})
+    n = int(sum(T))
+    for k in range(1, n + 1):
+        Nk, nl = p.layer_info(k)
+        assert Nk == math.comb(m + k - 1, k)
+        nxt = 0
+        for idx in range(nl):
+            base, q, K, hm = p.leaf(k, idx)
+            size = math.comb(q + K - 1, K)
+            assert base == nxt, (k, idx)
+            assert size <= leaf_max or K == 0 or q == 1 or (q == m and size == Nk)
+            assert len(hm) == k - K and all(h >= q for h in hm) and hm == sorted(hm, reverse=True)
+            # first and last state of the leaf: same high part, low part spans F(q, K)
+            first = slos.fock_unrank(m, k, base)
+            last = slos.fock_unrank(m, k, base + size - 1)
+            high = np.zeros(m, np.int32)
+            for h in hm:
+                high[h] += 1
+            assert np.array_equal(first[q:], high[q:]) and np.array_equal(last[q:], high[q:])
+            assert first[0] == K and last[q - 1] == K
+            nxt = base + size
+        assert nxt == Nk
+
+
+def test_plan_argument_validation():
+    bad = [
+        ((0, 0, [], slos.SLOS_C64), -1),
+        ((3, 2, [1, 0, 0], slos.SLOS_C64), -1),          # wrong photon count
+        ((3, 1, [2, -1, 0], slos.SLOS_C64), -1),         # negative occupation
+        ((3, 1, [1, 0, 0], slos.SLOS_C64 | slos.SLOS_C128), -4),
+        ((3, 1, [1, 0, 0], 0), -4),
+        ((3, 1, [1, 0, 0], slos.SLOS_C128 | slos.SLOS_COMPENSATED), -4),
+        ((3, 1, [1, 0, 0], slos.SLOS_C64 | 0x8000), -1),
+        ((256, 1, [1] + [0] * 255, slos.SLOS_C64), -1),
+        ((2, 33, [33, 0], slos.SLOS_C64), -1),
+    ]
+    import ctypes
+    L = slos.lib()
+    for (m, n, T, flags), code in bad:
+        arr = np.asarray(T if T else [0], dtype=np.int32)
+        h = ctypes.c_void_p()
+        rc = L.slos_plan(m, n, arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), flags, ctypes.byref(h))
+        assert rc == code, (m, n, T, flags, rc, L.slos_last_error())
+        assert not h.value
+        assert L.slos_last_error()
+
+
+def test_plan_options_validation():
+    for opts in ({"leaf_max": 70000}, {"block_threads": 96}, {"outputs_per_lane": 3},
+                 {"grid_blocks": -1}, {"comp_from_layer": -2}):
+        with pytest.raises(slos.SlosError) as e:
+            slos.Plan([1, 1, 0], "c64", host_only=True, options=opts)
+        assert e.value.code == -1
+
+
+def test_device_calls_reject_null_and_host_only_plans():
+    L = slos.lib()
+    assert L.slos_amplitudes(None, None, None, None, None) == -1
+    assert L.slos_num_outputs(None) == -1
+    L.slos_plan_destroy(None)
+    p = slos.Plan([1, 1, 0], "c64", host_only=True)
+    assert L.slos_probs(p._h, None, None, None, None) == -1
+    assert p.num_outputs == 6
+
+
+def test_algorithmic_bytes_formula():
+    # m=24, n=12, c64: 13.35 GB (each layer read once and written once)
+    b = slos.algorithmic_bytes(24, 12, 8)
+    assert abs(b / 1e9 - 13.35) < 0.01
+    assert slos.algorithmic_bytes(24, 12, 16) == 2 * b
+    N = [math.comb(6 + k - 1, k) for k in range(4)]
+    assert slos.algorithmic_bytes(6, 3, 16) == 16 * (sum(N[:3]) + sum(N[1:]))

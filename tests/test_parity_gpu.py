@@ -1,0 +1,272 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Outputs are compared by Fock tuple: the oracle enumerates S_{m,n} on its own
+and each tuple is looked up at the rank the library's rank function gives.
+
+Tolerances (per output S, with M outputs):
+  complex128: |a_gpu - a_ref| <= 1e-12 * max(|a_ref|, 1/sqrt(M))
+  complex64:  |P_gpu - P_ref| <= 1e-5 * max(P_ref, 1/M)
+  sum P:      |sum - 1| <= 1e-12 (c128) / 1e-6 (c64) for unitary U
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2204_00602_amd import inputs, slos
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def need_gpu():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    slos.lib()  # raises if the library is missing
+
+
+def dev_u(U, dtype):
+    t = torch.complex64 if dtype == "c64" else torch.complex128
+    return torch.from_numpy(np.ascontiguousarray(U)).to(t).cuda().contiguous()
+
+
+def run(T, U, dtype="c128", compensated=False, options=None, probs=False):
+    p = slos.Plan(T, dtype, compensated=compensated, options=options)
+    Ud = dev_u(U, dtype)
+    s = torch.zeros(1, dtype=torch.float64, device="cuda")
+    out = p.probs(Ud, sum_p=s) if probs else p.amplitudes(Ud, sum_p=s)
+    torch.cuda.synchronize()
+    return p, out, float(s.item())
+
+
+def gather(p, out, states):
+    idx = torch.tensor([slos.fock_rank(s) for s in states], dtype=torch.int64, device="cuda")
+    return out[idx].cpu().numpy()
+
+
+def check_c128(a, ref, M):
+    floor = 1.0 / math.sqrt(M)
+    err = np.abs(a - ref) / np.maximum(np.abs(ref), floor)
+    assert err.max() <= 1e-12, f"max floored rel err {err.max():.3e}"
+
+
+def check_c64_probs(P, Pref, M):
+    err = np.abs(P - Pref) / np.maximum(Pref, 1.0 / M)
+    assert err.max() <= 1e-5, f"max floored rel err {err.max():.3e}"
+    return err.max()
+
+
+def haar_case(m, T, seed):
+    return np.asarray(T, np.int32), inputs.haar_unitary(m, seed)
+
+
+# -------------------------------------------------------- small configs
+
+def test_config1_m6_n3_c128_all_outputs():
+    T, U = haar_case(6, [1, 1, 1, 0, 0, 0], 1)
+    p, out, s = run(T, U, "c128")
+    S = oracle.fock_states(6, 3)
+    assert p.num_outputs == S.shape[0] == 56
+    check_c128(gather(p, out, S), oracle.amplitudes(U, T, S), 56)
+    assert abs(s - 1.0) <= 1e-12
+
+
+def test_hom_zero_on_50_50_beam_splitter():
+    U = oracle.beam_splitter_rx(math.pi / 2)
+    for dtype in ("c128", "c64"):
+        p, out, s = run([1, 1], U, dtype)
+        a = gather(p, out, [[2, 0], [1, 1], [0, 2]])
+        P = np.abs(a) ** 2
+        assert P[1] <= (1e-30 if dtype == "c128" else 1e-14)
+        assert np.allclose(P[[0, 2]], 0.5, rtol=1e-6 if dtype == "c64" else 1e-15)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_config2_m12_n6_all_outputs(dtype):
+    T, U = haar_case(12, [1] * 6 + [0] * 6, 2)
+    p, out, s = run(T, U, dtype)
+    S = oracle.fock_states(12, 6)
+    ref = oracle.amplitudes(U, T, S)
+    a = gather(p, out, S)
+    if dtype == "c128":
+        check_c128(a, ref, 12376)
+        assert abs(s - 1.0) <= 1e-12
+    else:
+        check_c64_probs(np.abs(a.astype(np.complex128)) ** 2, np.abs(ref) ** 2, 12376)
+        assert abs(s - 1.0) <= 1e-6
+
+
+@pytest.mark.parametrize("opts", [
+    {"leaf_max": 7, "outputs_per_lane": 4},
+    {"leaf_max": 64, "outputs_per_lane": 1, "block_threads": 64},
+    {"leaf_max": 300, "outputs_per_lane": 2, "block_threads": 128, "grid_blocks": 3},
+    {"leaf_max": 1, "outputs_per_lane": 4, "grid_blocks": 1},
+    {"leaf_max": 65536},
+])
+def test_tilings_and_launch_shapes_agree(opts):
+    T, U = haar_case(9, [2, 0, 1, 0, 0, 2, 0, 0, 1], 9)
+    S = oracle.fock_states(9, 6)
+    ref = oracle.amplitudes(U, T, S)
+    p, out, s = run(T, U, "c128", options=opts)
+    check_c128(gather(p, out, S), ref, S.shape[0])
+    assert abs(s - 1.0) <= 1e-12
+
+
+@pytest.mark.parametrize("comp", [False, True])
+def test_compensated_c64_and_probs_api(comp):
+    T, U = haar_case(10, [1, 0, 2, 0, 1, 0, 0, 1, 0, 0], 12)
+    S = oracle.fock_states(10, 5)
+    Pref = oracle.probabilities(U, T, S)
+    p, out, s = run(T, U, "c64", compensated=comp, options={"comp_from_layer": 1}, probs=True)
+    assert out.dtype == torch.float32
+    check_c64_probs(gather(p, out, S).astype(np.float64), Pref, S.shape[0])
+    assert abs(s - 1.0) <= 1e-6
+    p, out, s = run(T, U, "c128", probs=True)
+    assert out.dtype == torch.float64
+    got = gather(p, out, S)
+    assert np.max(np.abs(got - Pref) / np.maximum(Pref, 1.0 / S.shape[0])) <= 2e-12
+
+
+# ---------------------------------------------------- closed forms, edges
+
+def test_vacuum_and_single_mode():
+    U = inputs.haar_unitary(4, 3)
+    p, out, s = run([0, 0, 0, 0], U, "c128")
+    assert p.num_outputs == 1 and out.cpu().numpy()[0] == 1.0 and s == 1.0
+    u = np.array([[0.6 - 0.3j]])
+    for n in (1, 5, 12):
+        p, out, s = run([n], u, "c128")
+        assert out.cpu().numpy()[0] == pytest.approx((0.6 - 0.3j) ** n, rel=1e-14)
+
+
+def test_single_photon_is_a_column_of_U():
+    U = inputs.haar_unitary(7, 4)
+    for i in (0, 3, 6):
+        T = np.zeros(7, np.int32)
+        T[i] = 1
+        p, out, _ = run(T, U, "c128")
+        a = gather(p, out, np.eye(7, dtype=np.int32))
+        assert np.allclose(a, U[:, i], atol=1e-16)
+
+
+def test_identity_all_ones_rank_one_closed_forms():
+    m, T = 5, np.array([2, 0, 1, 1, 0], np.int32)
+    n = int(T.sum())
+    S = oracle.fock_states(m, n)
+    p, out, _ = run(T, np.eye(m), "c128")
+    a = gather(p, out, S)
+    want = np.array([1.0 if np.array_equal(s, T) else 0.0 for s in S])
+    assert np.array_equal(a, want)
+    ft = np.prod([math.factorial(t) for t in T])
+    fs = np.array([np.prod([math.factorial(x) for x in s]) for s in S])
+    p, out, _ = run(T, np.ones((m, m)), "c128")
+    assert np.allclose(gather(p, out, S), math.factorial(n) / np.sqrt(fs * ft), rtol=1e-14)
+    rng = np.random.default_rng(5)
+    u = rng.standard_normal(m) + 1j * rng.standard_normal(m)
+    v = rng.standard_normal(m) + 1j * rng.standard_normal(m)
+    want = np.array([math.factorial(n) * np.prod(u ** s) * np.prod(v ** T) for s in S]) / np.sqrt(fs * ft)
+    p, out, _ = run(T, np.outer(u, v), "c128")
+    assert np.allclose(gather(p, out, S), want, rtol=1e-12)
+
+
+@pytest.mark.parametrize("m,n", [(6, 3), (12, 6), (8, 4), (4, 4)])
+def test_fourier_suppression_law(m, n):
+    F = inputs.fourier_unitary(m)
+    T = inputs.periodic_input(m, n)
+    p, out, s = run(T, F, "c128")
+    P = np.abs(out.cpu().numpy()) ** 2
+    M = p.num_outputs
+    states = np.stack([slos.fock_unrank(m, n, r) for r in range(M)])
+    q = (states * np.arange(m)).sum(axis=1) % n
+    assert P[q != 0].max() < 1e-26
+    assert abs(P[q == 0].sum() - 1.0) < 1e-12
+
+
+def test_ralph_cnot_truth_table(golden_dir):
+    import json
+    import os
+    g = json.load(open(os.path.join(golden_dir, "ralph_cnot.json")))
+    U = np.zeros((6, 6), np.complex128)
+    for j, row in enumerate(g["unitary"]):
+        for i, ((a, r), (b, sq)) in enumerate(row):
+            U[j, i] = (a * math.sqrt(r) + 1j * b * math.sqrt(sq)) / 3.0
+    logical = {k: np.array(v, np.int32) for k, v in g["logical_states"].items()}
+    perf = g["performance"][0] / g["performance"][1]
+    for kin, tin in logical.items():
+        p, out, _ = run(tin, U, "c128", probs=True)
+        for kout, tout in logical.items():
+            got = gather(p, out, [tout])[0]
+            want = perf if g["expected_map"][kin] == kout else 0.0
+            assert got == pytest.approx(want, abs=1e-15)
+
+
+def test_reciprocity_through_the_gpu():
+    m = 6
+    U = inputs.haar_unitary(m, 13)
+    T = np.array([1, 0, 2, 0, 0, 1], np.int32)
+    S = oracle.fock_states(m, 4)
+    p, out, _ = run(T, U, "c128", probs=True)
+    fwd = gather(p, out, S)
+    index = {tuple(s): i for i, s in enumerate(S)}
+    for s in S[::7]:
+        pb, ob, _ = run(s, np.ascontiguousarray(U.T), "c128", probs=True)
+        assert gather(pb, ob, [T])[0] == pytest.approx(fwd[index[tuple(s)]], abs=1e-14)
+
+
+def test_bitwise_determinism():
+    T, U = haar_case(12, [1] * 6 + [0] * 6, 22)
+    p = slos.Plan(T, "c64", compensated=True)
+    Ud = dev_u(U, "c64")
+    a1 = p.amplitudes(Ud).clone()
+    a2 = p.amplitudes(Ud)
+    torch.cuda.synchronize()
+    assert torch.equal(a1.view(torch.float32), a2.view(torch.float32))
+
+
+# ------------------------------------------- full-size headline workload
+
+def _sampled_states(m, n, P_gpu_dev, seed):
+    uni = inputs.uniform_fock_states(m, n, 10_000, seed)
+    bunched = inputs.bunched_fock_states(m, n, 100)
+    top = torch.topk(P_gpu_dev, 100).indices.cpu().numpy()
+    topS = np.stack([slos.fock_unrank(m, n, int(r)) for r in top])
+    return np.concatenate([uni, bunched, topS])
+
+
+def test_config3_m24_n12_c64_compensated_sampled():
+    """Headline size, launched as the benchmark launches it: 10k uniform
+    seeded outputs, the 100 most bunched and the 100 largest P vs the oracle."""
+    m, n = 24, 12
+    T = inputs.first_modes_input(m, n)
+    U = inputs.haar_unitary(m, 3)
+    p = slos.Plan(T, "c64", compensated=True)
+    Ud = dev_u(U, "c64")
+    s = torch.zeros(1, dtype=torch.float64, device="cuda")
+    out = p.amplitudes(Ud, sum_p=s)
+    torch.cuda.synchronize()
+    assert abs(float(s.item()) - 1.0) <= 1e-6
+    P_dev = out.abs() ** 2
+    S = _sampled_states(m, n, P_dev, 103)
+    a = gather(p, out, S).astype(np.complex128)
+    ref = oracle.amplitudes(U, T, S)
+    M = p.num_outputs
+    err = check_c64_probs(np.abs(a) ** 2, np.abs(ref) ** 2, M)
+    print(f"config3 c64+comp max floored rel err on P: {err:.3e}")
+    del out, P_dev
+    torch.cuda.empty_cache()
+
+
+def test_config3_m24_n12_c128_sampled():
+    m, n = 24, 12
+    T = inputs.first_modes_input(m, n)
+    U = inputs.haar_unitary(m, 3)
+    p = slos.Plan(T, "c128")
+    s = torch.zeros(1, dtype=torch.float64, device="cuda")
+    out = p.amplitudes(dev_u(U, "c128"), sum_p=s)
+    torch.cuda.synchronize()
+    assert abs(float(s.item()) - 1.0) <= 1e-12
+    S = inputs.uniform_fock_states(m, n, 2000, 104)
+    check_c128(gather(p, out, S), oracle.amplitudes(U, T, S), p.num_outputs)
+    del out
+    torch.cuda.empty_cache()
