@@ -133,6 +133,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", choices=["c64comp", "c64", "c128"], default=None,
                     help="time one variant only (for profiling runs)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run a plain 1 GiB device copy three times, so that a PMC "
+                         "profile of this command holds the counters of a copy of known size")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -145,6 +148,16 @@ def main():
         sys.exit(1)
     from paper_2204_00602_amd import inputs, slos
     slos.lib()
+
+    if args.calibrate_copy:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")   # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        torch.cuda.empty_cache()
+        print("[bench] copy calibration: 3 x 1 GiB device-to-device copies", file=sys.stderr, flush=True)
 
     m, n = M_MODES, N_PHOTONS
     T = inputs.first_modes_input(m, n)

@@ -80,16 +80,264 @@ template <> struct Acc<float, true> {
     __device__ __forceinline__ double im() const { return (double)a.s.y + (double)a.c.y; }
 };
 
-constexpr int kMaxWaves = 4;  // workgroups of at most 256 threads
+// cache-policy operand of the global-to-LDS copy: bit 1 = non-temporal
+#define SLOS_CPOL_NT 2
 
-template <typename T, int MODE, bool COMP, int RR>
+// ---- cross-lane helpers (wave64) -------------------------------------------
+__device__ __forceinline__ uint32_t rl32(uint32_t v, int l) { return (uint32_t)__builtin_amdgcn_readlane((int)v, l); }
+__device__ __forceinline__ uint64_t rl64(uint64_t v, int l)
+{
+    return (uint64_t)rl32((uint32_t)v, l) | ((uint64_t)rl32((uint32_t)(v >> 32), l) << 32);
+}
+__device__ __forceinline__ float rlv(float v, int l) { return __uint_as_float(rl32(__float_as_uint(v), l)); }
+__device__ __forceinline__ double rlv(double v, int l)
+{
+    return __longlong_as_double((long long)rl64((uint64_t)__double_as_longlong(v), l));
+}
+// dst lane receives `v` from the lane that names it (ds_permute); later writers win
+__device__ __forceinline__ uint32_t push32(uint32_t v, int dst)
+{
+    return (uint32_t)__builtin_amdgcn_ds_permute(dst << 2, (int)v);
+}
+__device__ __forceinline__ uint64_t push64(uint64_t v, int dst)
+{
+    return (uint64_t)push32((uint32_t)v, dst) | ((uint64_t)push32((uint32_t)(v >> 32), dst) << 32);
+}
+__device__ __forceinline__ float pushv(float v, int dst) { return __uint_as_float(push32(__float_as_uint(v), dst)); }
+__device__ __forceinline__ double pushv(double v, int dst)
+{
+    return __longlong_as_double((long long)push64((uint64_t)__double_as_longlong(v), dst));
+}
+
+// ---- leaf descriptors --------------------------------------------------------
+// A descriptor is fetched with one coalesced load (lane l holds dword l) and
+// read back with readlane, so every field is wave-uniform.
+template <bool WIDE> struct DescT;
+template <> struct DescT<false> {
+    using type = LeafDescNarrow;
+    static constexpr int kDwords = (int)(sizeof(LeafDescNarrow) / 4);
+};
+template <> struct DescT<true> {
+    using type = LeafDescWide;
+    static constexpr int kDwords = (int)(sizeof(LeafDescWide) / 4);
+};
+
+// Lanes 0..63 hold dwords 0..63 of the descriptor (the wide form uses a
+// second register for dwords 64..83).
+template <bool WIDE>
+struct DescRegs {
+    uint32_t a;
+    uint32_t b;
+};
+
+template <bool WIDE>
+__device__ __forceinline__ DescRegs<WIDE> load_desc(const void *descs, uint64_t li, int lane)
+{
+    const uint32_t *w = (const uint32_t *)((const char *)descs + li * sizeof(typename DescT<WIDE>::type));
+    DescRegs<WIDE> r;
+    constexpr int nd = DescT<WIDE>::kDwords;
+    r.a = lane < nd ? __builtin_nontemporal_load(&w[lane]) : 0u;
+    r.b = (WIDE && lane + 64 < nd) ? __builtin_nontemporal_load(&w[64 + lane]) : 0u;
+    return r;
+}
+
+template <bool WIDE>
+__device__ __forceinline__ uint32_t desc_dword(const DescRegs<WIDE> &r, int i)
+{
+    return i < 64 ? rl32(r.a, i) : rl32(r.b, i - 64);
+}
+
+struct Leaf {
+    uint64_t out_base;
+    uint64_t low_base;
+    double fac_hi;
+    uint32_t size;
+    uint32_t low_size;
+    uint32_t pred_off;
+    uint32_t fac_off;
+    int cmax;
+    int nh;
+};
+
+template <bool WIDE>
+__device__ __forceinline__ Leaf decode_head(const DescRegs<WIDE> &r)
+{
+    Leaf L;
+    L.out_base = (uint64_t)rl32(r.a, 0) | ((uint64_t)rl32(r.a, 1) << 32);
+    L.low_base = (uint64_t)rl32(r.a, 2) | ((uint64_t)rl32(r.a, 3) << 32);
+    L.fac_hi = __longlong_as_double((long long)((uint64_t)rl32(r.a, 4) | ((uint64_t)rl32(r.a, 5) << 32)));
+    L.size = rl32(r.a, 6);
+    L.low_size = rl32(r.a, 7);
+    L.pred_off = rl32(r.a, 8);
+    L.fac_off = rl32(r.a, 9);
+    const uint32_t ck = rl32(r.a, 10);
+    L.cmax = (int)(ck & 0xFFu);
+    L.nh = (int)((ck >> 8) & 0xFFu);
+    return L;
+}
+
+// rank in A_{k-1} of group g's block and the mode of group g
+template <bool WIDE>
+__device__ __forceinline__ uint64_t group_base(const DescRegs<WIDE> &r, const Leaf &L, int g)
+{
+    if (WIDE) {
+        const int d = 12 + 2 * g;
+        const uint64_t dl = (uint64_t)desc_dword<WIDE>(r, d) | ((uint64_t)desc_dword<WIDE>(r, d + 1) << 32);
+        return L.low_base - dl;
+    }
+    return L.low_base - (uint64_t)rl32(r.a, 12 + g);
+}
+
+template <bool WIDE>
+__device__ __forceinline__ int group_mode(const DescRegs<WIDE> &r, int g)
+{
+    constexpr int first = WIDE ? 12 + 2 * SLOS_WIDE_GROUPS : 12 + SLOS_NARROW_GROUPS;
+    return (int)((desc_dword<WIDE>(r, first + (g >> 2)) >> (8 * (g & 3))) & 0xFFu);
+}
+
+// Loads through a wave-uniform base pointer and a 32-bit per-lane byte
+// offset (the scalar-base + vector-offset addressing form).
+template <typename V>
+__device__ __forceinline__ V ld_off(const void *base, uint32_t off)
+{
+    return *(const V *)((const char *)base + off);
+}
+
+// Stage A_{k-1}[low_base, low_base + low_size) into this wave's LDS slice with
+// direct global-to-LDS copies of 16-byte chunks (64 lanes x 16 B per
+// instruction).  The copy starts at the 16-byte boundary at or below the
+// block, so the block begins `skew` bytes into the slice; up to 1 KiB past
+// the block is read as well (the layer buffers carry that slack).
+template <typename C>
+__device__ __forceinline__ const C *stage_low(const C *__restrict__ X, const Leaf &L, unsigned char *slice,
+                                              int lane)
+{
+    const uintptr_t sa = (uintptr_t)(X + L.low_base);
+    const uintptr_t a0 = sa & ~(uintptr_t)15;
+    const uint32_t skew = (uint32_t)(sa - a0);
+    const uint32_t nbytes = skew + L.low_size * (uint32_t)sizeof(C);
+    // each input element is staged exactly once per layer, so the copy is
+    // non-temporal (cache policy NT) and leaves the L2 to the high-mode blocks
+    for (uint32_t done = 0; done < nbytes; done += 1024u) {
+        if (done + 16u * (uint32_t)lane < nbytes) {
+            const void *src = (const void *)(a0 + done + 16u * (uint32_t)lane);
+            __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void *)(slice + done), 16, 0,
+                                             SLOS_CPOL_NT);
+        }
+    }
+    return (const C *)(slice + skew);
+}
+
+// One tile: RT outputs per lane, x = t0 + i*64 + lane clamped to the leaf so
+// every load is in bounds.  All block loads (up to HS high groups) and table
+// loads (up to CS low terms) of the tile are issued before any is used.
+template <typename T, int MODE, bool COMP, int RT, bool WIDE>
+__device__ __forceinline__ void tile(const LayerParams &p, const DescRegs<WIDE> &dr, const Leaf &L,
+                                     const typename Cx<T>::type *__restrict__ X,
+                                     const typename Cx<T>::type *u_lds, const typename Cx<T>::type *lowbuf,
+                                     uint32_t t0, int lane, double &psum)
+{
+    using C = typename Cx<T>::type;
+    constexpr int HS = 8;
+    constexpr int CS = 8;
+    uint32_t xc[RT], off[RT];
+    bool ok[RT];
+#pragma unroll
+    for (int i = 0; i < RT; ++i) {
+        const uint32_t x = t0 + (uint32_t)(i * 64 + lane);
+        ok[i] = x < L.size;
+        xc[i] = ok[i] ? x : L.size - 1u;
+        off[i] = xc[i] * (uint32_t)sizeof(C);
+    }
+    const uint32_t *__restrict__ pred = p.pred + L.pred_off;
+
+    // ---- issue
+    C v[HS][RT];
+    uint32_t e[CS][RT];
+    double lf[RT];
+#pragma unroll
+    for (int g = 0; g < HS; ++g) {
+        if (g < L.nh) {
+            const C *Xb = X + group_base<WIDE>(dr, L, g);
+#pragma unroll
+            for (int i = 0; i < RT; ++i) v[g][i] = ld_off<C>(Xb, off[i]);
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < CS; ++c) {
+        if (c < L.cmax) {
+#pragma unroll
+            for (int i = 0; i < RT; ++i) e[c][i] = ld_off<uint32_t>(pred, ((uint32_t)c * L.size + xc[i]) * 4u);
+        }
+    }
+    if (MODE != SLOS_MODE_MID) {
+#pragma unroll
+        for (int i = 0; i < RT; ++i) lf[i] = ld_off<double>(p.lowfac + L.fac_off, xc[i] * 8u);
+    }
+
+    // ---- multiply-add
+    Acc<T, COMP> acc[RT];
+#pragma unroll
+    for (int i = 0; i < RT; ++i) acc[i].zero();
+#pragma unroll
+    for (int g = 0; g < HS; ++g) {
+        if (g < L.nh) {
+            const C u = u_lds[group_mode<WIDE>(dr, g)];
+#pragma unroll
+            for (int i = 0; i < RT; ++i) acc[i].mac(u, v[g][i]);
+        }
+    }
+    for (int g = HS; g < L.nh; ++g) {  // leaves with more than HS high groups
+        const C *Xb = X + group_base<WIDE>(dr, L, g);
+        const C u = u_lds[group_mode<WIDE>(dr, g)];
+#pragma unroll
+        for (int i = 0; i < RT; ++i) acc[i].mac(u, ld_off<C>(Xb, off[i]));
+    }
+#pragma unroll
+    for (int c = 0; c < CS; ++c) {
+        if (c < L.cmax) {
+#pragma unroll
+            for (int i = 0; i < RT; ++i) acc[i].mac(u_lds[e[c][i] >> 24], lowbuf[e[c][i] & SLOS_PRED_MASK]);
+        }
+    }
+    for (int c = CS; c < L.cmax; ++c) {  // inner states with more than CS low terms
+#pragma unroll
+        for (int i = 0; i < RT; ++i) {
+            const uint32_t ec = ld_off<uint32_t>(pred, ((uint32_t)c * L.size + xc[i]) * 4u);
+            acc[i].mac(u_lds[ec >> 24], lowbuf[ec & SLOS_PRED_MASK]);
+        }
+    }
+
+    // ---- store
+#pragma unroll
+    for (int i = 0; i < RT; ++i) {
+        if (!ok[i]) continue;
+        const uint64_t o = L.out_base + xc[i];
+        if (MODE == SLOS_MODE_MID) {
+            const C a = acc[i].value();
+            __builtin_nontemporal_store(a.x, &((T *)p.Y)[2 * o]);
+            __builtin_nontemporal_store(a.y, &((T *)p.Y)[2 * o + 1]);
+        } else {
+            const double f = L.fac_hi * lf[i];
+            const double ar = acc[i].re() * f;
+            const double ai = acc[i].im() * f;
+            const double pr = ar * ar + ai * ai;
+            psum += pr;
+            if (MODE == SLOS_MODE_AMPL) {
+                __builtin_nontemporal_store((T)ar, &((T *)p.Y)[2 * o]);
+                __builtin_nontemporal_store((T)ai, &((T *)p.Y)[2 * o + 1]);
+            } else {
+                __builtin_nontemporal_store((T)pr, &((T *)p.Y)[o]);
+            }
+        }
+    }
+}
+
+template <typename T, int MODE, bool COMP, int RR, bool WIDE>
 __global__ __launch_bounds__(256) void layer_kernel(LayerParams p)
 {
     using C = typename Cx<T>::type;
     __shared__ C u_lds[256];
-    __shared__ uint64_t base_lds[kMaxWaves][SLOS_MAX_PHOTONS];
-    __shared__ C hu_lds[kMaxWaves][SLOS_MAX_PHOTONS];
-
     const C *__restrict__ X = (const C *)p.X;
     const C *__restrict__ Um = (const C *)p.U;
     for (int j = threadIdx.x; j < 256; j += blockDim.x) {
@@ -103,119 +351,109 @@ __global__ __launch_bounds__(256) void layer_kernel(LayerParams p)
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int wpb = blockDim.x >> 6;
     const uint64_t gw = (uint64_t)blockIdx.x * wpb + wv;
-    const uint64_t nw = (uint64_t)gridDim.x * wpb;
-    const uint64_t *__restrict__ binom = p.binom;
-    const int bs = p.bstride;
-    double psum = 0.0;
-
-    for (uint64_t li = gw; li < p.nleaves; li += nw) {
-        const LeafRec *L = p.leaves + li;
-        const uint64_t out_base = L->out_base;
-        const uint32_t size = L->size;
-        const int nhp = L->nhp;
-        const InnerType ty = p.types[L->tab];
-
-        // Predecessor blocks through the high modes.  Positions r = k, k-1, ..
-        // hold the high photons (descending modes); c_r = d_r + r - 1.  For the
-        // top photon of mode d at position r:
-        //   rank(t) - rank(t - e_d) = C(c_r, r) + sum_{r' > r} C(c_{r'} - 1, r').
-        uint64_t S = 0;
-        int nh = 0;
-        int grp = 0;
-        int prev = -1;
-        double hifac = 1.0;
-        for (int idx = 0; idx < nhp; ++idx) {
-            const int r = p.k - idx;
-            const int d = L->hm[idx];
-            const int c = d + r - 1;
-            if (d != prev) {
-                base_lds[wv][nh] = out_base - (binom[c * bs + r] + S);
-                hu_lds[wv][nh] = u_lds[d];
-                ++nh;
-                grp = 1;
-                prev = d;
-            } else {
-                ++grp;
-                hifac *= (double)grp;
-            }
-            S += binom[(c - 1) * bs + r];
+    // This (virtual) XCD owns chunks xcd, xcd + SLOS_XCDS, ... of xcd_chunk
+    // leaves; its waves take the owned leaves in order from a ticket counter.
+    // Workgroups are dealt to the XCDs round-robin, so blockIdx.x % SLOS_XCDS
+    // names the XCD; correctness does not depend on that placement.
+    const uint32_t xcd = blockIdx.x % SLOS_XCDS;
+    const uint64_t G = p.xcd_chunk;
+    const uint64_t nchunk = (p.nleaves + G - 1) / G;
+    const uint64_t owned_chunks = nchunk > xcd ? (nchunk - xcd + SLOS_XCDS - 1) / SLOS_XCDS : 0;
+    const uint64_t owned = owned_chunks * G;
+    auto global_leaf = [&](uint64_t local) { return ((local / G) * SLOS_XCDS + xcd) * G + local % G; };
+    // A ticket is a batch of p.ticket_leaves consecutive owned leaves; the
+    // wave walks its batch and takes a new ticket when the batch runs out.
+    // next_leaf returns p.nleaves when the XCD's share is done (slots past the
+    // layer end only occur at the end of the last chunk).
+    const uint32_t TB = p.ticket_leaves;
+    uint64_t bat_next = 0, bat_end = 0;
+    auto next_leaf = [&]() -> uint64_t {
+        if (bat_next >= bat_end) {
+            uint32_t t = 0;
+            if (lane == 0) t = atomicAdd(&p.tickets[xcd], TB);
+            bat_next = (uint64_t)__builtin_amdgcn_readfirstlane(t);
+            bat_end = bat_next + TB;
         }
-        // the block of the same high part with K-1 low photons
-        const uint64_t low_base = out_base - S;
-        const uint32_t *__restrict__ pred = p.pred + ty.pred_off;
-        const int cmax = (int)ty.cmax;
-        const double fac_hi = MODE != SLOS_MODE_MID ? sqrt(hifac) * p.norm_t : 1.0;
+        const uint64_t local = bat_next++;
+        if (local >= owned) return p.nleaves;
+        const uint64_t g = global_leaf(local);
+        return g < p.nleaves ? g : p.nleaves;
+    };
+    extern __shared__ unsigned char dyn_lds[];
+    unsigned char *slice = dyn_lds + (size_t)wv * p.lds_wave_bytes;
 
-        for (uint32_t t0 = 0; t0 < size; t0 += 64 * RR) {
-            Acc<T, COMP> acc[RR];
+    uint64_t li = next_leaf();
+    DescRegs<WIDE> cur{0u, 0u};
+    if (li < p.nleaves) cur = load_desc<WIDE>(p.desc, li, lane);
+    while (li < p.nleaves) {
+        double psum = 0.0;
+        const Leaf L = decode_head<WIDE>(cur);
+        const C *lowbuf = stage_low<C>(X, L, slice, lane);
+        // take the next leaf and prefetch its descriptor while this one is computed
+        const uint64_t nli = next_leaf();
+        DescRegs<WIDE> nxt{0u, 0u};
+        if (nli < p.nleaves) nxt = load_desc<WIDE>(p.desc, nli, lane);
+        // the staged block must have landed before the first LDS gather
+        __builtin_amdgcn_s_waitcnt(0);
+        __builtin_amdgcn_wave_barrier();
+        uint32_t t0 = 0;
+        for (; t0 + 64u * RR <= L.size; t0 += 64u * RR)
+            tile<T, MODE, COMP, RR, WIDE>(p, cur, L, X, u_lds, lowbuf, t0, lane, psum);
+        for (; t0 < L.size; t0 += 64u) tile<T, MODE, COMP, 1, WIDE>(p, cur, L, X, u_lds, lowbuf, t0, lane, psum);
+        // every LDS read of this block is done before the next copy lands
+        __builtin_amdgcn_s_waitcnt(0);
+        __builtin_amdgcn_wave_barrier();
+        if (MODE != SLOS_MODE_MID) {
+            // one FP64 partial per leaf, summed later in leaf order: the total
+            // does not depend on which wave took which leaf
 #pragma unroll
-            for (int q = 0; q < RR; ++q) acc[q].zero();
-
-            for (int h = 0; h < nh; ++h) {
-                const uint64_t b = base_lds[wv][h];
-                const C u = hu_lds[wv][h];
-                const C *__restrict__ Xb = X + b;
-#pragma unroll
-                for (int q = 0; q < RR; ++q) {
-                    const uint32_t x = t0 + q * 64 + lane;
-                    if (x < size) acc[q].mac(u, Xb[x]);
-                }
-            }
-            const C *__restrict__ Xl = X + low_base;
-            for (int c = 0; c < cmax; ++c) {
-#pragma unroll
-                for (int q = 0; q < RR; ++q) {
-                    const uint32_t x = t0 + q * 64 + lane;
-                    if (x < size) {
-                        const uint32_t e = pred[(size_t)c * size + x];
-                        acc[q].mac(u_lds[e >> 24], Xl[e & SLOS_PRED_MASK]);
-                    }
-                }
-            }
-#pragma unroll
-            for (int q = 0; q < RR; ++q) {
-                const uint32_t x = t0 + q * 64 + lane;
-                if (x < size) {
-                    if (MODE == SLOS_MODE_MID) {
-                        ((C *)p.Y)[out_base + x] = acc[q].value();
-                    } else {
-                        const double f = fac_hi * p.lowfac[ty.fac_off + x];
-                        const double ar = acc[q].re() * f;
-                        const double ai = acc[q].im() * f;
-                        const double pr = ar * ar + ai * ai;
-                        psum += pr;
-                        if (MODE == SLOS_MODE_AMPL)
-                            ((C *)p.Y)[out_base + x] = C{(T)ar, (T)ai};
-                        else
-                            ((T *)p.Y)[out_base + x] = (T)pr;
-                    }
-                }
-            }
+            for (int off = 32; off > 0; off >>= 1) psum += __shfl_xor(psum, off, 64);
+            if (lane == 0) p.partials[li] = psum;
         }
+        cur = nxt;
+        li = nli;
     }
-
-    if (MODE != SLOS_MODE_MID) {
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) psum += __shfl_xor(psum, off, 64);
-        if (lane == 0) p.partials[gw] = psum;
-    }
+    (void)gw;
 }
 
-// Deterministic sum of the per-wave partials: fixed strided order per thread,
-// then a fixed tree in LDS.
-__global__ __launch_bounds__(256) void reduce_kernel(const double *__restrict__ part, int count,
-                                                     double *__restrict__ out)
+// Deterministic two-stage sum of the per-leaf partials: workgroup b sums its
+// fixed contiguous segment (strided per thread, then a fixed LDS tree) into
+// stage[b]; a single workgroup then sums stage[] the same way.
+constexpr int kReduceBlocks = 256;
+
+__device__ __forceinline__ double block_sum(double s)
 {
     __shared__ double sh[256];
-    double s = 0.0;
-    for (int i = threadIdx.x; i < count; i += 256) s += part[i];
     sh[threadIdx.x] = s;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
         if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) *out = sh[0];
+    return sh[0];
+}
+
+__global__ __launch_bounds__(256) void reduce_stage1(const double *__restrict__ part, int64_t count,
+                                                     double *__restrict__ stage)
+{
+    const int64_t seg = (count + kReduceBlocks - 1) / kReduceBlocks;
+    const int64_t lo = (int64_t)blockIdx.x * seg;
+    const int64_t hi = lo + seg < count ? lo + seg : count;
+    double s = 0.0;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += 256) s += part[i];
+    s = block_sum(s);
+    if (threadIdx.x == 0) stage[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(256) void reduce_stage2(const double *__restrict__ stage, double *__restrict__ out)
+{
+    const double s = block_sum(threadIdx.x < kReduceBlocks ? stage[threadIdx.x] : 0.0);
+    if (threadIdx.x == 0) *out = s;
+}
+
+__global__ void zero_u32_kernel(uint32_t *buf, int count)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) buf[i] = 0u;
 }
 
 template <typename T>
@@ -231,25 +469,45 @@ __global__ void vacuum_kernel(void *out, int mode, double *sum_p)
     }
 }
 
-template <typename T, int MODE, bool COMP>
+template <typename T, int MODE, bool COMP, int RR, bool WIDE>
+hipError_t launch_one(const LayerParams &p, const LayerLaunch &l, hipStream_t s)
+{
+    static bool attr_set = false;  // per instantiation; first call per process
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute((const void *)layer_kernel<T, MODE, COMP, RR, WIDE>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)SLOS_LDS_DYNAMIC_MAX);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    const size_t lds = (size_t)p.lds_wave_bytes * (size_t)(l.threads / 64);
+    hipLaunchKernelGGL((layer_kernel<T, MODE, COMP, RR, WIDE>), dim3(l.grid), dim3(l.threads), lds, s, p);
+    return hipGetLastError();
+}
+
+template <typename T, int MODE, bool COMP, bool WIDE>
 hipError_t launch_rr(const LayerParams &p, const LayerLaunch &l, hipStream_t s)
 {
-    dim3 g(l.grid), b(l.threads);
     switch (l.rr) {
-    case 1: hipLaunchKernelGGL((layer_kernel<T, MODE, COMP, 1>), g, b, 0, s, p); break;
-    case 2: hipLaunchKernelGGL((layer_kernel<T, MODE, COMP, 2>), g, b, 0, s, p); break;
-    default: hipLaunchKernelGGL((layer_kernel<T, MODE, COMP, 4>), g, b, 0, s, p); break;
+    case 1: return launch_one<T, MODE, COMP, 1, WIDE>(p, l, s);
+    case 2: return launch_one<T, MODE, COMP, 2, WIDE>(p, l, s);
+    default: return launch_one<T, MODE, COMP, 4, WIDE>(p, l, s);
     }
-    return hipGetLastError();
+}
+
+template <typename T, int MODE, bool COMP>
+hipError_t launch_wide(const LayerParams &p, const LayerLaunch &l, hipStream_t s)
+{
+    return l.wide ? launch_rr<T, MODE, COMP, true>(p, l, s) : launch_rr<T, MODE, COMP, false>(p, l, s);
 }
 
 template <typename T, bool COMP>
 hipError_t launch_mode(const LayerParams &p, const LayerLaunch &l, hipStream_t s)
 {
     switch (l.mode) {
-    case SLOS_MODE_AMPL: return launch_rr<T, SLOS_MODE_AMPL, COMP>(p, l, s);
-    case SLOS_MODE_PROB: return launch_rr<T, SLOS_MODE_PROB, COMP>(p, l, s);
-    default: return launch_rr<T, SLOS_MODE_MID, COMP>(p, l, s);
+    case SLOS_MODE_AMPL: return launch_wide<T, SLOS_MODE_AMPL, COMP>(p, l, s);
+    case SLOS_MODE_PROB: return launch_wide<T, SLOS_MODE_PROB, COMP>(p, l, s);
+    default: return launch_wide<T, SLOS_MODE_MID, COMP>(p, l, s);
     }
 }
 
@@ -265,9 +523,12 @@ int slos_launch_layer(const LayerParams &p, const LayerLaunch &l, void *stream)
     return (int)launch_mode<double, false>(p, l, s);
 }
 
-int slos_launch_reduce(const double *partials, int count, double *out, void *stream)
+int slos_launch_reduce(const double *partials, int64_t count, double *stage, double *out, void *stream)
 {
-    hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(256), 0, (hipStream_t)stream, partials, count, out);
+    hipLaunchKernelGGL(reduce_stage1, dim3(kReduceBlocks), dim3(256), 0, (hipStream_t)stream, partials, count, stage);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return (int)e;
+    hipLaunchKernelGGL(reduce_stage2, dim3(1), dim3(256), 0, (hipStream_t)stream, stage, out);
     return (int)hipGetLastError();
 }
 
@@ -277,5 +538,11 @@ int slos_launch_vacuum(void *out, int c64, int mode, double *sum_p, void *stream
         hipLaunchKernelGGL(vacuum_kernel<float>, dim3(1), dim3(64), 0, (hipStream_t)stream, out, mode, sum_p);
     else
         hipLaunchKernelGGL(vacuum_kernel<double>, dim3(1), dim3(64), 0, (hipStream_t)stream, out, mode, sum_p);
+    return (int)hipGetLastError();
+}
+
+int slos_launch_zero_u32(uint32_t *buf, int count, void *stream)
+{
+    hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(256), 0, (hipStream_t)stream, buf, count);
     return (int)hipGetLastError();
 }

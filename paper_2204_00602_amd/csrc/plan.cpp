@@ -140,6 +140,7 @@ struct slos_plan_s {
     Binom B;
     std::vector<uint64_t> Nk;      // N_0 .. N_n
     std::vector<std::vector<LeafRec>> leaves;  // index k = 1..n
+    std::vector<uint32_t> low_max;             // per layer: largest low block
     std::vector<InnerType> types;
     std::vector<uint32_t> pred;
     std::vector<double> lowfac;
@@ -150,6 +151,9 @@ struct slos_plan_s {
     uint64_t *d_binom = nullptr;
     LeafRec *d_leaves = nullptr;
     std::vector<uint64_t> leaf_off;   // per layer offset into d_leaves
+    unsigned char *d_desc = nullptr;  // leaf descriptors of all layers
+    std::vector<uint64_t> desc_off;   // per layer byte offset into d_desc
+    std::vector<int> desc_wide;       // per layer: wide descriptors
     InnerType *d_types = nullptr;
     uint32_t *d_pred = nullptr;
     double *d_lowfac = nullptr;
@@ -158,7 +162,8 @@ struct slos_plan_s {
     void *d_keep = nullptr;           // A_0..A_{n-1} when KEEP_LAYERS
     std::vector<uint64_t> keep_off;   // element offsets of A_k in d_keep
     double *d_partials = nullptr;
-    int n_partials = 0;
+    int64_t n_partials = 0;
+    uint32_t *d_tickets = nullptr;    // SLOS_XCDS ticket counters per layer
     bool timing = false;
     bool timed_reduce = false;
     std::vector<hipEvent_t> events;   // n + 2 when timing is on
@@ -171,9 +176,10 @@ struct slos_plan_s {
         auto it = type_of.find(key);
         if (it != type_of.end()) return it->second;
         InnerType ty{};
-        ty.q = (uint32_t)q;
-        ty.K = (uint32_t)K;
+        ty.q = (uint16_t)q;
+        ty.K = (uint16_t)K;
         ty.size = (uint32_t)B(q + K - 1, K);
+        ty.low_size = K > 0 ? (uint32_t)B(q + K - 2, K - 1) : 0u;
         std::vector<int32_t> occ(q), sub(q);
         // first pass: cmax
         uint32_t cmax = 0;
@@ -230,6 +236,14 @@ struct slos_plan_s {
                 base += B(hm[idx] + r - 1, r);
             }
             L.out_base = base;
+            // FP64 normalisation of the high part: sqrt(prod o_j!) / sqrt(prod t_i!)
+            double f = 1.0;
+            int run = 0;
+            for (size_t idx = 0; idx < hm.size(); ++idx) {
+                run = (idx > 0 && hm[idx] == hm[idx - 1]) ? run + 1 : 1;
+                f *= (double)run;
+            }
+            L.fac_hi = std::sqrt(f) * norm_t;
             out.push_back(L);
             return;
         }
@@ -240,6 +254,46 @@ struct slos_plan_s {
         }
     }
 
+    // Host-side expansion of a leaf into its descriptor head and groups:
+    // for the top photon of high mode d at position r (c = d + r - 1),
+    //   rank(t) - rank(t - e_d) = C(c, r) + sum_{r' > r} C(c_{r'} - 1, r'),
+    // and the low block (same high part, K-1 low photons) starts at
+    //   out_base - sum_{r > K} C(c_r - 1, r).
+    void describe(int k, const LeafRec &L, LeafDescHead &h, std::vector<uint64_t> &deltas,
+                  std::vector<uint8_t> &modes) const
+    {
+        const InnerType &ty = types[L.tab];
+        uint64_t S = 0;
+        int prev = -1;
+        std::vector<uint64_t> bases;
+        deltas.clear();
+        modes.clear();
+        for (int idx = 0; idx < L.nhp; ++idx) {
+            const int r = k - idx;
+            const int d = L.hm[idx];
+            const int c = d + r - 1;
+            if (d != prev) {
+                bases.push_back(L.out_base - (B(c, r) + S));
+                modes.push_back((uint8_t)d);
+                prev = d;
+            }
+            S += B(c - 1, r);
+        }
+        h = LeafDescHead{};
+        h.out_base = L.out_base;
+        h.low_base = L.out_base - S;
+        h.fac_hi = L.fac_hi;
+        h.size = L.size;
+        h.low_size = ty.low_size;
+        h.pred_off = (uint32_t)ty.pred_off;
+        h.fac_off = (uint32_t)ty.fac_off;
+        h.cmax = (uint8_t)ty.cmax;
+        h.nh = (uint8_t)modes.size();
+        h.q = L.q;
+        h.K = L.K;
+        for (uint64_t b : bases) deltas.push_back(h.low_base - b);
+    }
+
     void free_device()
     {
         auto f = [](void *p) {
@@ -247,6 +301,8 @@ struct slos_plan_s {
         };
         f(d_binom);
         f(d_leaves);
+        f(d_desc);
+        d_desc = nullptr;
         f(d_types);
         f(d_pred);
         f(d_lowfac);
@@ -255,6 +311,8 @@ struct slos_plan_s {
         f(d_buf[1]);
         f(d_keep);
         f(d_partials);
+        f(d_tickets);
+        d_tickets = nullptr;
         d_binom = nullptr;
         d_leaves = nullptr;
         d_types = nullptr;
@@ -369,11 +427,17 @@ int slos_plan_ex(int m, int n, const int32_t *input_state, int flags, const slos
 
     slos_options_t o{};
     if (opts) o = *opts;
-    if (o.leaf_max == 0) o.leaf_max = 4096;
+    if (o.leaf_max == 0) o.leaf_max = 2048;
     if (o.comp_from_layer == 0) o.comp_from_layer = std::max(1, n - 1);
     if (o.block_threads == 0) o.block_threads = 256;
     if (o.grid_blocks == 0) o.grid_blocks = 2048;
-    if (o.outputs_per_lane == 0) o.outputs_per_lane = 4;
+    if (o.outputs_per_lane == 0) o.outputs_per_lane = dt == SLOS_C64 ? 4 : 2;
+    if (o.xcd_chunk == 0) o.xcd_chunk = 512;
+    if (o.ticket_leaves == 0) o.ticket_leaves = 8;
+    if (o.ticket_leaves < 1 || o.ticket_leaves > 4096)
+        return fail(SLOS_ERR_INVALID_ARG, "ticket_leaves = %d outside [1, 4096]", o.ticket_leaves);
+    if (o.xcd_chunk < 1 || o.xcd_chunk > (1 << 24))
+        return fail(SLOS_ERR_INVALID_ARG, "xcd_chunk = %d outside [1, 2^24]", o.xcd_chunk);
     if (o.leaf_max < 1 || o.leaf_max > 65536)
         return fail(SLOS_ERR_INVALID_ARG, "leaf_max = %d outside [1, 65536]", o.leaf_max);
     if (o.block_threads != 64 && o.block_threads != 128 && o.block_threads != 256)
@@ -413,10 +477,19 @@ int slos_plan_ex(int m, int n, const int32_t *input_state, int flags, const slos
             throw std::pair<int, std::string>(SLOS_ERR_SIZE_OVERFLOW, "layer too large for a device buffer");
 
         p->leaves.resize(n + 1);
+        p->low_max.assign(n + 1, 0);
         for (int k = 1; k <= n; ++k) {
             std::vector<uint8_t> hm;
             p->gen_leaves(k, m - 1, k, hm, p->leaves[k]);
+            for (const LeafRec &L : p->leaves[k])
+                p->low_max[k] = std::max(p->low_max[k], p->types[L.tab].low_size);
         }
+        // one wave must be able to hold its low block in LDS
+        const size_t es_ = (dt == SLOS_C64) ? 8 : 16;
+        for (int k = 1; k <= n; ++k)
+            if (slos_lds_wave_bytes(p->low_max[k], (uint32_t)es_) > SLOS_LDS_DYNAMIC_MAX)
+                throw std::pair<int, std::string>(SLOS_ERR_INVALID_ARG,
+                                                  "leaf_max too large: a low block does not fit in LDS");
     } catch (std::bad_alloc &) {
         delete p;
         return fail(SLOS_ERR_OOM, "host allocation failed while building tables");
@@ -425,6 +498,10 @@ int slos_plan_ex(int m, int n, const int32_t *input_state, int flags, const slos
         return fail(e.first, "%s", e.second.c_str());
     }
 
+    if (p->pred.size() >= (size_t(1) << 32) || p->lowfac.size() >= (size_t(1) << 32)) {
+        delete p;
+        return fail(SLOS_ERR_SIZE_OVERFLOW, "inner tables exceed 2^32 entries; lower leaf_max");
+    }
     if (p->host_only) {
         *out = p;
         return SLOS_OK;
@@ -446,8 +523,59 @@ int slos_plan_ex(int m, int n, const int32_t *input_state, int flags, const slos
         all.insert(all.end(), p->leaves[k].begin(), p->leaves[k].end());
     }
     p->leaf_off[n + 1] = all.size();
+    std::vector<unsigned char> descs;
+    p->desc_off.assign(n + 2, 0);
+    p->desc_wide.assign(n + 1, 0);
+    try {
+        std::vector<uint64_t> deltas;
+        std::vector<uint8_t> modes;
+        for (int k = 1; k <= n; ++k) {
+            // narrow unless a leaf has more than 16 groups or a 64-bit delta
+            int wide = 0;
+            for (const LeafRec &L : p->leaves[k]) {
+                LeafDescHead h;
+                p->describe(k, L, h, deltas, modes);
+                if (h.nh > SLOS_NARROW_GROUPS) wide = 1;
+                for (uint64_t d : deltas)
+                    if (d > 0xFFFFFFFFull) wide = 1;
+                if (wide) break;
+            }
+            p->desc_wide[k] = wide;
+            p->desc_off[k] = descs.size();
+            const size_t rec = wide ? sizeof(LeafDescWide) : sizeof(LeafDescNarrow);
+            descs.resize(descs.size() + rec * p->leaves[k].size());
+            unsigned char *dst = descs.data() + p->desc_off[k];
+            for (const LeafRec &L : p->leaves[k]) {
+                LeafDescHead h;
+                p->describe(k, L, h, deltas, modes);
+                if (wide) {
+                    LeafDescWide w{};
+                    w.h = h;
+                    for (size_t g = 0; g < deltas.size(); ++g) {
+                        w.delta[g] = deltas[g];
+                        w.mode[g] = modes[g];
+                    }
+                    std::memcpy(dst, &w, sizeof w);
+                } else {
+                    LeafDescNarrow w{};
+                    w.h = h;
+                    for (size_t g = 0; g < deltas.size(); ++g) {
+                        w.delta[g] = (uint32_t)deltas[g];
+                        w.mode[g] = modes[g];
+                    }
+                    std::memcpy(dst, &w, sizeof w);
+                }
+                dst += rec;
+            }
+        }
+        p->desc_off[n + 1] = descs.size();
+    } catch (std::bad_alloc &) {
+        delete p;
+        return fail(SLOS_ERR_OOM, "host allocation failed while building leaf descriptors");
+    }
     if ((rc = dev_upload(&p->d_binom, p->B.t.data(), p->B.t.size(), "binomial table")) ||
         (rc = dev_upload(&p->d_leaves, all.data(), all.size(), "leaf table")) ||
+        (rc = dev_upload(&p->d_desc, descs.data(), descs.size(), "leaf descriptors")) ||
         (rc = dev_upload(&p->d_types, p->types.data(), p->types.size(), "inner types")) ||
         (rc = dev_upload(&p->d_pred, p->pred.data(), p->pred.size(), "inner predecessor table")) ||
         (rc = dev_upload(&p->d_lowfac, p->lowfac.data(), p->lowfac.size(), "inner factorial table"))) {
@@ -461,7 +589,7 @@ int slos_plan_ex(int m, int n, const int32_t *input_state, int flags, const slos
     {
         double one_d[2] = {1.0, 0.0};
         float one_f[2] = {1.0f, 0.0f};
-        if ((rc = alloc_dev(&p->d_vac, es, "vacuum layer"))) {
+        if ((rc = alloc_dev(&p->d_vac, es + SLOS_BUFFER_SLACK, "vacuum layer"))) {
             p->free_device();
             delete p;
             return rc;
@@ -484,7 +612,7 @@ int slos_plan_ex(int m, int n, const int32_t *input_state, int flags, const slos
             tot += (p->Nk[k] + 15) / 16 * 16;  // 128-byte aligned layers
         }
         p->keep_off[n] = tot;
-        if ((rc = alloc_dev(&p->d_keep, tot * es, "kept layers"))) {
+        if ((rc = alloc_dev(&p->d_keep, tot * es + SLOS_BUFFER_SLACK, "kept layers"))) {
             p->free_device();
             delete p;
             return rc;
@@ -500,14 +628,16 @@ int slos_plan_ex(int m, int n, const int32_t *input_state, int flags, const slos
         uint64_t need[2] = {0, 0};
         for (int k = 1; k < n; ++k) need[k & 1] = std::max(need[k & 1], p->Nk[k]);
         for (int b = 0; b < 2; ++b)
-            if (need[b] && (rc = alloc_dev(&p->d_buf[b], need[b] * es, "layer buffer"))) {
+            if (need[b] && (rc = alloc_dev(&p->d_buf[b], need[b] * es + SLOS_BUFFER_SLACK, "layer buffer"))) {
                 p->free_device();
                 delete p;
                 return rc;
             }
     }
-    p->n_partials = p->opts.grid_blocks * (p->opts.block_threads / 64);
-    if ((rc = alloc_dev((void **)&p->d_partials, (size_t)p->n_partials * sizeof(double), "partial sums"))) {
+    p->n_partials = n > 0 ? (int64_t)p->leaves[n].size() : 1;
+    if ((rc = alloc_dev((void **)&p->d_partials, (size_t)(p->n_partials + SLOS_REDUCE_STAGE) * sizeof(double),
+                        "partial sums")) ||
+        (rc = alloc_dev((void **)&p->d_tickets, (size_t)(n + 1) * SLOS_XCDS * sizeof(uint32_t), "ticket counters"))) {
         p->free_device();
         delete p;
         return rc;
@@ -571,6 +701,10 @@ static int run_forward(slos_plan_t p, const void *U, void *out, double *sum_p, v
     const size_t es = p->elem();
     const int wpb = p->opts.block_threads / 64;
     hipStream_t hs = (hipStream_t)stream;
+    {
+        int e = slos_launch_zero_u32(p->d_tickets, (n + 1) * SLOS_XCDS, stream);
+        if (e) return hip_fail((hipError_t)e, "ticket reset kernel");
+    }
     if (p->timing) {
         hipError_t e = hipEventRecord(p->events[0], hs);
         if (e != hipSuccess) return hip_fail(e, "timing event");
@@ -587,6 +721,7 @@ static int run_forward(slos_plan_t p, const void *U, void *out, double *sum_p, v
         }
         lp.U = U;
         lp.leaves = p->d_leaves + p->leaf_off[k];
+        lp.desc = p->d_desc + p->desc_off[k];
         lp.nleaves = p->leaves[k].size();
         lp.types = p->d_types;
         lp.pred = p->d_pred;
@@ -604,19 +739,29 @@ static int run_forward(slos_plan_t p, const void *U, void *out, double *sum_p, v
         ll.compensated = p->comp && k >= p->opts.comp_from_layer;
         ll.rr = p->opts.outputs_per_lane;
         ll.threads = p->opts.block_threads;
-        uint64_t want = (lp.nleaves + wpb - 1) / wpb;
+        ll.low_max = p->low_max[k];
+        ll.wide = p->desc_wide[k];
+        lp.low_max = ll.low_max;
+        lp.lds_wave_bytes = slos_lds_wave_bytes(ll.low_max, (uint32_t)es);
+        // waves per workgroup: as many as the low blocks let fit in LDS
+        int wpb_k = wpb;
+        if (lp.lds_wave_bytes)
+            wpb_k = (int)std::min<size_t>((size_t)wpb, SLOS_LDS_DYNAMIC_MAX / lp.lds_wave_bytes);
+        ll.threads = 64 * wpb_k;
+        uint64_t want = (lp.nleaves + wpb_k - 1) / wpb_k;
         ll.grid = (int)std::min<uint64_t>(want, (uint64_t)p->opts.grid_blocks);
-        if (ll.grid < 1) ll.grid = 1;
-        if (k == n) {
-            // every wave of the last launch writes one partial
-            if (ll.grid * wpb > p->n_partials) return fail(SLOS_ERR_INVALID_ARG, "partial buffer too small");
-        }
+        // a whole number of workgroups per XCD
+        ll.grid = std::max(SLOS_XCDS, (ll.grid + SLOS_XCDS - 1) / SLOS_XCDS * SLOS_XCDS);
+        lp.xcd_chunk = (uint32_t)p->opts.xcd_chunk;
+        lp.tickets = p->d_tickets + (size_t)k * SLOS_XCDS;
+        lp.ticket_leaves = (uint32_t)p->opts.ticket_leaves;
+
         int e = slos_launch_layer(lp, ll, stream);
         if (e) return hip_fail((hipError_t)e, "layer kernel");
         if (p->timing && (e = (int)hipEventRecord(p->events[k], hs)))
             return hip_fail((hipError_t)e, "timing event");
         if (k == n && sum_p) {
-            e = slos_launch_reduce(p->d_partials, ll.grid * wpb, sum_p, stream);
+            e = slos_launch_reduce(p->d_partials, p->n_partials, p->d_partials + p->n_partials, sum_p, stream);
             if (e) return hip_fail((hipError_t)e, "sum reduction kernel");
             if (p->timing) {
                 if ((e = (int)hipEventRecord(p->events[n + 1], hs)))

@@ -21,10 +21,52 @@ struct LeafRec {
     uint8_t K;                         // photons in the low modes
     uint8_t nhp;                       // k - K photons in high modes
     uint8_t pad0;
+    uint32_t pad1;
+    double fac_hi;                     // sqrt(prod over high modes of o_j!) / sqrt(prod t_i!)
     uint8_t hm[SLOS_MAX_PHOTONS];      // modes of the high photons, descending
-    uint8_t pad1[12];
 };
 static_assert(sizeof(LeafRec) == 64, "LeafRec must stay 64 bytes");
+
+// What a wave needs to compute one leaf, precomputed on the host so that a
+// single coalesced load brings it in.  Group g (< nh) is the g-th occupied
+// high mode (descending): its predecessor block starts at rank
+// low_base - delta[g] of A_{k-1} and is multiplied by U[mode[g], i_k].
+// The narrow form holds 16 groups with 32-bit deltas; the wide form 32 groups
+// with 64-bit deltas (layers of 2^32 elements or more, or n > 16).
+struct LeafDescHead {
+    uint64_t out_base;   // rank of the leaf's first state in A_k
+    uint64_t low_base;   // rank of the low block (same high part, K-1 low photons) in A_{k-1}
+    double fac_hi;       // sqrt(prod high o_j!) / sqrt(prod t_i!)
+    uint32_t size;       // states in the leaf, |F(q, K)|
+    uint32_t low_size;   // states in the low block, |F(q, K-1)|
+    uint32_t pred_off;   // inner table offset (elements) in the pred pool
+    uint32_t fac_off;    // inner factorial offset in the lowfac pool
+    uint8_t cmax;        // inner term-list length
+    uint8_t nh;          // occupied high modes
+    uint8_t q;
+    uint8_t K;
+    uint32_t pad;
+};
+static_assert(sizeof(LeafDescHead) == 48, "LeafDescHead must stay 48 bytes");
+
+#define SLOS_NARROW_GROUPS 16
+#define SLOS_WIDE_GROUPS 32
+struct LeafDescNarrow {
+    LeafDescHead h;
+    uint32_t delta[SLOS_NARROW_GROUPS];
+    uint8_t mode[SLOS_NARROW_GROUPS];
+};
+static_assert(sizeof(LeafDescNarrow) == 128, "LeafDescNarrow must stay 128 bytes");
+struct LeafDescWide {
+    LeafDescHead h;
+    uint64_t delta[SLOS_WIDE_GROUPS];
+    uint8_t mode[SLOS_WIDE_GROUPS];
+};
+static_assert(sizeof(LeafDescWide) == 336, "LeafDescWide must stay 336 bytes");
+
+// Bytes of readable slack after every layer buffer: the low-block staging
+// copies whole 16-byte chunks in 1 KiB wave-wide steps.
+#define SLOS_BUFFER_SLACK 2048u
 
 // Inner table of one (q, K) pair: for each low state x (colex rank within
 // F(q, K)) the list of its occupied low modes j with the colex rank of
@@ -32,10 +74,11 @@ static_assert(sizeof(LeafRec) == 64, "LeafRec must stay 64 bytes");
 // with (SLOS_ZERO_MODE << 24); stored term-major: pred[pred_off + c*size + x].
 // lowfac[fac_off + x] = sqrt(prod_j x_j!) in FP64.
 struct InnerType {
-    uint32_t q;
-    uint32_t K;
-    uint32_t size;
-    uint32_t cmax;
+    uint16_t q;
+    uint16_t K;
+    uint32_t size;       // |F(q, K)|
+    uint32_t cmax;       // longest term list
+    uint32_t low_size;   // |F(q, K-1)| (0 when K = 0): the leaf's low block
     uint64_t pred_off;
     uint64_t fac_off;
 };
@@ -43,6 +86,8 @@ static_assert(sizeof(InnerType) == 32, "InnerType must stay 32 bytes");
 
 #define SLOS_ZERO_MODE 255u   // u[255] is held at zero in the kernels
 #define SLOS_PRED_MASK 0x00FFFFFFu
+
+#define SLOS_XCDS 8   // MI355X: 8 accelerator complex dies, workgroups dealt round-robin
 
 enum SlosLayerMode {
     SLOS_MODE_MID = 0,    // store A_k
@@ -55,6 +100,7 @@ struct LayerParams {
     void *Y;                // A_k, a or P (device)
     const void *U;          // m x m, row = output mode (device)
     const LeafRec *leaves;  // leaves of layer k (device)
+    const void *desc;       // LeafDescNarrow or LeafDescWide array of layer k (device)
     uint64_t nleaves;
     const InnerType *types;
     const uint32_t *pred;
@@ -65,7 +111,19 @@ struct LayerParams {
     int k;                  // layer index (photons in the output states)
     int col;                // input mode i_k of the photon added at this layer
     double norm_t;          // 1 / sqrt(prod_i t_i!)
-    double *partials;       // one FP64 partial sum of P per wave (last layer)
+    double *partials;       // one FP64 partial sum of P per leaf (last layer)
+    uint32_t low_max;       // LDS elements reserved per wave for a low block
+    uint32_t lds_wave_bytes;// LDS bytes per wave (low block staging slice)
+    // Leaves are dealt to XCDs in chunks of xcd_chunk consecutive leaves
+    // (chunk c to the workgroups with blockIdx.x % SLOS_XCDS == c % SLOS_XCDS,
+    // which the dispatcher places on one XCD): each L2 sees contiguous runs of
+    // the colex order while all XCDs stay in the same region of the layer.
+    uint32_t xcd_chunk;
+    // One ticket counter per XCD (zeroed before every forward call): a wave
+    // takes the XCD's next leaf in order, so the resident waves of an XCD
+    // always work on neighbouring leaves and share the L2.
+    uint32_t *tickets;
+    uint32_t ticket_leaves;  // consecutive leaves per ticket
 };
 
 struct LayerLaunch {
@@ -75,9 +133,24 @@ struct LayerLaunch {
     int rr;           // outputs per lane per tile: 1, 2, 4
     int threads;      // workgroup size (multiple of 64, <= 256)
     int grid;         // workgroups
+    uint32_t low_max; // largest low block of the layer (elements): LDS per wave
+    int wide;         // 1: LeafDescWide descriptors
 };
+
+// LDS bytes one wave needs to stage a low block of low_max elements of es bytes
+static inline uint32_t slos_lds_wave_bytes(uint32_t low_max, uint32_t es)
+{
+    return low_max ? ((low_max * es + 16u + 1023u) / 1024u) * 1024u : 0u;
+}
+
+// Dynamic LDS available to one workgroup of the layer kernel (gfx950: 160 KiB
+// per CU, minus the kernel's static U column).
+#define SLOS_LDS_DYNAMIC_MAX (160u * 1024u - 8u * 1024u)
 
 // Kernel launchers (layer.hip).  Return a hipError_t value as int.
 int slos_launch_layer(const LayerParams &p, const LayerLaunch &l, void *stream);
-int slos_launch_reduce(const double *partials, int count, double *out, void *stream);
+// stage: SLOS_REDUCE_STAGE doubles of scratch
+#define SLOS_REDUCE_STAGE 256
+int slos_launch_reduce(const double *partials, int64_t count, double *stage, double *out, void *stream);
 int slos_launch_vacuum(void *out, int c64, int mode, double *sum_p, void *stream);
+int slos_launch_zero_u32(uint32_t *buf, int count, void *stream);
