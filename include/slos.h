@@ -66,13 +66,13 @@ typedef struct slos_plan_s *slos_plan_t;
 
 /* Tuning options; a zero field takes its default. */
 typedef struct slos_options {
-    int32_t leaf_max;        /* max states per leaf tile (default 2048, <= 65536)    */
+    int32_t leaf_max;        /* max states per leaf tile (default 8192, <= 65536)    */
     int32_t comp_from_layer; /* first compensated layer (default n - 1, min 1)       */
     int32_t block_threads;   /* threads per workgroup: 64, 128, 256 (default 256)    */
     int32_t grid_blocks;     /* cap on workgroups per layer launch (default 2048)    */
     int32_t outputs_per_lane;/* 1, 2 or 4 outputs per lane per tile (default 4 for c64, 2 for c128)      */
     int32_t xcd_chunk;       /* consecutive leaves dealt to one XCD at a time (default 512) */
-    int32_t ticket_leaves;   /* consecutive leaves a wave takes per work ticket (default 8) */
+    int32_t ticket_leaves;   /* consecutive leaves a wave takes per work ticket (default 2) */
 } slos_options_t;
 
 /* ---- Fock-space arithmetic (host only; no device needed) ------------------ */

@@ -333,11 +333,37 @@ __device__ __forceinline__ void tile(const LayerParams &p, const DescRegs<WIDE> 
     }
 }
 
+// Stage the low block with all waves of the workgroup: 1 KiB chunk c of the
+// copy is issued by wave c % W.
+template <typename C>
+__device__ __forceinline__ const C *stage_low_team(const C *__restrict__ X, const Leaf &L, unsigned char *slice,
+                                                   int lane, int wv, int W)
+{
+    const uintptr_t sa = (uintptr_t)(X + L.low_base);
+    const uintptr_t a0 = sa & ~(uintptr_t)15;
+    const uint32_t skew = (uint32_t)(sa - a0);
+    const uint32_t nbytes = skew + L.low_size * (uint32_t)sizeof(C);
+    for (uint32_t done = 1024u * (uint32_t)wv; done < nbytes; done += 1024u * (uint32_t)W) {
+        if (done + 16u * (uint32_t)lane < nbytes) {
+            const void *src = (const void *)(a0 + done + 16u * (uint32_t)lane);
+            __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void *)(slice + done), 16, 0,
+                                             SLOS_CPOL_NT);
+        }
+    }
+    return (const C *)(slice + skew);
+}
+
+// One workgroup (W waves) computes one leaf at a time: it stages the leaf's
+// low block once in LDS and deals the leaf's tiles out to its waves.  Leaves
+// come from per-XCD ticket counters in batches of p.ticket_leaves, so the
+// workgroups resident on an XCD work on neighbouring leaves of the colex order
+// and share that XCD's L2.
 template <typename T, int MODE, bool COMP, int RR, bool WIDE>
 __global__ __launch_bounds__(256) void layer_kernel(LayerParams p)
 {
     using C = typename Cx<T>::type;
     __shared__ C u_lds[256];
+    __shared__ uint32_t ticket_slot[2];
     const C *__restrict__ X = (const C *)p.X;
     const C *__restrict__ Um = (const C *)p.U;
     for (int j = threadIdx.x; j < 256; j += blockDim.x) {
@@ -345,75 +371,75 @@ __global__ __launch_bounds__(256) void layer_kernel(LayerParams p)
         if (j < p.m) v = Um[(size_t)j * p.m + p.col];
         u_lds[j] = v;
     }
-    __syncthreads();
 
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int wpb = blockDim.x >> 6;
-    const uint64_t gw = (uint64_t)blockIdx.x * wpb + wv;
+    const int W = blockDim.x >> 6;
+
     // This (virtual) XCD owns chunks xcd, xcd + SLOS_XCDS, ... of xcd_chunk
-    // leaves; its waves take the owned leaves in order from a ticket counter.
-    // Workgroups are dealt to the XCDs round-robin, so blockIdx.x % SLOS_XCDS
-    // names the XCD; correctness does not depend on that placement.
+    // leaves.  Workgroups are dealt to the XCDs round-robin, so
+    // blockIdx.x % SLOS_XCDS names the XCD; correctness does not depend on it.
     const uint32_t xcd = blockIdx.x % SLOS_XCDS;
     const uint64_t G = p.xcd_chunk;
     const uint64_t nchunk = (p.nleaves + G - 1) / G;
     const uint64_t owned_chunks = nchunk > xcd ? (nchunk - xcd + SLOS_XCDS - 1) / SLOS_XCDS : 0;
     const uint64_t owned = owned_chunks * G;
-    auto global_leaf = [&](uint64_t local) { return ((local / G) * SLOS_XCDS + xcd) * G + local % G; };
-    // A ticket is a batch of p.ticket_leaves consecutive owned leaves; the
-    // wave walks its batch and takes a new ticket when the batch runs out.
-    // next_leaf returns p.nleaves when the XCD's share is done (slots past the
-    // layer end only occur at the end of the last chunk).
-    const uint32_t TB = p.ticket_leaves;
-    uint64_t bat_next = 0, bat_end = 0;
-    auto next_leaf = [&]() -> uint64_t {
-        if (bat_next >= bat_end) {
-            uint32_t t = 0;
-            if (lane == 0) t = atomicAdd(&p.tickets[xcd], TB);
-            bat_next = (uint64_t)__builtin_amdgcn_readfirstlane(t);
-            bat_end = bat_next + TB;
-        }
-        const uint64_t local = bat_next++;
+    auto to_leaf = [&](uint64_t local) -> uint64_t {
         if (local >= owned) return p.nleaves;
-        const uint64_t g = global_leaf(local);
-        return g < p.nleaves ? g : p.nleaves;
+        const uint64_t g = ((local / G) * SLOS_XCDS + xcd) * G + local % G;
+        return g < p.nleaves ? g : p.nleaves;  // slots past the end only in the last chunk
     };
-    extern __shared__ unsigned char dyn_lds[];
-    unsigned char *slice = dyn_lds + (size_t)wv * p.lds_wave_bytes;
+    uint32_t *ticket = p.tickets + (size_t)xcd * SLOS_TICKET_STRIDE;
+    const uint32_t TB = p.ticket_leaves;
 
-    uint64_t li = next_leaf();
+    extern __shared__ unsigned char dyn_lds[];
+    unsigned char *slice = dyn_lds;
+
+    // first batch
+    if (threadIdx.x == 0) ticket_slot[0] = atomicAdd(ticket, TB);
+    __syncthreads();
+    uint64_t bat_next = ticket_slot[0], bat_end = bat_next + TB;
+    uint64_t li = to_leaf(bat_next++);
     DescRegs<WIDE> cur{0u, 0u};
     if (li < p.nleaves) cur = load_desc<WIDE>(p.desc, li, lane);
+    uint32_t it = 0;
+
     while (li < p.nleaves) {
-        double psum = 0.0;
         const Leaf L = decode_head<WIDE>(cur);
-        const C *lowbuf = stage_low<C>(X, L, slice, lane);
-        // take the next leaf and prefetch its descriptor while this one is computed
-        const uint64_t nli = next_leaf();
+        const C *lowbuf = stage_low_team<C>(X, L, slice, lane, wv, W);
+        const bool refill = bat_next >= bat_end;
+        if (refill && threadIdx.x == 0) ticket_slot[it & 1] = atomicAdd(ticket, TB);
+        // the staged block has landed in LDS for every wave
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        if (refill) {
+            bat_next = ticket_slot[it & 1];
+            bat_end = bat_next + TB;
+        }
+        const uint64_t nli = to_leaf(bat_next++);
         DescRegs<WIDE> nxt{0u, 0u};
         if (nli < p.nleaves) nxt = load_desc<WIDE>(p.desc, nli, lane);
-        // the staged block must have landed before the first LDS gather
-        __builtin_amdgcn_s_waitcnt(0);
-        __builtin_amdgcn_wave_barrier();
-        uint32_t t0 = 0;
-        for (; t0 + 64u * RR <= L.size; t0 += 64u * RR)
-            tile<T, MODE, COMP, RR, WIDE>(p, cur, L, X, u_lds, lowbuf, t0, lane, psum);
-        for (; t0 < L.size; t0 += 64u) tile<T, MODE, COMP, 1, WIDE>(p, cur, L, X, u_lds, lowbuf, t0, lane, psum);
-        // every LDS read of this block is done before the next copy lands
-        __builtin_amdgcn_s_waitcnt(0);
-        __builtin_amdgcn_wave_barrier();
+
+        double psum = 0.0;
+        const uint32_t full = L.size / (64u * RR);              // full tiles
+        for (uint32_t t = (uint32_t)wv; t < full; t += (uint32_t)W)
+            tile<T, MODE, COMP, RR, WIDE>(p, cur, L, X, u_lds, lowbuf, t * 64u * RR, lane, psum);
+        const uint32_t rows = (L.size - full * 64u * RR + 63u) / 64u;  // leftover rows of 64
+        for (uint32_t r = (uint32_t)wv; r < rows; r += (uint32_t)W)
+            tile<T, MODE, COMP, 1, WIDE>(p, cur, L, X, u_lds, lowbuf, full * 64u * RR + r * 64u, lane, psum);
         if (MODE != SLOS_MODE_MID) {
-            // one FP64 partial per leaf, summed later in leaf order: the total
-            // does not depend on which wave took which leaf
+            // one FP64 partial per (leaf, wave), summed later in a fixed order
 #pragma unroll
             for (int off = 32; off > 0; off >>= 1) psum += __shfl_xor(psum, off, 64);
-            if (lane == 0) p.partials[li] = psum;
+            if (lane == 0) p.partials[li * (uint64_t)W + (uint64_t)wv] = psum;
         }
+        // every wave is done with this low block before the next copy lands
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
         cur = nxt;
         li = nli;
+        ++it;
     }
-    (void)gw;
 }
 
 // Deterministic two-stage sum of the per-leaf partials: workgroup b sums its
@@ -480,7 +506,7 @@ hipError_t launch_one(const LayerParams &p, const LayerLaunch &l, hipStream_t s)
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    const size_t lds = (size_t)p.lds_wave_bytes * (size_t)(l.threads / 64);
+    const size_t lds = (size_t)p.lds_wave_bytes;  // one low block per workgroup
     hipLaunchKernelGGL((layer_kernel<T, MODE, COMP, RR, WIDE>), dim3(l.grid), dim3(l.threads), lds, s, p);
     return hipGetLastError();
 }

@@ -427,13 +427,13 @@ int slos_plan_ex(int m, int n, const int32_t *input_state, int flags, const slos
 
     slos_options_t o{};
     if (opts) o = *opts;
-    if (o.leaf_max == 0) o.leaf_max = 2048;
+    if (o.leaf_max == 0) o.leaf_max = 8192;
     if (o.comp_from_layer == 0) o.comp_from_layer = std::max(1, n - 1);
     if (o.block_threads == 0) o.block_threads = 256;
     if (o.grid_blocks == 0) o.grid_blocks = 2048;
     if (o.outputs_per_lane == 0) o.outputs_per_lane = dt == SLOS_C64 ? 4 : 2;
     if (o.xcd_chunk == 0) o.xcd_chunk = 512;
-    if (o.ticket_leaves == 0) o.ticket_leaves = 8;
+    if (o.ticket_leaves == 0) o.ticket_leaves = 2;
     if (o.ticket_leaves < 1 || o.ticket_leaves > 4096)
         return fail(SLOS_ERR_INVALID_ARG, "ticket_leaves = %d outside [1, 4096]", o.ticket_leaves);
     if (o.xcd_chunk < 1 || o.xcd_chunk > (1 << 24))
@@ -634,10 +634,11 @@ int slos_plan_ex(int m, int n, const int32_t *input_state, int flags, const slos
                 return rc;
             }
     }
-    p->n_partials = n > 0 ? (int64_t)p->leaves[n].size() : 1;
+    p->n_partials = n > 0 ? (int64_t)p->leaves[n].size() * (p->opts.block_threads / 64) : 1;
     if ((rc = alloc_dev((void **)&p->d_partials, (size_t)(p->n_partials + SLOS_REDUCE_STAGE) * sizeof(double),
                         "partial sums")) ||
-        (rc = alloc_dev((void **)&p->d_tickets, (size_t)(n + 1) * SLOS_XCDS * sizeof(uint32_t), "ticket counters"))) {
+        (rc = alloc_dev((void **)&p->d_tickets,
+                        (size_t)(n + 1) * SLOS_XCDS * SLOS_TICKET_STRIDE * sizeof(uint32_t), "ticket counters"))) {
         p->free_device();
         delete p;
         return rc;
@@ -702,7 +703,7 @@ static int run_forward(slos_plan_t p, const void *U, void *out, double *sum_p, v
     const int wpb = p->opts.block_threads / 64;
     hipStream_t hs = (hipStream_t)stream;
     {
-        int e = slos_launch_zero_u32(p->d_tickets, (n + 1) * SLOS_XCDS, stream);
+        int e = slos_launch_zero_u32(p->d_tickets, (n + 1) * SLOS_XCDS * SLOS_TICKET_STRIDE, stream);
         if (e) return hip_fail((hipError_t)e, "ticket reset kernel");
     }
     if (p->timing) {
@@ -743,17 +744,15 @@ static int run_forward(slos_plan_t p, const void *U, void *out, double *sum_p, v
         ll.wide = p->desc_wide[k];
         lp.low_max = ll.low_max;
         lp.lds_wave_bytes = slos_lds_wave_bytes(ll.low_max, (uint32_t)es);
-        // waves per workgroup: as many as the low blocks let fit in LDS
-        int wpb_k = wpb;
-        if (lp.lds_wave_bytes)
-            wpb_k = (int)std::min<size_t>((size_t)wpb, SLOS_LDS_DYNAMIC_MAX / lp.lds_wave_bytes);
+        // a workgroup shares one low block: LDS does not limit its wave count
+        const int wpb_k = wpb;
         ll.threads = 64 * wpb_k;
         uint64_t want = (lp.nleaves + wpb_k - 1) / wpb_k;
         ll.grid = (int)std::min<uint64_t>(want, (uint64_t)p->opts.grid_blocks);
         // a whole number of workgroups per XCD
         ll.grid = std::max(SLOS_XCDS, (ll.grid + SLOS_XCDS - 1) / SLOS_XCDS * SLOS_XCDS);
         lp.xcd_chunk = (uint32_t)p->opts.xcd_chunk;
-        lp.tickets = p->d_tickets + (size_t)k * SLOS_XCDS;
+        lp.tickets = p->d_tickets + (size_t)k * SLOS_XCDS * SLOS_TICKET_STRIDE;
         lp.ticket_leaves = (uint32_t)p->opts.ticket_leaves;
 
         int e = slos_launch_layer(lp, ll, stream);

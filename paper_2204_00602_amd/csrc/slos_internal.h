@@ -88,6 +88,7 @@ static_assert(sizeof(InnerType) == 32, "InnerType must stay 32 bytes");
 #define SLOS_PRED_MASK 0x00FFFFFFu
 
 #define SLOS_XCDS 8   // MI355X: 8 accelerator complex dies, workgroups dealt round-robin
+#define SLOS_TICKET_STRIDE 64  // uint32 slots between ticket counters: one per 256-byte line
 
 enum SlosLayerMode {
     SLOS_MODE_MID = 0,    // store A_k
