@@ -134,6 +134,40 @@ int slos_amplitudes(slos_plan_t plan, const void *U, void *out, double *sum_p, v
  */
 int slos_probs(slos_plan_t plan, const void *U, void *probs, double *sum_p, void *stream);
 
+/* ---- differentiation ---------------------------------------------------------- */
+
+/*
+ * Reverse pass of the recurrence (adjoint of every layer, then of the
+ * normalisation).  grad_a: device, M complex in the plan's type: the gradient
+ * of a real loss L with respect to the amplitudes in the PyTorch convention
+ * (dL/dRe a + i dL/dIm a).  grad_U: device, m x m complex, overwritten with the
+ * gradient with respect to U in the same convention.  Uses the layers
+ * A_0..A_{n-1} kept by the last slos_amplitudes / slos_probs call on this plan,
+ * which must have used the same U.  Needs SLOS_KEEP_LAYERS (else
+ * SLOS_ERR_NOT_KEPT) and m <= 64.  Deterministic: no atomics.
+ */
+int slos_backward(slos_plan_t plan, const void *U, const void *grad_a, void *grad_U, void *stream);
+
+/*
+ * Rectangular MZI mesh (Section 2: any unitary decomposes into beam splitters
+ * and phase shifters in a square array).  MZI k = PS_1(phi_b) BS PS_0(phi_a) BS
+ * with BS of Eq. eq:bs at theta = pi/2 (the composition BS, PS(phi_a) on mode 0,
+ * BS, PS(phi_b) on mode 1).  Column c = 0..m-1 holds MZIs on modes (p, p+1),
+ * p = c mod 2, c mod 2 + 2, ..., p + 1 < m, taken in that order; U = T_last ...
+ * T_first.  phases: device FP64, batch x 2K with K = m(m-1)/2, (phi_a, phi_b)
+ * per MZI.  U: device, batch x m x m complex (dtype SLOS_C64 or SLOS_C128).
+ * 2 <= m <= 64.  Computed in FP64.
+ */
+int slos_mesh_unitary(int m, int batch, const double *phases, void *U, int dtype, void *stream);
+
+/*
+ * Gradient of a real loss with respect to the mesh phases, given grad_U
+ * (batch x m x m, PyTorch convention): grad_phases[b, l] = Re sum conj(G_U) o
+ * dU/dphi_l, written to device FP64 batch x 2K.  Reverse sweep over the MZIs.
+ */
+int slos_mesh_backward(int m, int batch, const double *phases, const void *grad_U, double *grad_phases, int dtype,
+                       void *stream);
+
 /* ---- timing ----------------------------------------------------------------- */
 
 /*

@@ -229,11 +229,7 @@ def mesh_loss(phases, m, T, targets, p_target) -> float:
 
 
 def mesh_grad_phases(phases, m, T, targets, p_target) -> np.ndarray:
-    """dL/dphases through the minor-permanent gradient and the mesh Jacobian.
-
-    dL/dphi = Re sum_{j,i} conj(G[j,i]) dU[j,i]/dphi, with dU/dphi from the
-    closed form of each MZI factor (d/dphi e^{i phi} = i e^{i phi}).
-    """
+    """dL/dphases through the minor-permanent gradient and the mesh Jacobian."""
     phases = np.asarray(phases, dtype=np.float64).reshape(-1)
     U = clements_unitary(m, phases)
     a = amplitudes(U, T, targets)
@@ -241,6 +237,15 @@ def mesh_grad_phases(phases, m, T, targets, p_target) -> np.ndarray:
     dLdP = 2.0 * (P - np.asarray(p_target))
     w = 2.0 * a * dLdP                    # PyTorch convention for d/d conj(a)
     G = grad_U(U, T, targets, w)
+    return mesh_vjp(phases, m, G)
+
+
+def mesh_vjp(phases, m, G) -> np.ndarray:
+    """dL/dphi = Re sum_{j,i} conj(G[j,i]) dU[j,i]/dphi for every mesh phase,
+    with dU/dphi from the closed form of each MZI factor
+    (d/dphi e^{i phi} = i e^{i phi}) and G = dL/dRe U + i dL/dIm U."""
+    phases = np.asarray(phases, dtype=np.float64).reshape(-1)
+    G = np.asarray(G, dtype=np.complex128)
     layout = clements_layout(m)
     factors = []
     for k, (_, p) in enumerate(layout):
@@ -313,6 +318,6 @@ def fibonacci(n: int) -> int:
 __all__ = [
     "perm", "fock_states", "amplitudes", "probabilities", "partial_certificate",
     "haar_pk_mean", "beam_splitter_rx", "phase_shifter", "mzi", "clements_layout",
-    "clements_unitary", "grad_U", "mesh_loss", "mesh_grad_phases", "mesh_grad_phases_fd",
+    "clements_unitary", "grad_U", "mesh_loss", "mesh_grad_phases", "mesh_grad_phases_fd", "mesh_vjp",
     "fock_count", "derangements", "fibonacci", "num_threads",
 ]

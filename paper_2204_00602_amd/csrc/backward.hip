@@ -1,0 +1,421 @@
+// HIP kernels (gfx950) for differentiation: the adjoint of the SLOS layer
+// recurrence and the rectangular MZI mesh (phases -> U and its reverse sweep).
+//
+// Forward layer (arXiv 2204.00602, Section 3.2.3 recurrence):
+//     A_k[t] = sum_j U[j, i_k] A_{k-1}[t - e_j].
+// With g = dL/d conj(.) (the PyTorch convention for a real loss L), the
+// reverse of one layer is
+//     g_{k-1}[t'] = sum_j conj(U[j, i_k]) g_k[t' + e_j]          (every mode j)
+//     G_U[j, i_k] += sum_{t'} g_k[t' + e_j] conj(A_{k-1}[t'])
+// and the last-layer normalisation a = c_S A_n[S] (c_S real) seeds
+//     g_n[S] = c_S g_a[S].
+// Work unit: the low block of one forward leaf of layer k (these blocks
+// partition A_{k-1}); one wave per unit, every output written by one lane, no
+// atomics.  Gradient partials are kept per (unit, mode) and summed in a fixed
+// order.
+#include <hip/hip_runtime.h>
+
+#include "slos_internal.h"
+
+namespace {
+
+template <typename T> struct Cb;
+template <> struct Cb<float> { using type = float2; };
+template <> struct Cb<double> { using type = double2; };
+
+// ---- seed: g_n = c_S * g_a over the last layer's leaves --------------------
+template <typename T>
+__global__ __launch_bounds__(256) void seed_kernel(const LeafDescHead *__restrict__ heads, uint64_t nleaves,
+                                                   uint32_t stride_bytes, const double *__restrict__ lowfac,
+                                                   const typename Cb<T>::type *__restrict__ ga,
+                                                   typename Cb<T>::type *__restrict__ gn)
+{
+    using C = typename Cb<T>::type;
+    const int lane = threadIdx.x & 63;
+    const uint64_t gw = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const uint64_t nw = (uint64_t)gridDim.x * (blockDim.x >> 6);
+    for (uint64_t li = gw; li < nleaves; li += nw) {
+        const LeafDescHead h = *(const LeafDescHead *)((const char *)heads + li * stride_bytes);
+        for (uint32_t x = lane; x < h.size; x += 64) {
+            const double f = h.fac_hi * lowfac[h.fac_off + x];
+            const C v = ga[h.out_base + x];
+            gn[h.out_base + x] = C{(T)(f * (double)v.x), (T)(f * (double)v.y)};
+        }
+    }
+}
+
+// ---- one reverse layer --------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(64) void bwd_layer_kernel(BwdParams p)
+{
+    using C = typename Cb<T>::type;
+    __shared__ C uc[256];                  // conj(U[j, i_k])
+    extern __shared__ double2 part[];      // [m][64] gradient partials of this wave
+    const C *__restrict__ gk = (const C *)p.gk;
+    C *__restrict__ gkm1 = (C *)p.gkm1;
+    const C *__restrict__ A = (const C *)p.Akm1;
+    const C *__restrict__ Um = (const C *)p.U;
+    const int lane = threadIdx.x;
+    for (int j = lane; j < 256; j += 64) {
+        C v{0, 0};
+        if (j < p.m) {
+            v = Um[(size_t)j * p.m + p.col];
+            v.y = -v.y;
+        }
+        uc[j] = v;
+    }
+    __syncthreads();
+
+    for (uint64_t u = blockIdx.x; u < p.nunits; u += gridDim.x) {
+        const BwdUnit U = p.units[u];
+        for (int j = 0; j < p.m; ++j) part[j * 64 + lane] = double2{0.0, 0.0};
+        const uint32_t *__restrict__ succ = p.succ + U.succ_off;
+        const uint64_t *__restrict__ hb = p.hbase + U.hbase_off;
+        for (uint32_t y0 = 0; y0 < U.low_size; y0 += 64) {
+            const uint32_t y = y0 + lane;
+            const bool ok = y < U.low_size;
+            const uint32_t yc = ok ? y : U.low_size - 1u;
+            const C a = A[U.low_base + yc];
+            double accr = 0.0, acci = 0.0;
+            for (int j = 0; j < p.m; ++j) {
+                // successor t' + e_j: inside the forward leaf for a low mode,
+                // the aligned block of the high part + e_j otherwise
+                const uint64_t pos = j < (int)U.q ? U.out_base + succ[(size_t)j * U.low_size + yc]
+                                                  : hb[j - (int)U.q] + yc;
+                const C s = gk[pos];
+                const double sr = (double)s.x, si = (double)s.y;
+                const double ur = (double)uc[j].x, ui = (double)uc[j].y;
+                accr += ur * sr - ui * si;
+                acci += ur * si + ui * sr;
+                if (ok) {
+                    // s * conj(a)
+                    const double ar = (double)a.x, ai = (double)a.y;
+                    double2 &pj = part[j * 64 + lane];
+                    pj.x += sr * ar + si * ai;
+                    pj.y += si * ar - sr * ai;
+                }
+            }
+            if (ok) gkm1[U.low_base + y] = C{(T)accr, (T)acci};
+        }
+        // reduce this unit's partials over lanes in a fixed tree
+        __syncthreads();
+        for (int j = 0; j < p.m; ++j) {
+            double2 v = part[j * 64 + lane];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) {
+                v.x += __shfl_xor(v.x, off, 64);
+                v.y += __shfl_xor(v.y, off, 64);
+            }
+            if (lane == 0) ((double2 *)p.partials)[u * (uint64_t)p.m + j] = v;
+        }
+        __syncthreads();
+    }
+}
+
+// colsum[j] = sum over units of partials[unit][j], fixed order
+__global__ __launch_bounds__(256) void colsum_kernel(const double2 *__restrict__ partials, uint64_t nunits, int m,
+                                                     double2 *__restrict__ colsum)
+{
+    __shared__ double2 sh[256];
+    const int j = blockIdx.x;
+    double2 s{0.0, 0.0};
+    for (uint64_t u = threadIdx.x; u < nunits; u += 256) {
+        const double2 v = partials[u * (uint64_t)m + j];
+        s.x += v.x;
+        s.y += v.y;
+    }
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            sh[threadIdx.x].x += sh[threadIdx.x + w].x;
+            sh[threadIdx.x].y += sh[threadIdx.x + w].y;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) colsum[j] = sh[0];
+}
+
+// G_U[j, i] = sum over layers k with i_k = i of colsum_k[j], in order of k
+template <typename T>
+__global__ void gradu_kernel(const double2 *__restrict__ colsum, const int32_t *__restrict__ photons, int n, int m,
+                             typename Cb<T>::type *__restrict__ GU)
+{
+    using C = typename Cb<T>::type;
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= m * m) return;
+    const int j = idx / m, i = idx % m;
+    double gr = 0.0, gi = 0.0;
+    for (int k = 1; k <= n; ++k)
+        if (photons[k - 1] == i) {
+            gr += colsum[(size_t)(k - 1) * m + j].x;
+            gi += colsum[(size_t)(k - 1) * m + j].y;
+        }
+    GU[(size_t)j * m + i] = C{(T)gr, (T)gi};
+}
+
+// ---- rectangular MZI mesh --------------------------------------------------------
+// MZI(a, b) = PS_1(b) BS PS_0(a) BS with BS = [[c, i s], [i s, c]] at theta = pi/2
+// (Eq. eq:bs): the composition BS, PS(phi_a) on mode 0, BS, PS(phi_b) on mode 1.
+// Column c holds MZIs on (p, p+1), p = c mod 2, c mod 2 + 2, ..., p + 1 < m, in
+// this order; U = T_last ... T_first.
+struct Cd {
+    double x, y;
+};
+__device__ __forceinline__ Cd cmul(Cd a, Cd b) { return Cd{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
+__device__ __forceinline__ Cd cadd(Cd a, Cd b) { return Cd{a.x + b.x, a.y + b.y}; }
+__device__ __forceinline__ Cd cconj(Cd a) { return Cd{a.x, -a.y}; }
+
+// 2x2 MZI block B and its derivatives dB/da, dB/db
+__device__ void mzi_block(double a, double b, Cd B[4], Cd dA[4], Cd dBb[4])
+{
+    const double r = 0.70710678118654752440;  // cos(pi/4) = sin(pi/4)
+    // BS * BS-like products written out: BS = r [[1, i], [i, 1]]
+    // M = BS PS0(a) BS = r^2 [[e^{ia} - 1, i(e^{ia} + 1)], [i(e^{ia} + 1), -e^{ia} + 1]]
+    double sa, ca, sb, cb;
+    sincos(a, &sa, &ca);
+    sincos(b, &sb, &cb);
+    const Cd ea{ca, sa}, eb{cb, sb};
+    const double h = r * r;
+    const Cd m00{h * (ea.x - 1.0), h * ea.y};
+    const Cd m01{-h * ea.y, h * (ea.x + 1.0)};   // i h (e^{ia} + 1)
+    const Cd m10 = m01;
+    const Cd m11{h * (1.0 - ea.x), -h * ea.y};
+    // B = diag(1, e^{ib}) M
+    B[0] = m00;
+    B[1] = m01;
+    B[2] = cmul(eb, m10);
+    B[3] = cmul(eb, m11);
+    // dM/da: d e^{ia} = i e^{ia}
+    const Cd iea{-ea.y, ea.x};
+    const Cd d00{h * iea.x, h * iea.y};
+    const Cd d01{-h * iea.y, h * iea.x};          // i h (i e^{ia})
+    const Cd d11{-h * iea.x, -h * iea.y};
+    dA[0] = d00;
+    dA[1] = d01;
+    dA[2] = cmul(eb, d01);
+    dA[3] = cmul(eb, d11);
+    const Cd ieb{-eb.y, eb.x};
+    dBb[0] = Cd{0.0, 0.0};
+    dBb[1] = Cd{0.0, 0.0};
+    dBb[2] = cmul(ieb, m10);
+    dBb[3] = cmul(ieb, m11);
+}
+
+// one workgroup per phase set; thread c owns column c of the running product
+template <typename T>
+__global__ void mesh_forward_kernel(int m, int nmzi, const double *__restrict__ phases,
+                                    typename Cb<T>::type *__restrict__ Uout)
+{
+    using C = typename Cb<T>::type;
+    extern __shared__ Cd Ush[];  // m x m
+    const int b = blockIdx.x;
+    const double *ph = phases + (size_t)b * 2 * nmzi;
+    const int c = threadIdx.x;
+    if (c < m)
+        for (int r = 0; r < m; ++r) Ush[r * m + c] = Cd{r == c ? 1.0 : 0.0, 0.0};
+    __syncthreads();
+    int k = 0;
+    for (int col = 0; col < m; ++col)
+        for (int p0 = col % 2; p0 + 1 < m; p0 += 2, ++k) {
+            Cd B[4], dA[4], dB[4];
+            mzi_block(ph[2 * k], ph[2 * k + 1], B, dA, dB);
+            if (c < m) {
+                const Cd x0 = Ush[p0 * m + c], x1 = Ush[(p0 + 1) * m + c];
+                Ush[p0 * m + c] = cadd(cmul(B[0], x0), cmul(B[1], x1));
+                Ush[(p0 + 1) * m + c] = cadd(cmul(B[2], x0), cmul(B[3], x1));
+            }
+            __syncthreads();
+        }
+    if (c < m)
+        for (int r = 0; r < m; ++r) {
+            const Cd v = Ush[r * m + c];
+            Uout[(size_t)b * m * m + (size_t)r * m + c] = C{(T)v.x, (T)v.y};
+        }
+}
+
+// Reverse sweep: with U = L_k T_k R_k, P = L_k^H G_U and Q = L_k^H U = T_k R_k,
+//   dL/dphi = Re sum conj(P) o (dT_k T_k^H Q),
+// then P <- T_k^H P and Q <- T_k^H Q move to the previous MZI.
+template <typename T>
+__global__ void mesh_backward_kernel(int m, int nmzi, const double *__restrict__ phases,
+                                     const typename Cb<T>::type *__restrict__ GU, double *__restrict__ gphases)
+{
+    extern __shared__ Cd sh[];  // P (m x m), Q (m x m), red (2 x blockDim)
+    Cd *P = sh;
+    Cd *Q = sh + m * m;
+    double *red = (double *)(sh + 2 * m * m);
+    const int b = blockIdx.x;
+    const double *ph = phases + (size_t)b * 2 * nmzi;
+    const int c = threadIdx.x;
+    // Q = U (rebuilt here), P = G_U
+    if (c < m)
+        for (int r = 0; r < m; ++r) {
+            Q[r * m + c] = Cd{r == c ? 1.0 : 0.0, 0.0};
+            const auto g = GU[(size_t)b * m * m + (size_t)r * m + c];
+            P[r * m + c] = Cd{(double)g.x, (double)g.y};
+        }
+    __syncthreads();
+    int k = 0;
+    for (int col = 0; col < m; ++col)
+        for (int p0 = col % 2; p0 + 1 < m; p0 += 2, ++k) {
+            Cd B[4], dA[4], dB[4];
+            mzi_block(ph[2 * k], ph[2 * k + 1], B, dA, dB);
+            if (c < m) {
+                const Cd x0 = Q[p0 * m + c], x1 = Q[(p0 + 1) * m + c];
+                Q[p0 * m + c] = cadd(cmul(B[0], x0), cmul(B[1], x1));
+                Q[(p0 + 1) * m + c] = cadd(cmul(B[2], x0), cmul(B[3], x1));
+            }
+            __syncthreads();
+        }
+    for (k = nmzi - 1; k >= 0; --k) {
+        // position of MZI k
+        int col = 0, p0 = 0, kk = 0;
+        for (col = 0; col < m; ++col) {
+            const int cnt = (m - 1 - (col % 2) + 1) / 2;
+            if (kk + cnt > k) {
+                p0 = col % 2 + 2 * (k - kk);
+                break;
+            }
+            kk += cnt;
+        }
+        Cd B[4], dA[4], dB[4];
+        mzi_block(ph[2 * k], ph[2 * k + 1], B, dA, dB);
+        // D = dT T^H restricted to rows p0, p0+1 (2x2): D = dB B^H
+        Cd Da[4], Db[4];
+        for (int r = 0; r < 2; ++r)
+            for (int s = 0; s < 2; ++s) {
+                Da[2 * r + s] = cadd(cmul(dA[2 * r], cconj(B[2 * s])), cmul(dA[2 * r + 1], cconj(B[2 * s + 1])));
+                Db[2 * r + s] = cadd(cmul(dB[2 * r], cconj(B[2 * s])), cmul(dB[2 * r + 1], cconj(B[2 * s + 1])));
+            }
+        double va = 0.0, vb = 0.0;
+        if (c < m) {
+            const Cd q0 = Q[p0 * m + c], q1 = Q[(p0 + 1) * m + c];
+            const Cd pp0 = P[p0 * m + c], pp1 = P[(p0 + 1) * m + c];
+            const Cd ya0 = cadd(cmul(Da[0], q0), cmul(Da[1], q1));
+            const Cd ya1 = cadd(cmul(Da[2], q0), cmul(Da[3], q1));
+            const Cd yb0 = cadd(cmul(Db[0], q0), cmul(Db[1], q1));
+            const Cd yb1 = cadd(cmul(Db[2], q0), cmul(Db[3], q1));
+            va = pp0.x * ya0.x + pp0.y * ya0.y + pp1.x * ya1.x + pp1.y * ya1.y;
+            vb = pp0.x * yb0.x + pp0.y * yb0.y + pp1.x * yb1.x + pp1.y * yb1.y;
+        }
+        red[c] = va;
+        red[blockDim.x + c] = vb;
+        __syncthreads();
+        for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+            if (c < w) {
+                red[c] += red[c + w];
+                red[blockDim.x + c] += red[blockDim.x + c + w];
+            }
+            __syncthreads();
+        }
+        if (c == 0) {
+            gphases[(size_t)b * 2 * nmzi + 2 * k] = red[0];
+            gphases[(size_t)b * 2 * nmzi + 2 * k + 1] = red[blockDim.x];
+        }
+        // P <- T^H P, Q <- T^H Q on rows p0, p0+1
+        if (c < m) {
+            const Cd q0 = Q[p0 * m + c], q1 = Q[(p0 + 1) * m + c];
+            Q[p0 * m + c] = cadd(cmul(cconj(B[0]), q0), cmul(cconj(B[2]), q1));
+            Q[(p0 + 1) * m + c] = cadd(cmul(cconj(B[1]), q0), cmul(cconj(B[3]), q1));
+            const Cd x0 = P[p0 * m + c], x1 = P[(p0 + 1) * m + c];
+            P[p0 * m + c] = cadd(cmul(cconj(B[0]), x0), cmul(cconj(B[2]), x1));
+            P[(p0 + 1) * m + c] = cadd(cmul(cconj(B[1]), x0), cmul(cconj(B[3]), x1));
+        }
+        __syncthreads();
+    }
+}
+
+} // namespace
+
+int slos_launch_seed(const void *heads, uint64_t nleaves, uint32_t stride, const double *lowfac, const void *ga,
+                     void *gn, int c64, void *stream)
+{
+    const int grid = (int)(nleaves < 1024 ? (nleaves + 3) / 4 : 256);
+    if (c64)
+        hipLaunchKernelGGL(seed_kernel<float>, dim3(grid > 0 ? grid : 1), dim3(256), 0, (hipStream_t)stream,
+                           (const LeafDescHead *)heads, nleaves, stride, lowfac, (const float2 *)ga, (float2 *)gn);
+    else
+        hipLaunchKernelGGL(seed_kernel<double>, dim3(grid > 0 ? grid : 1), dim3(256), 0, (hipStream_t)stream,
+                           (const LeafDescHead *)heads, nleaves, stride, lowfac, (const double2 *)ga, (double2 *)gn);
+    return (int)hipGetLastError();
+}
+
+// raise the dynamic-LDS limit of a kernel once per process
+template <typename K>
+static hipError_t allow_lds(K kernel, bool &done)
+{
+    if (done) return hipSuccess;
+    hipError_t e = hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)SLOS_LDS_DYNAMIC_MAX);
+    if (e == hipSuccess) done = true;
+    return e;
+}
+
+int slos_launch_bwd_layer(const BwdParams &p, int c64, int grid, void *stream)
+{
+    static bool a32 = false, a64 = false;
+    hipError_t e = c64 ? allow_lds(bwd_layer_kernel<float>, a32) : allow_lds(bwd_layer_kernel<double>, a64);
+    if (e != hipSuccess) return (int)e;
+    const size_t lds = (size_t)p.m * 64 * sizeof(double2);
+    if (c64)
+        hipLaunchKernelGGL(bwd_layer_kernel<float>, dim3(grid), dim3(64), lds, (hipStream_t)stream, p);
+    else
+        hipLaunchKernelGGL(bwd_layer_kernel<double>, dim3(grid), dim3(64), lds, (hipStream_t)stream, p);
+    return (int)hipGetLastError();
+}
+
+int slos_launch_colsum(const void *partials, uint64_t nunits, int m, void *colsum, void *stream)
+{
+    hipLaunchKernelGGL(colsum_kernel, dim3(m), dim3(256), 0, (hipStream_t)stream, (const double2 *)partials,
+                       nunits, m, (double2 *)colsum);
+    return (int)hipGetLastError();
+}
+
+int slos_launch_gradu(const void *colsum, const int32_t *photons, int n, int m, void *GU, int c64, void *stream)
+{
+    const int total = m * m;
+    const int grid = (total + 255) / 256;
+    if (c64)
+        hipLaunchKernelGGL(gradu_kernel<float>, dim3(grid), dim3(256), 0, (hipStream_t)stream,
+                           (const double2 *)colsum, photons, n, m, (float2 *)GU);
+    else
+        hipLaunchKernelGGL(gradu_kernel<double>, dim3(grid), dim3(256), 0, (hipStream_t)stream,
+                           (const double2 *)colsum, photons, n, m, (double2 *)GU);
+    return (int)hipGetLastError();
+}
+
+int slos_launch_mesh_forward(int m, int batch, const double *phases, void *U, int c64, void *stream)
+{
+    const int nmzi = m * (m - 1) / 2;
+    const int threads = ((m + 63) / 64) * 64;
+    const size_t lds = (size_t)m * m * sizeof(Cd);
+    static bool a32 = false, a64 = false;
+    hipError_t e = c64 ? allow_lds(mesh_forward_kernel<float>, a32) : allow_lds(mesh_forward_kernel<double>, a64);
+    if (e != hipSuccess) return (int)e;
+    if (c64)
+        hipLaunchKernelGGL(mesh_forward_kernel<float>, dim3(batch), dim3(threads), lds, (hipStream_t)stream, m, nmzi,
+                           phases, (float2 *)U);
+    else
+        hipLaunchKernelGGL(mesh_forward_kernel<double>, dim3(batch), dim3(threads), lds, (hipStream_t)stream, m,
+                           nmzi, phases, (double2 *)U);
+    return (int)hipGetLastError();
+}
+
+int slos_launch_mesh_backward(int m, int batch, const double *phases, const void *GU, double *gphases, int c64,
+                              void *stream)
+{
+    const int nmzi = m * (m - 1) / 2;
+    const int threads = ((m + 63) / 64) * 64;
+    const size_t lds = 2 * (size_t)m * m * sizeof(Cd) + 2 * (size_t)threads * sizeof(double);
+    static bool a32 = false, a64 = false;
+    hipError_t e = c64 ? allow_lds(mesh_backward_kernel<float>, a32) : allow_lds(mesh_backward_kernel<double>, a64);
+    if (e != hipSuccess) return (int)e;
+    if (c64)
+        hipLaunchKernelGGL(mesh_backward_kernel<float>, dim3(batch), dim3(threads), lds, (hipStream_t)stream, m,
+                           nmzi, phases, (const float2 *)GU, gphases);
+    else
+        hipLaunchKernelGGL(mesh_backward_kernel<double>, dim3(batch), dim3(threads), lds, (hipStream_t)stream, m,
+                           nmzi, phases, (const double2 *)GU, gphases);
+    return (int)hipGetLastError();
+}

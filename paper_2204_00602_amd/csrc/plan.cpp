@@ -164,6 +164,20 @@ struct slos_plan_s {
     double *d_partials = nullptr;
     int64_t n_partials = 0;
     uint32_t *d_tickets = nullptr;    // SLOS_XCDS ticket counters per layer
+    // differentiation (SLOS_KEEP_LAYERS plans)
+    std::vector<std::vector<BwdUnit>> units;   // per layer
+    std::vector<uint32_t> succ;                // inner successor tables
+    std::vector<uint64_t> hbase;               // high-mode successor block bases
+    std::map<std::pair<int, int>, uint32_t> succ_of;
+    BwdUnit *d_units = nullptr;
+    std::vector<uint64_t> unit_off;
+    uint32_t *d_succ = nullptr;
+    uint64_t *d_hbase = nullptr;
+    void *d_g[2] = {nullptr, nullptr};         // adjoint layers (ping-pong)
+    void *d_bpart = nullptr;                   // double2 partials, all layers
+    std::vector<uint64_t> bpart_off;           // per layer, in double2 units
+    void *d_colsum = nullptr;                  // double2 [n][m]
+    int32_t *d_photons = nullptr;
     bool timing = false;
     bool timed_reduce = false;
     std::vector<hipEvent_t> events;   // n + 2 when timing is on
@@ -294,6 +308,58 @@ struct slos_plan_s {
         for (uint64_t b : bases) deltas.push_back(h.low_base - b);
     }
 
+    // succ[i*low_size + y] = colex rank in F(q, K) of y + e_i, y in F(q, K-1)
+    uint32_t succ_table(int q, int K)
+    {
+        auto key = std::make_pair(q, K);
+        auto it = succ_of.find(key);
+        if (it != succ_of.end()) return it->second;
+        const uint32_t ls = (uint32_t)B(q + K - 2, K - 1);
+        const uint32_t off = (uint32_t)succ.size();
+        succ.resize(succ.size() + (size_t)q * ls);
+        std::vector<int32_t> occ(q);
+        for (uint32_t y = 0; y < ls; ++y) {
+            colex_unrank(B, q, K - 1, y, occ.data());
+            for (int i = 0; i < q; ++i) {
+                occ[i] += 1;
+                succ[off + (size_t)i * ls + y] = (uint32_t)colex_rank(B, q, occ.data());
+                occ[i] -= 1;
+            }
+        }
+        succ_of[key] = off;
+        return off;
+    }
+
+    // reverse-layer units of layer k: one per forward leaf with K >= 1
+    void build_units(int k)
+    {
+        std::vector<int32_t> occ(m);
+        for (const LeafRec &L : leaves[k]) {
+            if (L.K == 0) continue;
+            BwdUnit u{};
+            LeafDescHead h;
+            std::vector<uint64_t> dl;
+            std::vector<uint8_t> md;
+            describe(k, L, h, dl, md);
+            u.out_base = h.out_base;
+            u.low_base = h.low_base;
+            u.low_size = h.low_size;
+            u.q = L.q;
+            u.succ_off = succ_table(L.q, L.K);
+            u.hbase_off = hbase.size();
+            // state (h + e_j, K-1 low photons in mode 0) for each high mode j
+            std::fill(occ.begin(), occ.end(), 0);
+            for (int i = 0; i < L.nhp; ++i) occ[L.hm[i]] += 1;
+            occ[0] += L.K - 1;
+            for (int j = L.q; j < m; ++j) {
+                occ[j] += 1;
+                hbase.push_back(colex_rank(B, m, occ.data()));
+                occ[j] -= 1;
+            }
+            units[k].push_back(u);
+        }
+    }
+
     void free_device()
     {
         auto f = [](void *p) {
@@ -313,6 +379,21 @@ struct slos_plan_s {
         f(d_partials);
         f(d_tickets);
         d_tickets = nullptr;
+        f(d_units);
+        f(d_succ);
+        f(d_hbase);
+        f(d_g[0]);
+        f(d_g[1]);
+        f(d_bpart);
+        f(d_colsum);
+        f(d_photons);
+        d_units = nullptr;
+        d_succ = nullptr;
+        d_hbase = nullptr;
+        d_g[0] = d_g[1] = nullptr;
+        d_bpart = nullptr;
+        d_colsum = nullptr;
+        d_photons = nullptr;
         d_binom = nullptr;
         d_leaves = nullptr;
         d_types = nullptr;
@@ -427,7 +508,7 @@ int slos_plan_ex(int m, int n, const int32_t *input_state, int flags, const slos
 
     slos_options_t o{};
     if (opts) o = *opts;
-    if (o.leaf_max == 0) o.leaf_max = 8192;
+    if (o.leaf_max == 0) o.leaf_max = (flags & SLOS_KEEP_LAYERS) ? 1024 : 8192;
     if (o.comp_from_layer == 0) o.comp_from_layer = std::max(1, n - 1);
     if (o.block_threads == 0) o.block_threads = 256;
     if (o.grid_blocks == 0) o.grid_blocks = 2048;
@@ -483,6 +564,10 @@ int slos_plan_ex(int m, int n, const int32_t *input_state, int flags, const slos
             p->gen_leaves(k, m - 1, k, hm, p->leaves[k]);
             for (const LeafRec &L : p->leaves[k])
                 p->low_max[k] = std::max(p->low_max[k], p->types[L.tab].low_size);
+        }
+        if (p->keep) {
+            p->units.resize(n + 1);
+            for (int k = 1; k <= n; ++k) p->build_units(k);
         }
         // one wave must be able to hold its low block in LDS
         const size_t es_ = (dt == SLOS_C64) ? 8 : 16;
@@ -642,6 +727,33 @@ int slos_plan_ex(int m, int n, const int32_t *input_state, int flags, const slos
         p->free_device();
         delete p;
         return rc;
+    }
+    if (p->keep && n > 0) {
+        std::vector<BwdUnit> allu;
+        p->unit_off.assign(n + 2, 0);
+        p->bpart_off.assign(n + 2, 0);
+        uint64_t bp = 0;
+        for (int k = 1; k <= n; ++k) {
+            p->unit_off[k] = allu.size();
+            p->bpart_off[k] = bp;
+            allu.insert(allu.end(), p->units[k].begin(), p->units[k].end());
+            bp += (uint64_t)p->units[k].size() * (uint64_t)m;
+        }
+        p->bpart_off[n + 1] = bp;
+        uint64_t gmax = *std::max_element(p->Nk.begin(), p->Nk.end());
+        std::vector<int32_t> ph(p->photons.begin(), p->photons.end());
+        if ((rc = dev_upload(&p->d_units, allu.data(), allu.size(), "reverse units")) ||
+            (rc = dev_upload(&p->d_succ, p->succ.data(), p->succ.size(), "successor tables")) ||
+            (rc = dev_upload(&p->d_hbase, p->hbase.data(), p->hbase.size(), "successor bases")) ||
+            (rc = dev_upload(&p->d_photons, ph.data(), ph.size(), "photon list")) ||
+            (rc = alloc_dev(&p->d_g[0], gmax * es, "adjoint layer")) ||
+            (rc = alloc_dev(&p->d_g[1], gmax * es, "adjoint layer")) ||
+            (rc = alloc_dev(&p->d_bpart, std::max<uint64_t>(bp, 1) * 16, "gradient partials")) ||
+            (rc = alloc_dev(&p->d_colsum, (size_t)n * m * 16, "gradient columns"))) {
+            p->free_device();
+            delete p;
+            return rc;
+        }
     }
     *out = p;
     return SLOS_OK;
@@ -812,6 +924,74 @@ int slos_plan_layer_ms(slos_plan_t p, float *ms, int count)
         e = hipEventElapsedTime(&ms[p->n], p->events[p->n], p->events[p->n + 1]);
         if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
     }
+    return SLOS_OK;
+}
+
+int slos_backward(slos_plan_t p, const void *U, const void *grad_a, void *grad_U, void *stream)
+{
+    int rc = check_plan(p);
+    if (rc) return rc;
+    if (!p->keep) return fail(SLOS_ERR_NOT_KEPT, "slos_backward needs a plan built with SLOS_KEEP_LAYERS");
+    if (!U || !grad_a || !grad_U) return fail(SLOS_ERR_INVALID_ARG, "U, grad_a and grad_U must be device pointers");
+    const int n = p->n, m = p->m;
+    if (m > SLOS_BWD_MAX_MODES)
+        return fail(SLOS_ERR_INVALID_ARG, "slos_backward supports m <= %d", SLOS_BWD_MAX_MODES);
+    const int c64 = p->c64 ? 1 : 0;
+    int e;
+    if (n == 0) {
+        // a(vacuum) = 1 does not depend on U
+        if ((e = slos_launch_zero_u32((uint32_t *)grad_U, (int)((size_t)m * m * p->elem() / 4), stream)))
+            return hip_fail((hipError_t)e, "zero kernel");
+        return SLOS_OK;
+    }
+    const size_t es = p->elem();
+    const size_t rec = p->desc_wide[n] ? sizeof(LeafDescWide) : sizeof(LeafDescNarrow);
+    // g_n = c_S g_a
+    if ((e = slos_launch_seed(p->d_desc + p->desc_off[n], p->leaves[n].size(), (uint32_t)rec, p->d_lowfac, grad_a,
+                              p->d_g[n & 1], c64, stream)))
+        return hip_fail((hipError_t)e, "seed kernel");
+    for (int k = n; k >= 1; --k) {
+        BwdParams bp{};
+        bp.gk = p->d_g[k & 1];
+        bp.gkm1 = p->d_g[(k - 1) & 1];
+        bp.Akm1 = (const char *)p->d_keep + p->keep_off[k - 1] * es;
+        bp.U = U;
+        bp.units = p->d_units + p->unit_off[k];
+        bp.nunits = p->units[k].size();
+        bp.succ = p->d_succ;
+        bp.hbase = p->d_hbase;
+        bp.partials = (char *)p->d_bpart + p->bpart_off[k] * 16;
+        bp.m = m;
+        bp.col = p->photons[k - 1];
+        const int grid = (int)std::max<uint64_t>(1, std::min<uint64_t>(bp.nunits, 4096));
+        if ((e = slos_launch_bwd_layer(bp, c64, grid, stream))) return hip_fail((hipError_t)e, "reverse layer");
+        if ((e = slos_launch_colsum(bp.partials, bp.nunits, m, (char *)p->d_colsum + (size_t)(k - 1) * m * 16,
+                                    stream)))
+            return hip_fail((hipError_t)e, "column sum kernel");
+    }
+    if ((e = slos_launch_gradu(p->d_colsum, p->d_photons, n, m, grad_U, c64, stream)))
+        return hip_fail((hipError_t)e, "gradient assembly");
+    return SLOS_OK;
+}
+
+int slos_mesh_unitary(int m, int batch, const double *phases, void *U, int dtype, void *stream)
+{
+    if (m < 2 || m > SLOS_MESH_MAX_MODES || batch < 1 || !phases || !U)
+        return fail(SLOS_ERR_INVALID_ARG, "need 2 <= m <= %d, batch >= 1 and device pointers", SLOS_MESH_MAX_MODES);
+    if (dtype != SLOS_C64 && dtype != SLOS_C128) return fail(SLOS_ERR_DTYPE, "dtype must be SLOS_C64 or SLOS_C128");
+    int e = slos_launch_mesh_forward(m, batch, phases, U, dtype == SLOS_C64, stream);
+    if (e) return hip_fail((hipError_t)e, "mesh kernel");
+    return SLOS_OK;
+}
+
+int slos_mesh_backward(int m, int batch, const double *phases, const void *grad_U, double *grad_phases, int dtype,
+                       void *stream)
+{
+    if (m < 2 || m > SLOS_MESH_MAX_MODES || batch < 1 || !phases || !grad_U || !grad_phases)
+        return fail(SLOS_ERR_INVALID_ARG, "need 2 <= m <= %d, batch >= 1 and device pointers", SLOS_MESH_MAX_MODES);
+    if (dtype != SLOS_C64 && dtype != SLOS_C128) return fail(SLOS_ERR_DTYPE, "dtype must be SLOS_C64 or SLOS_C128");
+    int e = slos_launch_mesh_backward(m, batch, phases, grad_U, grad_phases, dtype == SLOS_C64, stream);
+    if (e) return hip_fail((hipError_t)e, "mesh reverse kernel");
     return SLOS_OK;
 }
 

@@ -155,3 +155,48 @@ int slos_launch_layer(const LayerParams &p, const LayerLaunch &l, void *stream);
 int slos_launch_reduce(const double *partials, int64_t count, double *stage, double *out, void *stream);
 int slos_launch_vacuum(void *out, int c64, int mode, double *sum_p, void *stream);
 int slos_launch_zero_u32(uint32_t *buf, int count, void *stream);
+
+// ---- differentiation ----------------------------------------------------------
+
+// One unit of the reverse layer k: the low block of a forward leaf of layer k
+// (same high part h, K-1 low photons), which lies at low_base in A_{k-1}.
+// The successor of low state y through low mode i < q is the forward leaf's
+// state out_base + succ[succ_off + i*low_size + y]; through high mode j >= q it
+// is hbase[hbase_off + j - q] + y (the block of high part h + e_j in layer k).
+struct BwdUnit {
+    uint64_t out_base;
+    uint64_t low_base;
+    uint64_t hbase_off;
+    uint32_t low_size;
+    uint32_t succ_off;
+    uint32_t q;
+    uint32_t pad;
+};
+static_assert(sizeof(BwdUnit) == 40, "BwdUnit must stay 40 bytes");
+
+struct BwdParams {
+    const void *gk;          // g_k (layer k), plan dtype
+    void *gkm1;              // g_{k-1}
+    const void *Akm1;        // kept A_{k-1}
+    const void *U;           // m x m
+    const BwdUnit *units;
+    uint64_t nunits;
+    const uint32_t *succ;
+    const uint64_t *hbase;
+    void *partials;          // double2 [nunits][m]
+    int m;
+    int col;                 // i_k
+};
+
+#define SLOS_BWD_MAX_MODES 64   // the reverse layer keeps m x 64 FP64 partials in LDS
+#define SLOS_MESH_MAX_MODES 64  // the mesh kernels keep two m x m FP64 matrices in LDS
+
+int slos_launch_seed(const void *heads, uint64_t nleaves, uint32_t stride, const double *lowfac, const void *ga,
+                     void *gn, int c64, void *stream);
+int slos_launch_bwd_layer(const BwdParams &p, int c64, int grid, void *stream);
+int slos_launch_colsum(const void *partials, uint64_t nunits, int m, void *colsum, void *stream);
+int slos_launch_gradu(const void *colsum, const int32_t *photons, int n, int m, void *GU, int c64, void *stream);
+int slos_launch_mesh_forward(int m, int batch, const double *phases, void *U, int c64, void *stream);
+int slos_launch_mesh_backward(int m, int batch, const double *phases, const void *GU, double *gphases, int c64,
+                              void *stream);
+

@@ -72,13 +72,17 @@ def lib():
     L.slos_plan_leaf.argtypes = [vp, ctypes.c_int, ctypes.c_int64, i64p, i32p, i32p, i32p]
     L.slos_amplitudes.argtypes = [vp, vp, vp, vp, vp]
     L.slos_probs.argtypes = [vp, vp, vp, vp, vp]
+    L.slos_backward.argtypes = [vp, vp, vp, vp, vp]
+    L.slos_mesh_unitary.argtypes = [ctypes.c_int, ctypes.c_int, vp, vp, ctypes.c_int, vp]
+    L.slos_mesh_backward.argtypes = [ctypes.c_int, ctypes.c_int, vp, vp, vp, ctypes.c_int, vp]
     L.slos_plan_set_timing.argtypes = [vp, ctypes.c_int]
     L.slos_plan_layer_ms.argtypes = [vp, ctypes.POINTER(ctypes.c_float), ctypes.c_int]
     L.slos_last_error.argtypes = []
     L.slos_last_error.restype = ctypes.c_char_p
     for name in ("slos_fock_count", "slos_fock_rank", "slos_fock_unrank", "slos_plan",
                  "slos_plan_ex", "slos_plan_info", "slos_plan_leaf", "slos_amplitudes",
-                 "slos_probs", "slos_plan_set_timing", "slos_plan_layer_ms"):
+                 "slos_probs", "slos_plan_set_timing", "slos_plan_layer_ms", "slos_backward",
+                 "slos_mesh_unitary", "slos_mesh_backward"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -214,6 +218,7 @@ class Plan:
         """out[rank(S)] = a(S) for all S; returns out (and fills sum_p[0] = sum P if given)."""
         import torch
         self._check_U(U)
+        self.forward_count = getattr(self, "forward_count", 0) + 1
         if out is None:
             out = torch.empty(self.num_outputs, dtype=self._complex_dtype(), device=U.device)
         elif out.dtype != self._complex_dtype() or out.numel() != self.num_outputs or not out.is_contiguous():
@@ -230,6 +235,7 @@ class Plan:
         """out[rank(S)] = P(S) (float32 for c64, float64 for c128)."""
         import torch
         self._check_U(U)
+        self.forward_count = getattr(self, "forward_count", 0) + 1
         rdt = torch.float32 if self.dtype == "c64" else torch.float64
         if out is None:
             out = torch.empty(self.num_outputs, dtype=rdt, device=U.device)
@@ -243,6 +249,23 @@ class Plan:
         _check(self._lib.slos_probs(self._h, U.data_ptr(), out.data_ptr(), sp, _stream_ptr(stream)))
         return out
 
+    def backward(self, U, grad_a, grad_U=None, stream=None):
+        """Gradient with respect to U of a real loss, given its gradient with
+        respect to the amplitudes (both in the PyTorch complex convention).
+        Uses the layers kept by the last forward call on this plan."""
+        import torch
+        self._check_U(U)
+        if not (self.flags & SLOS_KEEP_LAYERS):
+            raise SlosError(-6, "plan was built without keep_layers=True")
+        if grad_a.dtype != self._complex_dtype() or grad_a.numel() != self.num_outputs:
+            raise ValueError("grad_a has the wrong dtype or size")
+        grad_a = grad_a.contiguous()
+        if grad_U is None:
+            grad_U = torch.empty_like(U)
+        _check(self._lib.slos_backward(self._h, U.data_ptr(), grad_a.data_ptr(), grad_U.data_ptr(),
+                                       _stream_ptr(stream)))
+        return grad_U
+
     def rank(self, state) -> int:
         s = _state_arr(state, self.m)
         if int(s.sum()) != self.n:
@@ -251,6 +274,39 @@ class Plan:
 
     def unrank(self, r: int) -> np.ndarray:
         return fock_unrank(self.m, self.n, r)
+
+
+def mesh_mzi_count(m: int) -> int:
+    return m * (m - 1) // 2
+
+
+def mesh_unitary(phases, m: int, dtype: str = "c128", stream=None):
+    """U (batch x m x m) of the rectangular MZI mesh for FP64 phases (batch x m(m-1))."""
+    import torch
+    if phases.dtype != torch.float64 or phases.device.type != "cuda":
+        raise TypeError("phases must be a float64 CUDA tensor")
+    phases = phases.contiguous()
+    batch = phases.shape[0] if phases.dim() == 2 else 1
+    if phases.numel() != batch * 2 * mesh_mzi_count(m):
+        raise ValueError("phases must hold 2 * m(m-1)/2 values per batch entry")
+    cdt = torch.complex64 if dtype == "c64" else torch.complex128
+    U = torch.empty((batch, m, m), dtype=cdt, device=phases.device)
+    _check(lib().slos_mesh_unitary(m, batch, phases.data_ptr(), U.data_ptr(),
+                                   SLOS_C64 if dtype == "c64" else SLOS_C128, _stream_ptr(stream)))
+    return U
+
+
+def mesh_backward(phases, grad_U, stream=None):
+    """dL/dphases (batch x m(m-1), FP64) from grad_U (batch x m x m, PyTorch convention)."""
+    import torch
+    phases = phases.contiguous()
+    grad_U = grad_U.contiguous()
+    batch, m = grad_U.shape[0], grad_U.shape[-1]
+    dt = SLOS_C64 if grad_U.dtype == torch.complex64 else SLOS_C128
+    g = torch.empty((batch, 2 * mesh_mzi_count(m)), dtype=torch.float64, device=phases.device)
+    _check(lib().slos_mesh_backward(m, batch, phases.data_ptr(), grad_U.data_ptr(), g.data_ptr(), dt,
+                                    _stream_ptr(stream)))
+    return g
 
 
 def algorithmic_bytes(m: int, n: int, elem_bytes: int, last_write_bytes: Optional[int] = None) -> int:
