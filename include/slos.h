@@ -168,6 +168,40 @@ int slos_mesh_unitary(int m, int batch, const double *phases, void *U, int dtype
 int slos_mesh_backward(int m, int batch, const double *phases, const void *grad_U, double *grad_phases, int dtype,
                        void *stream);
 
+/* ---- batches of independent instances --------------------------------------- */
+
+typedef struct slos_batch_s *slos_batch_t;
+
+/*
+ * Plan `count` independent instances of uneven size (the QML loop of Appendix
+ * B.6 evaluates many unitaries per loss).  Instance i has ms[i] modes and its
+ * input occupations follow those of instance i-1 in `inputs` (sum of ms[i]
+ * int32 in total), with at most 16 photons.  flags: SLOS_C64 or SLOS_C128.
+ * opts: leaf_max (default 1024), block_threads, grid_blocks (workgroups,
+ * default 1024), outputs_per_lane (default 2); other fields are ignored.
+ * The whole batch runs in one kernel launch: each workgroup computes whole
+ * instances, all layers, assigned on the host largest-first to the least
+ * loaded workgroup, so no workgroup waits on another.
+ */
+int slos_batch_plan(int count, const int32_t *ms, const int32_t *inputs, int flags, const slos_options_t *opts,
+                    slos_batch_t *out);
+void slos_batch_destroy(slos_batch_t batch);
+
+/* Packed layouts: U of instance i starts at element u_offsets[i] (row-major
+ * m_i x m_i), its C(m_i+n_i-1, n_i) amplitudes at out_offsets[i] (colex
+ * order).  Both arrays take count + 1 entries (the last is the total). */
+int slos_batch_offsets(slos_batch_t batch, int64_t *u_offsets, int64_t *out_offsets);
+
+/* All amplitudes of every instance (device, packed).  sum_p: device, count
+ * doubles (sum of P per instance, FP64), or NULL. */
+int slos_batch_amplitudes(slos_batch_t batch, const void *U, void *out, double *sum_p, void *stream);
+
+/* Capture the batch launch for these buffers into a HIP graph owned by the
+ * batch (replacing an earlier one); slos_batch_replay launches it on a stream.
+ * The buffers stay bound to the graph. */
+int slos_batch_capture(slos_batch_t batch, const void *U, void *out, double *sum_p);
+int slos_batch_replay(slos_batch_t batch, void *stream);
+
 /* ---- timing ----------------------------------------------------------------- */
 
 /*

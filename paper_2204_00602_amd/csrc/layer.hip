@@ -442,6 +442,92 @@ __global__ __launch_bounds__(256) void layer_kernel(LayerParams p)
     }
 }
 
+// ---- batches ----------------------------------------------------------------------
+// One workgroup runs whole instances, layer after layer; its waves take the
+// layer's leaves in turn (each wave stages its leaf's low block in its own LDS
+// slice) and a barrier separates layers.  Layers live in two per-workgroup
+// scratch buffers; the last one goes straight to the packed output.  The host
+// assigns instances to workgroups (largest first, to the least loaded), so no
+// workgroup waits on another and the schedule is fixed.
+template <typename T, int RR>
+__global__ __launch_bounds__(256) void batch_kernel(BatchParams bp)
+{
+    using C = typename Cx<T>::type;
+    __shared__ C u_lds[256];
+    __shared__ double wsum[4];
+    extern __shared__ unsigned char dyn_lds[];
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int W = blockDim.x >> 6;
+    unsigned char *slice = dyn_lds + (size_t)wv * bp.lds_wave_bytes;
+    C *scr[2];
+    scr[0] = (C *)bp.scratch + (size_t)blockIdx.x * 2 * bp.scratch_stride;
+    scr[1] = scr[0] + bp.scratch_stride;
+    const C *Ub = (const C *)bp.U;
+
+    for (uint32_t e = bp.wg_start[blockIdx.x]; e < bp.wg_start[blockIdx.x + 1]; ++e) {
+        const uint32_t ii = bp.wg_list[e];
+        const BatchInst &I = bp.inst[ii];
+        const int m = (int)I.m, n = (int)I.n;
+        double psum = 0.0;
+        if (n == 0 && threadIdx.x == 0) {
+            // no photons: the single output is the vacuum, amplitude 1
+            ((C *)bp.out)[I.out_off] = C{(T)1, (T)0};
+            psum = 1.0;
+        }
+        for (int k = 1; k <= n; ++k) {
+            __syncthreads();  // layer k-1 is complete and every LDS slice is free
+            const int col = I.col[k - 1];
+            for (int j = threadIdx.x; j < 256; j += blockDim.x) {
+                C v{0, 0};
+                if (j < m) v = Ub[I.U_off + (size_t)j * m + col];
+                u_lds[j] = v;
+            }
+            __syncthreads();
+            const C *X = k == 1 ? (const C *)bp.vac : scr[(k - 1) & 1];
+            LayerParams lp{};
+            lp.Y = k == n ? (void *)((C *)bp.out + I.out_off) : (void *)scr[k & 1];
+            lp.pred = bp.pred;
+            lp.lowfac = bp.lowfac;
+            const uint32_t nl = I.nleaves[k - 1];
+            for (uint32_t li = (uint32_t)wv; li < nl; li += (uint32_t)W) {
+                const DescRegs<false> d = load_desc<false>(bp.desc, (uint64_t)I.desc_off[k - 1] + li, lane);
+                const Leaf L = decode_head<false>(d);
+                const C *lowbuf = stage_low<C>(X, L, slice, lane);
+                __builtin_amdgcn_s_waitcnt(0);
+                __builtin_amdgcn_wave_barrier();
+                const uint32_t full = L.size / (64u * RR);
+                if (k == n) {
+                    for (uint32_t t = 0; t < full; ++t)
+                        tile<T, SLOS_MODE_AMPL, false, RR, false>(lp, d, L, X, u_lds, lowbuf, t * 64u * RR, lane,
+                                                                 psum);
+                    for (uint32_t t0 = full * 64u * RR; t0 < L.size; t0 += 64u)
+                        tile<T, SLOS_MODE_AMPL, false, 1, false>(lp, d, L, X, u_lds, lowbuf, t0, lane, psum);
+                } else {
+                    for (uint32_t t = 0; t < full; ++t)
+                        tile<T, SLOS_MODE_MID, false, RR, false>(lp, d, L, X, u_lds, lowbuf, t * 64u * RR, lane,
+                                                                psum);
+                    for (uint32_t t0 = full * 64u * RR; t0 < L.size; t0 += 64u)
+                        tile<T, SLOS_MODE_MID, false, 1, false>(lp, d, L, X, u_lds, lowbuf, t0, lane, psum);
+                }
+                __builtin_amdgcn_s_waitcnt(0);
+                __builtin_amdgcn_wave_barrier();
+            }
+        }
+        // sum P of the instance: per wave, then over waves in order
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) psum += __shfl_xor(psum, off, 64);
+        __syncthreads();
+        if (lane == 0) wsum[wv] = psum;
+        __syncthreads();
+        if (threadIdx.x == 0 && bp.sum_p) {
+            double s = 0.0;
+            for (int w = 0; w < W; ++w) s += wsum[w];
+            bp.sum_p[ii] = s;
+        }
+    }
+}
+
 // Deterministic two-stage sum of the per-leaf partials: workgroup b sums its
 // fixed contiguous segment (strided per thread, then a fixed LDS tree) into
 // stage[b]; a single workgroup then sums stage[] the same way.
@@ -572,3 +658,37 @@ int slos_launch_zero_u32(uint32_t *buf, int count, void *stream)
     hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(256), 0, (hipStream_t)stream, buf, count);
     return (int)hipGetLastError();
 }
+
+template <typename T, int RR>
+static hipError_t batch_attr()
+{
+    return hipFuncSetAttribute((const void *)batch_kernel<T, RR>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)SLOS_LDS_DYNAMIC_MAX);
+}
+
+int slos_prepare_batch_kernels(void)
+{
+    hipError_t e;
+    if ((e = batch_attr<float, 1>()) || (e = batch_attr<float, 2>()) || (e = batch_attr<float, 4>()) ||
+        (e = batch_attr<double, 1>()) || (e = batch_attr<double, 2>()) || (e = batch_attr<double, 4>()))
+        return (int)e;
+    return 0;
+}
+
+int slos_launch_batch(const BatchParams &p, int c64, int rr, int threads, int grid, void *stream)
+{
+    const size_t lds = (size_t)p.lds_wave_bytes * (size_t)(threads / 64);
+    hipStream_t s = (hipStream_t)stream;
+    dim3 g(grid), b(threads);
+    if (c64) {
+        if (rr == 1) hipLaunchKernelGGL((batch_kernel<float, 1>), g, b, lds, s, p);
+        else if (rr == 2) hipLaunchKernelGGL((batch_kernel<float, 2>), g, b, lds, s, p);
+        else hipLaunchKernelGGL((batch_kernel<float, 4>), g, b, lds, s, p);
+    } else {
+        if (rr == 1) hipLaunchKernelGGL((batch_kernel<double, 1>), g, b, lds, s, p);
+        else if (rr == 2) hipLaunchKernelGGL((batch_kernel<double, 2>), g, b, lds, s, p);
+        else hipLaunchKernelGGL((batch_kernel<double, 4>), g, b, lds, s, p);
+    }
+    return (int)hipGetLastError();
+}
+

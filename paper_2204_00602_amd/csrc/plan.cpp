@@ -1006,3 +1006,313 @@ int slos_probs(slos_plan_t p, const void *U, void *probs, double *sum_p, void *s
 }
 
 } // extern "C"
+
+// ---- batches ----------------------------------------------------------------------
+
+struct slos_batch_s {
+    int count = 0;
+    bool c64 = true;
+    slos_options_t opts{};
+    slos_plan_s builder;                 // shared binomials, leaves and inner tables
+    std::vector<BatchInst> inst;
+    std::vector<int64_t> out_off, u_off; // count + 1 each
+    std::vector<LeafDescNarrow> desc;
+    std::vector<uint32_t> wg_start, wg_list;
+    uint64_t scratch_stride = 0;         // elements per scratch buffer
+    uint32_t lds_wave_bytes = 0;
+    int grid = 0;
+    // device
+    BatchInst *d_inst = nullptr;
+    uint32_t *d_wg_start = nullptr, *d_wg_list = nullptr;
+    LeafDescNarrow *d_desc = nullptr;
+    uint32_t *d_pred = nullptr;
+    double *d_lowfac = nullptr;
+    void *d_scratch = nullptr;
+    void *d_vac = nullptr;
+    hipGraphExec_t exec = nullptr;
+
+    void free_device()
+    {
+        auto f = [](void *q) {
+            if (q) (void)hipFree(q);
+        };
+        f(d_inst);
+        f(d_wg_start);
+        f(d_wg_list);
+        f(d_desc);
+        f(d_pred);
+        f(d_lowfac);
+        f(d_scratch);
+        f(d_vac);
+        if (exec) (void)hipGraphExecDestroy(exec);
+        d_inst = nullptr;
+        d_wg_start = d_wg_list = nullptr;
+        d_desc = nullptr;
+        d_pred = nullptr;
+        d_lowfac = nullptr;
+        d_scratch = d_vac = nullptr;
+        exec = nullptr;
+    }
+
+    BatchParams params(const void *U, void *out, double *sum_p) const
+    {
+        BatchParams bp{};
+        bp.U = U;
+        bp.out = out;
+        bp.sum_p = sum_p;
+        bp.inst = d_inst;
+        bp.wg_start = d_wg_start;
+        bp.wg_list = d_wg_list;
+        bp.desc = d_desc;
+        bp.pred = d_pred;
+        bp.lowfac = d_lowfac;
+        bp.scratch = d_scratch;
+        bp.scratch_stride = scratch_stride;
+        bp.vac = d_vac;
+        bp.lds_wave_bytes = lds_wave_bytes;
+        return bp;
+    }
+};
+
+extern "C" {
+
+int slos_batch_plan(int count, const int32_t *ms, const int32_t *inputs, int flags, const slos_options_t *opts,
+                    slos_batch_t *out)
+{
+    if (!out) return fail(SLOS_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (count < 1 || !ms || !inputs) return fail(SLOS_ERR_INVALID_ARG, "need count >= 1, ms and inputs");
+    if (flags & ~(SLOS_C64 | SLOS_C128))
+        return fail(SLOS_ERR_INVALID_ARG, "batch flags take SLOS_C64 or SLOS_C128 only");
+    const int dt = flags & (SLOS_C64 | SLOS_C128);
+    if (dt != SLOS_C64 && dt != SLOS_C128)
+        return fail(SLOS_ERR_DTYPE, "flags must hold exactly one of SLOS_C64, SLOS_C128");
+    slos_options_t o{};
+    if (opts) o = *opts;
+    if (o.leaf_max == 0) o.leaf_max = 1024;
+    if (o.block_threads == 0) o.block_threads = 256;
+    if (o.grid_blocks == 0) o.grid_blocks = 1024;
+    if (o.outputs_per_lane == 0) o.outputs_per_lane = 2;
+    if (o.leaf_max < 1 || o.leaf_max > 65536 || (o.block_threads != 64 && o.block_threads != 128 &&
+                                                 o.block_threads != 256) ||
+        o.grid_blocks < 1 || o.grid_blocks > (1 << 20) ||
+        (o.outputs_per_lane != 1 && o.outputs_per_lane != 2 && o.outputs_per_lane != 4))
+        return fail(SLOS_ERR_INVALID_ARG, "invalid batch options");
+
+    int maxm = 0, maxn = 0;
+    int64_t pos = 0;
+    for (int i = 0; i < count; ++i) {
+        const int m = ms[i];
+        if (m < 1 || m > SLOS_MAX_MODES) return fail(SLOS_ERR_INVALID_ARG, "instance %d: m = %d", i, m);
+        long tot = 0;
+        for (int j = 0; j < m; ++j) {
+            if (inputs[pos + j] < 0) return fail(SLOS_ERR_INVALID_ARG, "instance %d: negative occupation", i);
+            tot += inputs[pos + j];
+        }
+        if (tot > SLOS_BATCH_MAX_N)
+            return fail(SLOS_ERR_INVALID_ARG, "instance %d: %ld photons, batches take at most %d", i, tot,
+                        SLOS_BATCH_MAX_N);
+        maxm = std::max(maxm, m);
+        maxn = std::max(maxn, (int)tot);
+        pos += m;
+    }
+
+    slos_batch_s *b = new (std::nothrow) slos_batch_s;
+    if (!b) return fail(SLOS_ERR_OOM, "host allocation of the batch failed");
+    b->count = count;
+    b->c64 = dt == SLOS_C64;
+    b->opts = o;
+    const size_t es = b->c64 ? 8 : 16;
+    try {
+        slos_plan_s &P = b->builder;
+        P.opts = o;
+        P.B.build(maxm + maxn, maxn);
+        b->inst.resize(count);
+        b->out_off.assign(count + 1, 0);
+        b->u_off.assign(count + 1, 0);
+        uint32_t low_max = 0;
+        uint64_t scratch = 1;
+        std::vector<double> cost(count);
+        pos = 0;
+        for (int i = 0; i < count; ++i) {
+            const int m = ms[i];
+            BatchInst &I = b->inst[i];
+            I = BatchInst{};
+            I.m = (uint32_t)m;
+            std::vector<int> photons;
+            double tf = 1.0;
+            for (int j = 0; j < m; ++j) {
+                for (int c = 0; c < inputs[pos + j]; ++c) photons.push_back(j);
+                for (int v = 2; v <= inputs[pos + j]; ++v) tf *= v;
+            }
+            const int n = (int)photons.size();
+            I.n = (uint32_t)n;
+            P.norm_t = 1.0 / std::sqrt(tf);
+            uint64_t M = P.B(m + n - 1, n);
+            b->u_off[i + 1] = b->u_off[i] + (int64_t)m * m;
+            b->out_off[i + 1] = b->out_off[i] + (int64_t)M;
+            I.U_off = (uint64_t)b->u_off[i];
+            I.out_off = (uint64_t)b->out_off[i];
+            double c = 0.0;
+            for (int k = 1; k <= n; ++k) {
+                std::vector<LeafRec> lv;
+                std::vector<uint8_t> hm;
+                P.gen_leaves(k, m - 1, k, hm, lv);
+                I.col[k - 1] = (uint8_t)photons[k - 1];
+                I.desc_off[k - 1] = (uint32_t)b->desc.size();
+                I.nleaves[k - 1] = (uint32_t)lv.size();
+                std::vector<uint64_t> deltas;
+                std::vector<uint8_t> modes;
+                for (const LeafRec &L : lv) {
+                    LeafDescHead h;
+                    P.describe(k, L, h, deltas, modes);
+                    if (h.nh > SLOS_NARROW_GROUPS) throw std::pair<int, std::string>(SLOS_ERR_INVALID_ARG, "too many groups");
+                    LeafDescNarrow w{};
+                    w.h = h;
+                    for (size_t g = 0; g < deltas.size(); ++g) {
+                        w.delta[g] = (uint32_t)deltas[g];
+                        w.mode[g] = modes[g];
+                    }
+                    b->desc.push_back(w);
+                    low_max = std::max(low_max, h.low_size);
+                }
+                const uint64_t Nk = P.B(m + k - 1, k);
+                if (k < n) scratch = std::max(scratch, Nk);
+                c += (double)(P.B(m + k - 2, k - 1) + Nk);
+            }
+            cost[i] = c + 64.0 * n;
+            pos += m;
+        }
+        // largest instance first, each to the least loaded workgroup
+        const int G = std::min(o.grid_blocks, count);
+        std::vector<int> order(count);
+        for (int i = 0; i < count; ++i) order[i] = i;
+        std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+        std::vector<double> load(G, 0.0);
+        std::vector<std::vector<uint32_t>> lists(G);
+        for (int i : order) {
+            int g = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+            load[g] += cost[i];
+            lists[g].push_back((uint32_t)i);
+        }
+        b->grid = G;
+        b->wg_start.assign(G + 1, 0);
+        for (int g = 0; g < G; ++g) {
+            b->wg_start[g + 1] = b->wg_start[g] + (uint32_t)lists[g].size();
+            b->wg_list.insert(b->wg_list.end(), lists[g].begin(), lists[g].end());
+        }
+        b->scratch_stride = scratch + (SLOS_BUFFER_SLACK + es - 1) / es;
+        b->lds_wave_bytes = slos_lds_wave_bytes(low_max, (uint32_t)es);
+        if (b->lds_wave_bytes * (uint32_t)(o.block_threads / 64) > SLOS_LDS_DYNAMIC_MAX)
+            throw std::pair<int, std::string>(SLOS_ERR_INVALID_ARG, "leaf_max too large for the LDS of a workgroup");
+        if (P.pred.size() >= (size_t(1) << 32) || b->desc.size() >= (size_t(1) << 32))
+            throw std::pair<int, std::string>(SLOS_ERR_SIZE_OVERFLOW, "batch tables too large");
+    } catch (std::bad_alloc &) {
+        delete b;
+        return fail(SLOS_ERR_OOM, "host allocation failed while building the batch");
+    } catch (std::pair<int, std::string> &e) {
+        delete b;
+        return fail(e.first, "%s", e.second.c_str());
+    }
+
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess || ndev < 1) {
+        delete b;
+        return fail(SLOS_ERR_NO_DEVICE, "no HIP device (%s)", hipGetErrorString(e));
+    }
+    int rc;
+    double one_d[2] = {1.0, 0.0};
+    float one_f[2] = {1.0f, 0.0f};
+    if ((rc = dev_upload(&b->d_inst, b->inst.data(), b->inst.size(), "batch instances")) ||
+        (rc = dev_upload(&b->d_wg_start, b->wg_start.data(), b->wg_start.size(), "batch schedule")) ||
+        (rc = dev_upload(&b->d_wg_list, b->wg_list.data(), b->wg_list.size(), "batch schedule")) ||
+        (rc = dev_upload(&b->d_desc, b->desc.data(), b->desc.size(), "batch descriptors")) ||
+        (rc = dev_upload(&b->d_pred, b->builder.pred.data(), b->builder.pred.size(), "batch inner tables")) ||
+        (rc = dev_upload(&b->d_lowfac, b->builder.lowfac.data(), b->builder.lowfac.size(), "batch factorials")) ||
+        (rc = alloc_dev(&b->d_scratch, (size_t)b->grid * 2 * b->scratch_stride * es + SLOS_BUFFER_SLACK,
+                        "batch scratch")) ||
+        (rc = alloc_dev(&b->d_vac, es + SLOS_BUFFER_SLACK, "vacuum layer"))) {
+        b->free_device();
+        delete b;
+        return rc;
+    }
+    if ((e = hipMemcpy(b->d_vac, b->c64 ? (const void *)one_f : (const void *)one_d, es, hipMemcpyHostToDevice)) !=
+            hipSuccess ||
+        (e = (hipError_t)slos_prepare_batch_kernels()) != hipSuccess) {
+        rc = hip_fail(e, "batch set-up");
+        b->free_device();
+        delete b;
+        return rc;
+    }
+    *out = b;
+    return SLOS_OK;
+}
+
+void slos_batch_destroy(slos_batch_t b)
+{
+    if (!b) return;
+    (void)hipDeviceSynchronize();
+    b->free_device();
+    delete b;
+}
+
+int slos_batch_offsets(slos_batch_t b, int64_t *u_offsets, int64_t *out_offsets)
+{
+    if (!b) return fail(SLOS_ERR_INVALID_ARG, "batch is NULL");
+    for (int i = 0; i <= b->count; ++i) {
+        if (u_offsets) u_offsets[i] = b->u_off[i];
+        if (out_offsets) out_offsets[i] = b->out_off[i];
+    }
+    return SLOS_OK;
+}
+
+int slos_batch_amplitudes(slos_batch_t b, const void *U, void *out, double *sum_p, void *stream)
+{
+    if (!b) return fail(SLOS_ERR_INVALID_ARG, "batch is NULL");
+    if (!U || !out) return fail(SLOS_ERR_INVALID_ARG, "U and out must be device pointers");
+    const BatchParams bp = b->params(U, out, sum_p);
+    int e = slos_launch_batch(bp, b->c64, b->opts.outputs_per_lane, b->opts.block_threads, b->grid, stream);
+    if (e) return hip_fail((hipError_t)e, "batch kernel");
+    return SLOS_OK;
+}
+
+int slos_batch_capture(slos_batch_t b, const void *U, void *out, double *sum_p)
+{
+    if (!b) return fail(SLOS_ERR_INVALID_ARG, "batch is NULL");
+    if (!U || !out) return fail(SLOS_ERR_INVALID_ARG, "U and out must be device pointers");
+    if (b->exec) {
+        (void)hipGraphExecDestroy(b->exec);
+        b->exec = nullptr;
+    }
+    hipStream_t s;
+    hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(e, "capture stream");
+    hipGraph_t g = nullptr;
+    e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        const BatchParams bp = b->params(U, out, sum_p);
+        int le = slos_launch_batch(bp, b->c64, b->opts.outputs_per_lane, b->opts.block_threads, b->grid, s);
+        hipError_t ee = hipStreamEndCapture(s, &g);
+        e = le ? (hipError_t)le : ee;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipStreamDestroy(s);
+    if (e != hipSuccess) {
+        b->exec = nullptr;
+        return hip_fail(e, "graph capture of the batch");
+    }
+    return SLOS_OK;
+}
+
+int slos_batch_replay(slos_batch_t b, void *stream)
+{
+    if (!b) return fail(SLOS_ERR_INVALID_ARG, "batch is NULL");
+    if (!b->exec) return fail(SLOS_ERR_INVALID_ARG, "no captured graph: call slos_batch_capture first");
+    hipError_t e = hipGraphLaunch(b->exec, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "graph launch");
+    return SLOS_OK;
+}
+
+} // extern "C"

@@ -200,3 +200,40 @@ int slos_launch_mesh_forward(int m, int batch, const double *phases, void *U, in
 int slos_launch_mesh_backward(int m, int batch, const double *phases, const void *GU, double *gphases, int c64,
                               void *stream);
 
+// ---- batches of independent instances -------------------------------------------
+
+#define SLOS_BATCH_MAX_N 16
+
+// One instance of a batch.  Layer k (1..n) has nleaves[k-1] narrow leaf
+// descriptors starting at record desc_off[k-1]; its photon comes from input
+// mode col[k-1].  U and the outputs live in packed arrays at U_off / out_off
+// (elements).
+struct BatchInst {
+    uint64_t U_off;
+    uint64_t out_off;
+    uint32_t m;
+    uint32_t n;
+    uint32_t desc_off[SLOS_BATCH_MAX_N];
+    uint32_t nleaves[SLOS_BATCH_MAX_N];
+    uint8_t col[SLOS_BATCH_MAX_N];
+};
+
+struct BatchParams {
+    const void *U;              // packed U matrices
+    void *out;                  // packed amplitudes
+    double *sum_p;              // per instance, or NULL
+    const BatchInst *inst;
+    const uint32_t *wg_start;   // workgroup g runs wg_list[wg_start[g] .. wg_start[g+1])
+    const uint32_t *wg_list;
+    const LeafDescNarrow *desc;
+    const uint32_t *pred;
+    const double *lowfac;
+    void *scratch;              // two layer buffers per workgroup
+    uint64_t scratch_stride;    // elements per buffer, slack included
+    const void *vac;            // A_0 = [1]
+    uint32_t lds_wave_bytes;
+};
+
+int slos_launch_batch(const BatchParams &p, int c64, int rr, int threads, int grid, void *stream);
+int slos_prepare_batch_kernels(void);
+

@@ -75,6 +75,14 @@ def lib():
     L.slos_backward.argtypes = [vp, vp, vp, vp, vp]
     L.slos_mesh_unitary.argtypes = [ctypes.c_int, ctypes.c_int, vp, vp, ctypes.c_int, vp]
     L.slos_mesh_backward.argtypes = [ctypes.c_int, ctypes.c_int, vp, vp, vp, ctypes.c_int, vp]
+    L.slos_batch_plan.argtypes = [ctypes.c_int, i32p, i32p, ctypes.c_int, ctypes.POINTER(Options),
+                                  ctypes.POINTER(vp)]
+    L.slos_batch_destroy.argtypes = [vp]
+    L.slos_batch_destroy.restype = None
+    L.slos_batch_offsets.argtypes = [vp, i64p, i64p]
+    L.slos_batch_amplitudes.argtypes = [vp, vp, vp, vp, vp]
+    L.slos_batch_capture.argtypes = [vp, vp, vp, vp]
+    L.slos_batch_replay.argtypes = [vp, vp]
     L.slos_plan_set_timing.argtypes = [vp, ctypes.c_int]
     L.slos_plan_layer_ms.argtypes = [vp, ctypes.POINTER(ctypes.c_float), ctypes.c_int]
     L.slos_last_error.argtypes = []
@@ -82,7 +90,8 @@ def lib():
     for name in ("slos_fock_count", "slos_fock_rank", "slos_fock_unrank", "slos_plan",
                  "slos_plan_ex", "slos_plan_info", "slos_plan_leaf", "slos_amplitudes",
                  "slos_probs", "slos_plan_set_timing", "slos_plan_layer_ms", "slos_backward",
-                 "slos_mesh_unitary", "slos_mesh_backward"):
+                 "slos_mesh_unitary", "slos_mesh_backward", "slos_batch_plan", "slos_batch_offsets",
+                 "slos_batch_amplitudes", "slos_batch_capture", "slos_batch_replay"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -274,6 +283,94 @@ class Plan:
 
     def unrank(self, r: int) -> np.ndarray:
         return fock_unrank(self.m, self.n, r)
+
+
+class Batch:
+    """Many independent (U, input state) instances of uneven size, computed by
+    one kernel launch (optionally replayed from a captured HIP graph).
+
+    U and the amplitudes are packed: instance i's U starts at element
+    u_offsets[i] (row-major m_i x m_i), its amplitudes at out_offsets[i].
+    """
+
+    def __init__(self, input_states, dtype: str = "c64", options: Optional[dict] = None):
+        states = [np.ascontiguousarray(np.asarray(s, dtype=np.int32).reshape(-1)) for s in input_states]
+        self.count = len(states)
+        self.ms = np.array([s.size for s in states], dtype=np.int32)
+        self.ns = np.array([int(s.sum()) for s in states], dtype=np.int32)
+        flat = np.ascontiguousarray(np.concatenate(states)) if states else np.zeros(0, np.int32)
+        if dtype not in ("c64", "c128"):
+            raise ValueError("dtype must be 'c64' or 'c128'")
+        self.dtype = dtype
+        opts = Options()
+        for k, v in (options or {}).items():
+            setattr(opts, k, int(v))
+        self._lib = lib()
+        h = ctypes.c_void_p()
+        i32p = ctypes.POINTER(ctypes.c_int32)
+        _check(self._lib.slos_batch_plan(self.count, self.ms.ctypes.data_as(i32p), flat.ctypes.data_as(i32p),
+                                         SLOS_C64 if dtype == "c64" else SLOS_C128, ctypes.byref(opts),
+                                         ctypes.byref(h)))
+        self._h = h
+        self.u_offsets = np.zeros(self.count + 1, dtype=np.int64)
+        self.out_offsets = np.zeros(self.count + 1, dtype=np.int64)
+        i64p = ctypes.POINTER(ctypes.c_int64)
+        _check(self._lib.slos_batch_offsets(h, self.u_offsets.ctypes.data_as(i64p),
+                                            self.out_offsets.ctypes.data_as(i64p)))
+        self.total_outputs = int(self.out_offsets[-1])
+        self.total_u = int(self.u_offsets[-1])
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.slos_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _cdt(self):
+        import torch
+        return torch.complex64 if self.dtype == "c64" else torch.complex128
+
+    def pack_u(self, Us):
+        """Pack a list of m_i x m_i arrays/tensors into one device tensor."""
+        import torch
+        parts = [torch.as_tensor(np.asarray(u) if not isinstance(u, torch.Tensor) else u).reshape(-1) for u in Us]
+        return torch.cat(parts).to(self._cdt()).cuda().contiguous()
+
+    def _check(self, U, out, sum_p):
+        import torch
+        if U.dtype != self._cdt() or U.numel() != self.total_u or U.device.type != "cuda":
+            raise ValueError("U must be the packed device tensor of the batch")
+        if out.dtype != self._cdt() or out.numel() != self.total_outputs:
+            raise ValueError("out has the wrong dtype or size")
+        if sum_p is not None and (sum_p.dtype != torch.float64 or sum_p.numel() != self.count):
+            raise ValueError("sum_p must be a float64 tensor with one entry per instance")
+
+    def amplitudes(self, U, out=None, sum_p=None, stream=None):
+        import torch
+        if out is None:
+            out = torch.empty(self.total_outputs, dtype=self._cdt(), device=U.device)
+        self._check(U, out, sum_p)
+        _check(self._lib.slos_batch_amplitudes(self._h, U.data_ptr(), out.data_ptr(),
+                                               None if sum_p is None else sum_p.data_ptr(), _stream_ptr(stream)))
+        return out
+
+    def capture(self, U, out, sum_p=None):
+        """Record the batch launch on these buffers into a HIP graph."""
+        self._check(U, out, sum_p)
+        self._bound = (U, out, sum_p)  # the graph keeps raw pointers: keep the tensors alive
+        _check(self._lib.slos_batch_capture(self._h, U.data_ptr(), out.data_ptr(),
+                                            None if sum_p is None else sum_p.data_ptr()))
+
+    def replay(self, stream=None):
+        _check(self._lib.slos_batch_replay(self._h, _stream_ptr(stream)))
+
+    def output(self, out, i):
+        return out[int(self.out_offsets[i]):int(self.out_offsets[i + 1])]
 
 
 def mesh_mzi_count(m: int) -> int:

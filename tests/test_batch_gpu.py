@@ -1,0 +1,98 @@
+"""GPU parity of batched instances (one launch, and its captured HIP graph)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2204_00602_amd import inputs, slos
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def need_gpu():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    slos.lib()
+
+
+def edge_instances():
+    out = []
+    out.append((3, 0, np.zeros(3, np.int32), inputs.haar_unitary(3, 300)))          # vacuum
+    out.append((1, 4, np.array([4], np.int32), np.array([[0.6 + 0.8j]])))            # one mode
+    out.append((5, 4, np.array([2, 0, 2, 0, 0], np.int32), inputs.haar_unitary(5, 301)))  # bunched
+    out.append((2, 2, np.array([1, 1], np.int32), oracle.beam_splitter_rx(math.pi / 2)))   # HOM
+    return out
+
+
+def check_instance(batch, out, i, T, U, dtype, sample=None):
+    m = T.size
+    n = int(T.sum())
+    got = batch.output(out, i).cpu().numpy().astype(np.complex128)
+    M = math.comb(m + n - 1, n)
+    assert got.size == M
+    S = oracle.fock_states(m, n) if (sample is None or M <= sample) else inputs.uniform_fock_states(m, n, sample, 7 + i)
+    ref = oracle.amplitudes(U, T, S)
+    idx = np.array([slos.fock_rank(s) for s in S], dtype=np.int64)
+    a = got[idx]
+    if dtype == "c128":
+        err = np.abs(a - ref) / np.maximum(np.abs(ref), 1.0 / math.sqrt(M))
+        assert err.max() <= 1e-12, (i, err.max())
+    else:
+        P, Pr = np.abs(a) ** 2, np.abs(ref) ** 2
+        err = np.abs(P - Pr) / np.maximum(Pr, 1.0 / M)
+        assert err.max() <= 1e-5, (i, err.max())
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("opts", [None, {"leaf_max": 16, "outputs_per_lane": 1, "block_threads": 64, "grid_blocks": 5},
+                                  {"leaf_max": 300, "outputs_per_lane": 4, "block_threads": 128}])
+def test_batch_matches_oracle(dtype, opts):
+    inst = inputs.batch_instances(40, seed=4) + edge_instances()
+    b = slos.Batch([t for (_, _, t, _) in inst], dtype, options=opts)
+    U = b.pack_u([u for (_, _, _, u) in inst])
+    s = torch.zeros(b.count, dtype=torch.float64, device="cuda")
+    out = b.amplitudes(U, sum_p=s)
+    torch.cuda.synchronize()
+    for i, (m, n, T, Ui) in enumerate(inst):
+        check_instance(b, out, i, T, Ui, dtype, sample=400)
+    sp = s.cpu().numpy()
+    tol = 1e-12 if dtype == "c128" else 1e-6
+    # every U is unitary (the 1x1 one is the phase 0.6+0.8i), so each instance sums to 1
+    assert np.abs(sp - 1.0).max() <= tol
+
+
+def test_batch_graph_replays_follow_new_inputs():
+    inst = inputs.batch_instances(24, seed=9)
+    b = slos.Batch([t for (_, _, t, _) in inst], "c64")
+    U = b.pack_u([u for (_, _, _, u) in inst])
+    out = torch.empty(b.total_outputs, dtype=torch.complex64, device="cuda")
+    s = torch.zeros(b.count, dtype=torch.float64, device="cuda")
+    b.capture(U, out, s)
+    for rep in range(3):
+        # new unitaries written into the bound input buffer, eager work between replays
+        Us = [inputs.haar_unitary(m, 1000 * rep + i) for i, (m, _, _, _) in enumerate(inst)]
+        U.copy_(b.pack_u(Us))
+        eager_out = b.amplitudes(U.clone())
+        torch.cuda.synchronize()
+        b.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out.view(torch.float32), eager_out.view(torch.float32)), rep
+        for i in (0, 7, 23):
+            check_instance(b, out, i, inst[i][2], Us[i], "c64", sample=200)
+        assert np.abs(s.cpu().numpy() - 1.0).max() <= 1e-6
+
+
+def test_config4_sampled_instances():
+    """4096 instances, m in 6..14, n in 2..min(7, m), <= 2 photons per mode, c64."""
+    inst = inputs.batch_instances(4096, seed=4)
+    b = slos.Batch([t for (_, _, t, _) in inst], "c64")
+    U = b.pack_u([u for (_, _, _, u) in inst])
+    s = torch.zeros(b.count, dtype=torch.float64, device="cuda")
+    out = b.amplitudes(U, sum_p=s)
+    torch.cuda.synchronize()
+    assert np.abs(s.cpu().numpy() - 1.0).max() <= 1e-6
+    rng = np.random.default_rng(404)
+    for i in rng.choice(4096, 24, replace=False):
+        check_instance(b, out, int(i), inst[i][2], inst[i][3], "c64", sample=150)

@@ -155,3 +155,21 @@ def test_algorithmic_bytes_formula():
     assert slos.algorithmic_bytes(24, 12, 16) == 2 * b
     N = [math.comb(6 + k - 1, k) for k in range(4)]
     assert slos.algorithmic_bytes(6, 3, 16) == 16 * (sum(N[:3]) + sum(N[1:]))
+
+
+def test_batch_plan_validation():
+    import ctypes
+    L = slos.lib()
+    h = ctypes.c_void_p()
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    ms = np.array([3, 2], np.int32)
+    bad_inputs = [np.array([1, -1, 0, 1, 0], np.int32), np.array([17, 0, 0, 0, 0], np.int32)]
+    for inp in bad_inputs:
+        rc = L.slos_batch_plan(2, ms.ctypes.data_as(i32p), inp.ctypes.data_as(i32p), slos.SLOS_C64, None,
+                               ctypes.byref(h))
+        assert rc == -1 and not h.value
+    ok = np.array([1, 0, 1, 1, 1], np.int32)
+    assert L.slos_batch_plan(0, ms.ctypes.data_as(i32p), ok.ctypes.data_as(i32p), slos.SLOS_C64, None,
+                             ctypes.byref(h)) == -1
+    assert L.slos_batch_plan(2, ms.ctypes.data_as(i32p), ok.ctypes.data_as(i32p), 0, None, ctypes.byref(h)) == -4
+    L.slos_batch_destroy(None)
