@@ -99,17 +99,104 @@ def time_variant(torch, slos, T, U_np, dtype, compensated, steps, warmup):
     return res
 
 
-def cpu_baseline(U_np, T, target_s=15.0):
+def time_batched(torch, slos, steps, warmup, count=4096, seed=4):
+    """4096 uneven instances (m in 6..14, n in 2..min(7, m), <= 2 photons per
+    mode, Haar U each), complex64, one persistent launch replayed from a HIP
+    graph.  Launch options come from the autotuner (cached per device)."""
+    from paper_2204_00602_amd import autotune, inputs
+    inst = inputs.batch_instances(count, seed=seed)
+    states = [t for (_, _, t, _) in inst]
+    Us = [u for (_, _, _, u) in inst]
+    t0 = time.perf_counter()
+    opts = autotune.tune_batch(states, "c64", Us=Us)
+    tune_s = time.perf_counter() - t0
+    b = slos.Batch(states, "c64", options=opts)
+    U = b.pack_u(Us)
+    out = torch.empty(b.total_outputs, dtype=torch.complex64, device="cuda")
+    sum_p = torch.zeros(b.count, dtype=torch.float64, device="cuda")
+    b.capture(U, out, sum_p)
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        b.replay(stream)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        b.replay(stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    alg = sum(slos.algorithmic_bytes(int(mm), int(nn), 8) for (mm, nn, _, _) in inst)
+    dev = float((sum_p - 1.0).abs().max().item())
+    res = {
+        "workload": f"{count} instances, m ~ U{{6..14}}, n ~ U{{2..min(7,m)}}, <=2 photons per mode, "
+                    f"Haar U (seed {seed}), complex64, one persistent launch replayed from a HIP graph",
+        "outputs": b.total_outputs, "ms_per_batch": ms,
+        "amplitudes_per_s": b.total_outputs / (ms * 1e-3),
+        "algorithmic_bytes": alg, "achieved_GBps": alg / (ms * 1e-3) / 1e9,
+        "roofline_frac": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS,
+        "max_abs_sum_p_minus_1": dev, "options": opts, "autotune_s": tune_s,
+    }
+    b.close()
+    return res
+
+
+def time_gradient(torch, slos, steps, warmup, batch=64, m=12, n=6, targets=200):
+    """Gradient of sum_b sum_S (P_b(S) - P_t(S))^2 over 200 seeded targets with
+    respect to the 132 phases of a Clements mesh (m=12, n=6), for 64 phase sets:
+    mesh -> amplitudes (complex64) -> loss -> adjoint -> mesh adjoint."""
+    from paper_2204_00602_amd import autograd as ag, inputs
+    k = slos.mesh_mzi_count(m)
+    T = inputs.first_modes_input(m, n)
+    phases = torch.from_numpy(inputs.mesh_phases(batch, k, 5)).cuda()
+    teacher = torch.from_numpy(inputs.mesh_phases(batch, k, 55)).cuda()
+    idx = torch.tensor([slos.fock_rank(s) for s in inputs.uniform_fock_states(m, n, targets, 505)],
+                       device="cuda")
+    plans = [slos.Plan(T, "c64", keep_layers=True) for _ in range(batch)]
+    with torch.no_grad():
+        Ut = slos.mesh_unitary(teacher, m, "c64")
+        p_t = torch.stack([plans[b].probs(Ut[b].contiguous())[idx] for b in range(batch)]).to(torch.float64)
+
+    def step():
+        ph = phases.clone().requires_grad_(True)
+        U = ag.mesh(ph, m, "c64")
+        loss = 0.0
+        for b in range(batch):
+            a = ag.amplitudes(plans[b], U[b].contiguous())
+            loss = loss + (((a[idx].abs() ** 2).to(torch.float64) - p_t[b]) ** 2).sum()
+        loss.backward()
+        return ph.grad
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        g = step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    finite = bool(torch.isfinite(g).all().item())
+    for p in plans:
+        p.close()
+    return {
+        "workload": f"Clements mesh m={m} ({k} MZIs, {2 * k} phases), n={n}, batch {batch} phase sets, "
+                    f"{targets} seeded targets, complex64 forward + adjoint, torch.autograd",
+        "ms_per_batch": ms, "gradient_evals_per_s": batch / (ms * 1e-3), "finite": finite,
+    }
+
+
+def cpu_baseline(U_np, T, target_s=20.0):
     """The oracle, untuned, on a bounded sample of the workload's outputs."""
     import oracle
     from paper_2204_00602_amd import inputs
     cores = oracle.num_threads()
-    calib = inputs.uniform_fock_states(M_MODES, N_PHOTONS, 4 * cores, SAMPLE_SEED)
+    calib = inputs.uniform_fock_states(M_MODES, N_PHOTONS, 32 * cores, SAMPLE_SEED)
     t0 = time.perf_counter()
     oracle.amplitudes(U_np, T, calib)
     dt = time.perf_counter() - t0
     per = dt / len(calib)
-    count = int(min(max(target_s / max(per, 1e-9), 64), 200_000))
+    count = int(min(max(target_s / max(per, 1e-9), 64), 2_000_000))
     sample = inputs.uniform_fock_states(M_MODES, N_PHOTONS, count, SAMPLE_SEED + 1)
     t0 = time.perf_counter()
     oracle.amplitudes(U_np, T, sample)
@@ -131,6 +218,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the batched and gradient workloads")
     ap.add_argument("--only", choices=["c64comp", "c64", "c128"], default=None,
                     help="time one variant only (for profiling runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -138,8 +227,8 @@ def main():
                          "profile of this command holds the counters of a copy of known size")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(the multi-GPU sharding is described in DESIGN.md, not built)", file=sys.stderr)
+        print(f"bench.py: this benchmark runs on one GPU; --gpus {args.gpus} is not supported "
+              "(sharding across GPUs is not built)", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -228,6 +317,14 @@ def main():
         for k in results:
             if k != "c128":
                 line["variants"][k]["speedup_over_c128"] = results["c128"]["ms_per_step"] / results[k]["ms_per_step"]
+    if not args.no_extras and not args.only:
+        print("[bench] batched workload: 4096 uneven instances (tuning, then graph replays)",
+              file=sys.stderr, flush=True)
+        line["batched"] = time_batched(torch, slos, args.steps, args.warmup)
+        print(f"[bench] batched: {line['batched']['ms_per_batch']:.3f} ms/batch", file=sys.stderr, flush=True)
+        print("[bench] gradient workload: mesh m=12 n=6, 64 phase sets", file=sys.stderr, flush=True)
+        line["gradient"] = time_gradient(torch, slos, max(3, args.steps // 4), 1)
+        print(f"[bench] gradient: {line['gradient']['ms_per_batch']:.3f} ms/batch", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(U, T)

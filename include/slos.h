@@ -53,8 +53,16 @@ extern "C" {
 /* ---- plan flags ---------------------------------------------------------- */
 #define SLOS_C64 0x1          /* complex64 recurrence, fp32 probabilities          */
 #define SLOS_C128 0x2         /* complex128 recurrence, fp64 probabilities         */
-#define SLOS_COMPENSATED 0x100 /* c64 only: error-free (two-sum/two-product)
-                                  accumulation on layers k >= comp_from_layer      */
+#define SLOS_COMPENSATED 0x100 /* c64 only: compensated accumulation on layers
+                                  k >= comp_from_layer.  Each FMA's rounding error
+                                  is recovered exactly (the two-sum of the running
+                                  sum and the product, made exact by starting the
+                                  sum at a power-of-two bias >= 4 sum|u_j v_j|)
+                                  and summed in a second float; 4 flops per real
+                                  product                                          */
+#define SLOS_COMP_KNUTH 0x800  /* with SLOS_COMPENSATED: FMA two-product plus
+                                  Knuth's branch-free two-sum instead (10 flops per
+                                  real product; same error order)                  */
 #define SLOS_KEEP_LAYERS 0x200 /* keep A_0..A_{n-1} on the device (for backward)   */
 #define SLOS_HOST_ONLY 0x400   /* build the host tables only; no device memory;
                                   for slos_plan_info / slos_plan_leaf inspection  */
@@ -66,13 +74,19 @@ typedef struct slos_plan_s *slos_plan_t;
 
 /* Tuning options; a zero field takes its default. */
 typedef struct slos_options {
-    int32_t leaf_max;        /* max states per leaf tile (default 8192, <= 65536)    */
-    int32_t comp_from_layer; /* first compensated layer (default n - 1, min 1)       */
+    int32_t leaf_max;        /* max states per leaf tile, <= 65536 (default 8192 for
+                                c64, 4096 for c128, 1024 with SLOS_KEEP_LAYERS); a
+                                small layer uses smaller leaves so that it still
+                                spreads over ~2048 workgroups                        */
+    int32_t comp_from_layer; /* first compensated layer (default 1: every layer)     */
     int32_t block_threads;   /* threads per workgroup: 64, 128, 256 (default 256)    */
     int32_t grid_blocks;     /* cap on workgroups per layer launch (default 2048)    */
-    int32_t outputs_per_lane;/* 1, 2 or 4 outputs per lane per tile (default 4 for c64, 2 for c128)      */
-    int32_t xcd_chunk;       /* consecutive leaves dealt to one XCD at a time (default 512) */
-    int32_t ticket_leaves;   /* consecutive leaves a wave takes per work ticket (default 2) */
+    int32_t outputs_per_lane;/* 1, 2 or 4 outputs per lane per tile (default 4 for
+                                c64, 2 for compensated c64 and for c128)             */
+    int32_t xcd_chunk;       /* consecutive leaves dealt to one XCD at a time
+                                (default 128; fewer when a layer has few leaves)    */
+    int32_t ticket_leaves;   /* consecutive leaves a workgroup takes per work ticket
+                                (default 4)                                          */
 } slos_options_t;
 
 /* ---- Fock-space arithmetic (host only; no device needed) ------------------ */
@@ -91,8 +105,8 @@ int slos_fock_unrank(int m, int n, int64_t rank, int32_t *state);
 /*
  * Build a plan for m modes (1..255) and the input Fock state `input_state`
  * (m int32 occupations, all >= 0, summing to n <= 32).  `flags` holds exactly
- * one of SLOS_C64 / SLOS_C128 plus optional SLOS_COMPENSATED (C64 only),
- * SLOS_KEEP_LAYERS, SLOS_HOST_ONLY.  Checks that C(m+n-1, n) and all buffers
+ * one of SLOS_C64 / SLOS_C128 plus optional SLOS_COMPENSATED (C64 only; with
+ * SLOS_COMP_KNUTH), SLOS_KEEP_LAYERS, SLOS_HOST_ONLY.  Checks that C(m+n-1, n) and all buffers
  * fit, builds the photon list i_1 <= .. <= i_n (Section 2: photons are
  * creation operators, so their order does not change the result), the
  * binomial table, the leaf decomposition of every layer and the inner tables,

@@ -35,8 +35,10 @@ __device__ __forceinline__ void cmac(C &acc, const C u, const C v)
     acc.y = fma_(u.y, v.x, acc.y);
 }
 
-// Error-free accumulation of a*b into (s, c): the product's rounding error
-// comes from an FMA, the sum's from Knuth's two-sum; both go to c.
+// ---- compensated complex64 accumulation ---------------------------------
+// SLOS_COMP_TWOSUM: every real product a*b is split exactly into p + pe with an
+// FMA (two-product) and added to the running sum s with Knuth's two-sum; both
+// rounding errors go to a second float c.  Ten operations per product.
 __device__ __forceinline__ void acc_exact(float &s, float &c, float a, float b)
 {
 #pragma clang fp contract(off)
@@ -61,23 +63,72 @@ __device__ __forceinline__ void cmac_comp(CompAcc &a, const float2 u, const floa
     acc_exact(a.s.y, a.c.y, u.y, v.x);
 }
 
-template <typename T, bool COMP> struct Acc;
-template <typename T> struct Acc<T, false> {
+// Default compensated mode: biased FMA accumulation.  The sum starts at a
+// power of two sigma >= 4 * sum_i |a_i b_i| (a bound from the operands, taken
+// before the sum).  Every partial sum then stays within [3/4, 5/4] sigma, so
+// for t = fma(a, b, s) the difference s - t is exact (Sterbenz) and
+// fma(a, b, s - t) is the FMA's rounding error, correct to one rounding of a
+// number below ulp(sigma).  Those errors go to a second float c, and the
+// result is (s - sigma) + c, where s - sigma is exact again.  The error-free
+// transformation is the two-sum of s and a*b computed with the FMA; the bias
+// makes its short form exact.  Four operations per real product; the error is
+// within one rounding of the result plus O(terms * 2^-46 * sigma).
+__device__ __forceinline__ void acc_biased(float &s, float &c, float a, float b)
+{
+#pragma clang fp contract(off)
+    const float t = __builtin_fmaf(a, b, s);
+    const float d = s - t;
+    c = c + __builtin_fmaf(a, b, d);
+    s = t;
+}
+
+// 8 * 2^floor(log2 b) (> 4b), at least 2^-117
+__device__ __forceinline__ float bias_for(float b)
+{
+    const float f = __uint_as_float(__float_as_uint(b) & 0x7F800000u);
+    return 8.0f * fmaxf(f, 0x1p-120f);
+}
+
+template <typename T, int COMP> struct Acc;
+template <typename T> struct Acc<T, SLOS_COMP_NONE> {
     using C = typename Cx<T>::type;
     C a;
     __device__ __forceinline__ void zero() { a = C{0, 0}; }
+    __device__ __forceinline__ void start(float) {}
     __device__ __forceinline__ void mac(const C u, const C v) { cmac(a, u, v); }
     __device__ __forceinline__ C value() const { return a; }
     __device__ __forceinline__ double re() const { return (double)a.x; }
     __device__ __forceinline__ double im() const { return (double)a.y; }
 };
-template <> struct Acc<float, true> {
+template <> struct Acc<float, SLOS_COMP_TWOSUM> {
     CompAcc a;
     __device__ __forceinline__ void zero() { a.s = float2{0.f, 0.f}; a.c = float2{0.f, 0.f}; }
+    __device__ __forceinline__ void start(float) {}
     __device__ __forceinline__ void mac(const float2 u, const float2 v) { cmac_comp(a, u, v); }
     __device__ __forceinline__ float2 value() const { return float2{a.s.x + a.c.x, a.s.y + a.c.y}; }
     __device__ __forceinline__ double re() const { return (double)a.s.x + (double)a.c.x; }
     __device__ __forceinline__ double im() const { return (double)a.s.y + (double)a.c.y; }
+};
+template <> struct Acc<float, SLOS_COMP_BIASED> {
+    float sr, si, cr, ci, sigma;
+    __device__ __forceinline__ void zero() { sr = si = cr = ci = sigma = 0.f; }
+    // b >= sum over the terms of (|u.x| + |u.y|)(|v.x| + |v.y|)
+    __device__ __forceinline__ void start(float b)
+    {
+        sigma = bias_for(b);
+        sr = sigma;
+        si = sigma;
+    }
+    __device__ __forceinline__ void mac(const float2 u, const float2 v)
+    {
+        acc_biased(sr, cr, u.x, v.x);
+        acc_biased(sr, cr, -u.y, v.y);
+        acc_biased(si, ci, u.x, v.y);
+        acc_biased(si, ci, u.y, v.x);
+    }
+    __device__ __forceinline__ float2 value() const { return float2{(sr - sigma) + cr, (si - sigma) + ci}; }
+    __device__ __forceinline__ double re() const { return (double)(sr - sigma) + (double)cr; }
+    __device__ __forceinline__ double im() const { return (double)(si - sigma) + (double)ci; }
 };
 
 // cache-policy operand of the global-to-LDS copy: bit 1 = non-temporal
@@ -229,96 +280,125 @@ __device__ __forceinline__ const C *stage_low(const C *__restrict__ X, const Lea
 }
 
 // One tile: RT outputs per lane, x = t0 + i*64 + lane clamped to the leaf so
-// every load is in bounds.  All block loads (up to HS high groups) and table
-// loads (up to CS low terms) of the tile are issued before any is used.
-template <typename T, int MODE, bool COMP, int RT, bool WIDE>
-__device__ __forceinline__ void tile(const LayerParams &p, const DescRegs<WIDE> &dr, const Leaf &L,
-                                     const typename Cx<T>::type *__restrict__ X,
-                                     const typename Cx<T>::type *u_lds, const typename Cx<T>::type *lowbuf,
-                                     uint32_t t0, int lane, double &psum)
+// every load is in bounds.  tile_load issues all block loads (up to HS high
+// groups) and table loads (up to CS low terms) of the tile; tile_compute uses
+// them.
+constexpr int kHS = 8;
+constexpr int kCS = 8;
+
+template <typename T, int RT>
+struct TileIn {
+    typename Cx<T>::type v[kHS][RT];
+    uint32_t e[kCS][RT];
+    double lf[RT];
+    uint32_t xc[RT];
+    uint32_t off[RT];
+};
+
+template <typename T, int MODE, int RT, bool WIDE>
+__device__ __forceinline__ void tile_load(TileIn<T, RT> &in, const LayerParams &p, const DescRegs<WIDE> &dr,
+                                          const Leaf &L, const typename Cx<T>::type *__restrict__ X, uint32_t t0,
+                                          int lane)
 {
     using C = typename Cx<T>::type;
-    constexpr int HS = 8;
-    constexpr int CS = 8;
-    uint32_t xc[RT], off[RT];
-    bool ok[RT];
 #pragma unroll
     for (int i = 0; i < RT; ++i) {
         const uint32_t x = t0 + (uint32_t)(i * 64 + lane);
-        ok[i] = x < L.size;
-        xc[i] = ok[i] ? x : L.size - 1u;
-        off[i] = xc[i] * (uint32_t)sizeof(C);
+        in.xc[i] = x < L.size ? x : L.size - 1u;
+        in.off[i] = in.xc[i] * (uint32_t)sizeof(C);
     }
     const uint32_t *__restrict__ pred = p.pred + L.pred_off;
-
-    // ---- issue
-    C v[HS][RT];
-    uint32_t e[CS][RT];
-    double lf[RT];
 #pragma unroll
-    for (int g = 0; g < HS; ++g) {
+    for (int g = 0; g < kHS; ++g) {
         if (g < L.nh) {
             const C *Xb = X + group_base<WIDE>(dr, L, g);
 #pragma unroll
-            for (int i = 0; i < RT; ++i) v[g][i] = ld_off<C>(Xb, off[i]);
+            for (int i = 0; i < RT; ++i) in.v[g][i] = ld_off<C>(Xb, in.off[i]);
         }
     }
 #pragma unroll
-    for (int c = 0; c < CS; ++c) {
+    for (int c = 0; c < kCS; ++c) {
         if (c < L.cmax) {
 #pragma unroll
-            for (int i = 0; i < RT; ++i) e[c][i] = ld_off<uint32_t>(pred, ((uint32_t)c * L.size + xc[i]) * 4u);
+            for (int i = 0; i < RT; ++i) in.e[c][i] = ld_off<uint32_t>(pred, ((uint32_t)c * L.size + in.xc[i]) * 4u);
         }
     }
     if (MODE != SLOS_MODE_MID) {
 #pragma unroll
-        for (int i = 0; i < RT; ++i) lf[i] = ld_off<double>(p.lowfac + L.fac_off, xc[i] * 8u);
+        for (int i = 0; i < RT; ++i) in.lf[i] = ld_off<double>(p.lowfac + L.fac_off, in.xc[i] * 8u);
     }
+}
+
+template <typename T, int MODE, int COMP, int RT, bool WIDE>
+__device__ __forceinline__ void tile_compute(const TileIn<T, RT> &in, const LayerParams &p, const DescRegs<WIDE> &dr,
+                                             const Leaf &L, const typename Cx<T>::type *__restrict__ X,
+                                             const typename Cx<T>::type *u_lds, const float *ul1_lds,
+                                             const typename Cx<T>::type *lowbuf, uint32_t t0, int lane, double &psum)
+{
+    using C = typename Cx<T>::type;
+    const uint32_t *__restrict__ pred = p.pred + L.pred_off;
+
+    // Visit every term (output i, mode j, predecessor value) of the tile:
+    // high groups from registers (or, past kHS groups, straight from memory),
+    // low terms from the staged block.
+    auto terms = [&](auto &&f) {
+#pragma unroll
+        for (int g = 0; g < kHS; ++g) {
+            if (g < L.nh) {
+                const int j = group_mode<WIDE>(dr, g);
+#pragma unroll
+                for (int i = 0; i < RT; ++i) f(i, j, in.v[g][i]);
+            }
+        }
+        for (int g = kHS; g < L.nh; ++g) {  // leaves with more than kHS high groups
+            const C *Xb = X + group_base<WIDE>(dr, L, g);
+            const int j = group_mode<WIDE>(dr, g);
+#pragma unroll
+            for (int i = 0; i < RT; ++i) f(i, j, ld_off<C>(Xb, in.off[i]));
+        }
+#pragma unroll
+        for (int c = 0; c < kCS; ++c) {
+            if (c < L.cmax) {
+#pragma unroll
+                for (int i = 0; i < RT; ++i) f(i, (int)(in.e[c][i] >> 24), lowbuf[in.e[c][i] & SLOS_PRED_MASK]);
+            }
+        }
+        for (int c = kCS; c < L.cmax; ++c) {  // inner states with more than kCS low terms
+#pragma unroll
+            for (int i = 0; i < RT; ++i) {
+                const uint32_t ec = ld_off<uint32_t>(pred, ((uint32_t)c * L.size + in.xc[i]) * 4u);
+                f(i, (int)(ec >> 24), lowbuf[ec & SLOS_PRED_MASK]);
+            }
+        }
+    };
 
     // ---- multiply-add
     Acc<T, COMP> acc[RT];
 #pragma unroll
     for (int i = 0; i < RT; ++i) acc[i].zero();
+    if constexpr (COMP == SLOS_COMP_BIASED) {
+        float bnd[RT];
 #pragma unroll
-    for (int g = 0; g < HS; ++g) {
-        if (g < L.nh) {
-            const C u = u_lds[group_mode<WIDE>(dr, g)];
+        for (int i = 0; i < RT; ++i) bnd[i] = 0.f;
+        terms([&](int i, int j, const C x) { bnd[i] = __builtin_fmaf(ul1_lds[j], fabsf(x.x) + fabsf(x.y), bnd[i]); });
 #pragma unroll
-            for (int i = 0; i < RT; ++i) acc[i].mac(u, v[g][i]);
-        }
+        for (int i = 0; i < RT; ++i) acc[i].start(bnd[i]);
+        // read the low terms from LDS again rather than keep them in registers
+        asm volatile("" ::: "memory");
     }
-    for (int g = HS; g < L.nh; ++g) {  // leaves with more than HS high groups
-        const C *Xb = X + group_base<WIDE>(dr, L, g);
-        const C u = u_lds[group_mode<WIDE>(dr, g)];
-#pragma unroll
-        for (int i = 0; i < RT; ++i) acc[i].mac(u, ld_off<C>(Xb, off[i]));
-    }
-#pragma unroll
-    for (int c = 0; c < CS; ++c) {
-        if (c < L.cmax) {
-#pragma unroll
-            for (int i = 0; i < RT; ++i) acc[i].mac(u_lds[e[c][i] >> 24], lowbuf[e[c][i] & SLOS_PRED_MASK]);
-        }
-    }
-    for (int c = CS; c < L.cmax; ++c) {  // inner states with more than CS low terms
-#pragma unroll
-        for (int i = 0; i < RT; ++i) {
-            const uint32_t ec = ld_off<uint32_t>(pred, ((uint32_t)c * L.size + xc[i]) * 4u);
-            acc[i].mac(u_lds[ec >> 24], lowbuf[ec & SLOS_PRED_MASK]);
-        }
-    }
+    terms([&](int i, int j, const C x) { acc[i].mac(u_lds[j], x); });
 
     // ---- store
 #pragma unroll
     for (int i = 0; i < RT; ++i) {
-        if (!ok[i]) continue;
-        const uint64_t o = L.out_base + xc[i];
+        if (t0 + (uint32_t)(i * 64 + lane) >= L.size) continue;
+        const uint64_t o = L.out_base + in.xc[i];
         if (MODE == SLOS_MODE_MID) {
             const C a = acc[i].value();
             __builtin_nontemporal_store(a.x, &((T *)p.Y)[2 * o]);
             __builtin_nontemporal_store(a.y, &((T *)p.Y)[2 * o + 1]);
         } else {
-            const double f = L.fac_hi * lf[i];
+            const double f = L.fac_hi * in.lf[i];
             const double ar = acc[i].re() * f;
             const double ai = acc[i].im() * f;
             const double pr = ar * ar + ai * ai;
@@ -331,6 +411,17 @@ __device__ __forceinline__ void tile(const LayerParams &p, const DescRegs<WIDE> 
             }
         }
     }
+}
+
+template <typename T, int MODE, int COMP, int RT, bool WIDE>
+__device__ __forceinline__ void tile(const LayerParams &p, const DescRegs<WIDE> &dr, const Leaf &L,
+                                     const typename Cx<T>::type *__restrict__ X,
+                                     const typename Cx<T>::type *u_lds, const float *ul1_lds,
+                                     const typename Cx<T>::type *lowbuf, uint32_t t0, int lane, double &psum)
+{
+    TileIn<T, RT> in;
+    tile_load<T, MODE, RT, WIDE>(in, p, dr, L, X, t0, lane);
+    tile_compute<T, MODE, COMP, RT, WIDE>(in, p, dr, L, X, u_lds, ul1_lds, lowbuf, t0, lane, psum);
 }
 
 // Stage the low block with all waves of the workgroup: 1 KiB chunk c of the
@@ -358,11 +449,12 @@ __device__ __forceinline__ const C *stage_low_team(const C *__restrict__ X, cons
 // come from per-XCD ticket counters in batches of p.ticket_leaves, so the
 // workgroups resident on an XCD work on neighbouring leaves of the colex order
 // and share that XCD's L2.
-template <typename T, int MODE, bool COMP, int RR, bool WIDE>
+template <typename T, int MODE, int COMP, int RR, bool WIDE>
 __global__ __launch_bounds__(256) void layer_kernel(LayerParams p)
 {
     using C = typename Cx<T>::type;
     __shared__ C u_lds[256];
+    __shared__ float ul1_lds[COMP == SLOS_COMP_BIASED ? 256 : 1];  // |Re u_j| + |Im u_j|
     __shared__ uint32_t ticket_slot[2];
     const C *__restrict__ X = (const C *)p.X;
     const C *__restrict__ Um = (const C *)p.U;
@@ -370,6 +462,7 @@ __global__ __launch_bounds__(256) void layer_kernel(LayerParams p)
         C v{0, 0};
         if (j < p.m) v = Um[(size_t)j * p.m + p.col];
         u_lds[j] = v;
+        if (COMP == SLOS_COMP_BIASED) ul1_lds[j] = (float)(fabs(v.x) + fabs(v.y));
     }
 
     const int lane = threadIdx.x & 63;
@@ -423,10 +516,11 @@ __global__ __launch_bounds__(256) void layer_kernel(LayerParams p)
         double psum = 0.0;
         const uint32_t full = L.size / (64u * RR);              // full tiles
         for (uint32_t t = (uint32_t)wv; t < full; t += (uint32_t)W)
-            tile<T, MODE, COMP, RR, WIDE>(p, cur, L, X, u_lds, lowbuf, t * 64u * RR, lane, psum);
+            tile<T, MODE, COMP, RR, WIDE>(p, cur, L, X, u_lds, ul1_lds, lowbuf, t * 64u * RR, lane, psum);
         const uint32_t rows = (L.size - full * 64u * RR + 63u) / 64u;  // leftover rows of 64
         for (uint32_t r = (uint32_t)wv; r < rows; r += (uint32_t)W)
-            tile<T, MODE, COMP, 1, WIDE>(p, cur, L, X, u_lds, lowbuf, full * 64u * RR + r * 64u, lane, psum);
+            tile<T, MODE, COMP, 1, WIDE>(p, cur, L, X, u_lds, ul1_lds, lowbuf, full * 64u * RR + r * 64u, lane,
+                                         psum);
         if (MODE != SLOS_MODE_MID) {
             // one FP64 partial per (leaf, wave), summed later in a fixed order
 #pragma unroll
@@ -499,16 +593,18 @@ __global__ __launch_bounds__(256) void batch_kernel(BatchParams bp)
                 const uint32_t full = L.size / (64u * RR);
                 if (k == n) {
                     for (uint32_t t = 0; t < full; ++t)
-                        tile<T, SLOS_MODE_AMPL, false, RR, false>(lp, d, L, X, u_lds, lowbuf, t * 64u * RR, lane,
-                                                                 psum);
+                        tile<T, SLOS_MODE_AMPL, SLOS_COMP_NONE, RR, false>(lp, d, L, X, u_lds, nullptr, lowbuf,
+                                                                          t * 64u * RR, lane, psum);
                     for (uint32_t t0 = full * 64u * RR; t0 < L.size; t0 += 64u)
-                        tile<T, SLOS_MODE_AMPL, false, 1, false>(lp, d, L, X, u_lds, lowbuf, t0, lane, psum);
+                        tile<T, SLOS_MODE_AMPL, SLOS_COMP_NONE, 1, false>(lp, d, L, X, u_lds, nullptr, lowbuf, t0,
+                                                                         lane, psum);
                 } else {
                     for (uint32_t t = 0; t < full; ++t)
-                        tile<T, SLOS_MODE_MID, false, RR, false>(lp, d, L, X, u_lds, lowbuf, t * 64u * RR, lane,
-                                                                psum);
+                        tile<T, SLOS_MODE_MID, SLOS_COMP_NONE, RR, false>(lp, d, L, X, u_lds, nullptr, lowbuf,
+                                                                         t * 64u * RR, lane, psum);
                     for (uint32_t t0 = full * 64u * RR; t0 < L.size; t0 += 64u)
-                        tile<T, SLOS_MODE_MID, false, 1, false>(lp, d, L, X, u_lds, lowbuf, t0, lane, psum);
+                        tile<T, SLOS_MODE_MID, SLOS_COMP_NONE, 1, false>(lp, d, L, X, u_lds, nullptr, lowbuf, t0,
+                                                                        lane, psum);
                 }
                 __builtin_amdgcn_s_waitcnt(0);
                 __builtin_amdgcn_wave_barrier();
@@ -581,7 +677,7 @@ __global__ void vacuum_kernel(void *out, int mode, double *sum_p)
     }
 }
 
-template <typename T, int MODE, bool COMP, int RR, bool WIDE>
+template <typename T, int MODE, int COMP, int RR, bool WIDE>
 hipError_t launch_one(const LayerParams &p, const LayerLaunch &l, hipStream_t s)
 {
     static bool attr_set = false;  // per instantiation; first call per process
@@ -597,7 +693,8 @@ hipError_t launch_one(const LayerParams &p, const LayerLaunch &l, hipStream_t s)
     return hipGetLastError();
 }
 
-template <typename T, int MODE, bool COMP, bool WIDE>
+
+template <typename T, int MODE, int COMP, bool WIDE>
 hipError_t launch_rr(const LayerParams &p, const LayerLaunch &l, hipStream_t s)
 {
     switch (l.rr) {
@@ -607,13 +704,13 @@ hipError_t launch_rr(const LayerParams &p, const LayerLaunch &l, hipStream_t s)
     }
 }
 
-template <typename T, int MODE, bool COMP>
+template <typename T, int MODE, int COMP>
 hipError_t launch_wide(const LayerParams &p, const LayerLaunch &l, hipStream_t s)
 {
     return l.wide ? launch_rr<T, MODE, COMP, true>(p, l, s) : launch_rr<T, MODE, COMP, false>(p, l, s);
 }
 
-template <typename T, bool COMP>
+template <typename T, int COMP>
 hipError_t launch_mode(const LayerParams &p, const LayerLaunch &l, hipStream_t s)
 {
     switch (l.mode) {
@@ -629,10 +726,11 @@ int slos_launch_layer(const LayerParams &p, const LayerLaunch &l, void *stream)
 {
     hipStream_t s = (hipStream_t)stream;
     if (l.c64) {
-        if (l.compensated) return (int)launch_mode<float, true>(p, l, s);
-        return (int)launch_mode<float, false>(p, l, s);
+        if (l.compensated == SLOS_COMP_BIASED) return (int)launch_mode<float, SLOS_COMP_BIASED>(p, l, s);
+        if (l.compensated == SLOS_COMP_TWOSUM) return (int)launch_mode<float, SLOS_COMP_TWOSUM>(p, l, s);
+        return (int)launch_mode<float, SLOS_COMP_NONE>(p, l, s);
     }
-    return (int)launch_mode<double, false>(p, l, s);
+    return (int)launch_mode<double, SLOS_COMP_NONE>(p, l, s);
 }
 
 int slos_launch_reduce(const double *partials, int64_t count, double *stage, double *out, void *stream)

@@ -230,11 +230,11 @@ struct slos_plan_s {
     }
 
     // Leaves of layer k: split F(j+1, K) by the occupation of mode j (blocks
-    // t_j = 0, 1, .., K in colex order) until a block holds <= leaf_max states.
-    void gen_leaves(int k, int j, int K, std::vector<uint8_t> &hm, std::vector<LeafRec> &out)
+    // t_j = 0, 1, .., K in colex order) until a block holds <= cap states.
+    void gen_leaves(int k, int j, int K, uint64_t cap, std::vector<uint8_t> &hm, std::vector<LeafRec> &out)
     {
         uint64_t size = B(j + K, K);
-        if (K == 0 || j == 0 || size <= (uint64_t)opts.leaf_max) {
+        if (K == 0 || j == 0 || size <= cap) {
             LeafRec L{};
             L.q = (uint8_t)(j + 1);
             L.K = (uint8_t)K;
@@ -263,7 +263,7 @@ struct slos_plan_s {
         }
         for (int s = 0; s <= K; ++s) {
             for (int c = 0; c < s; ++c) hm.push_back((uint8_t)j);
-            gen_leaves(k, j - 1, K - s, hm, out);
+            gen_leaves(k, j - 1, K - s, cap, hm, out);
             for (int c = 0; c < s; ++c) hm.pop_back();
         }
     }
@@ -496,25 +496,32 @@ int slos_plan_ex(int m, int n, const int32_t *input_state, int flags, const slos
         return fail(SLOS_ERR_INVALID_ARG, "n = %d outside [0, %d]", n, SLOS_MAX_PHOTONS);
     int rc = check_state(m, n, input_state, "input_state");
     if (rc) return rc;
-    const int known = SLOS_C64 | SLOS_C128 | SLOS_COMPENSATED | SLOS_KEEP_LAYERS | SLOS_HOST_ONLY;
+    const int known = SLOS_C64 | SLOS_C128 | SLOS_COMPENSATED | SLOS_COMP_KNUTH | SLOS_KEEP_LAYERS | SLOS_HOST_ONLY;
     if (flags & ~known) return fail(SLOS_ERR_INVALID_ARG, "unknown flag bits 0x%x", flags & ~known);
     int dt = flags & (SLOS_C64 | SLOS_C128);
     if (dt != SLOS_C64 && dt != SLOS_C128)
         return fail(SLOS_ERR_DTYPE, "flags must hold exactly one of SLOS_C64, SLOS_C128");
     if ((flags & SLOS_COMPENSATED) && dt != SLOS_C64)
         return fail(SLOS_ERR_DTYPE, "SLOS_COMPENSATED applies to SLOS_C64 plans only");
+    if ((flags & SLOS_COMP_KNUTH) && !(flags & SLOS_COMPENSATED))
+        return fail(SLOS_ERR_INVALID_ARG, "SLOS_COMP_KNUTH needs SLOS_COMPENSATED");
     int64_t M;
     if ((rc = slos_fock_count(m, n, &M))) return rc;
 
     slos_options_t o{};
     if (opts) o = *opts;
-    if (o.leaf_max == 0) o.leaf_max = (flags & SLOS_KEEP_LAYERS) ? 1024 : 8192;
-    if (o.comp_from_layer == 0) o.comp_from_layer = std::max(1, n - 1);
+    // defaults: the fastest settings of a coordinate-descent search at
+    // m=24, n=12 on gfx950 (a c128 low block of an 8192-state leaf takes
+    // enough LDS to halve the resident workgroups, hence the smaller leaves)
+    if (o.leaf_max == 0) o.leaf_max = (flags & SLOS_KEEP_LAYERS) ? 1024 : (dt == SLOS_C64 ? 8192 : 4096);
+    if (o.comp_from_layer == 0) o.comp_from_layer = 1;
     if (o.block_threads == 0) o.block_threads = 256;
     if (o.grid_blocks == 0) o.grid_blocks = 2048;
-    if (o.outputs_per_lane == 0) o.outputs_per_lane = dt == SLOS_C64 ? 4 : 2;
-    if (o.xcd_chunk == 0) o.xcd_chunk = 512;
-    if (o.ticket_leaves == 0) o.ticket_leaves = 2;
+    // compensated tiles hold five floats per output: two outputs per lane keep
+    // three waves per SIMD
+    if (o.outputs_per_lane == 0) o.outputs_per_lane = (dt == SLOS_C64 && !(flags & SLOS_COMPENSATED)) ? 4 : 2;
+    if (o.xcd_chunk == 0) o.xcd_chunk = 128;
+    if (o.ticket_leaves == 0) o.ticket_leaves = 4;
     if (o.ticket_leaves < 1 || o.ticket_leaves > 4096)
         return fail(SLOS_ERR_INVALID_ARG, "ticket_leaves = %d outside [1, 4096]", o.ticket_leaves);
     if (o.xcd_chunk < 1 || o.xcd_chunk > (1 << 24))
@@ -560,8 +567,12 @@ int slos_plan_ex(int m, int n, const int32_t *input_state, int flags, const slos
         p->leaves.resize(n + 1);
         p->low_max.assign(n + 1, 0);
         for (int k = 1; k <= n; ++k) {
+            // small layers get smaller leaves so that they still spread over
+            // about SLOS_TARGET_LEAVES workgroups
+            const uint64_t cap = std::min<uint64_t>((uint64_t)o.leaf_max,
+                                                    std::max<uint64_t>(SLOS_MIN_LEAF, p->Nk[k] / SLOS_TARGET_LEAVES));
             std::vector<uint8_t> hm;
-            p->gen_leaves(k, m - 1, k, hm, p->leaves[k]);
+            p->gen_leaves(k, m - 1, k, cap, hm, p->leaves[k]);
             for (const LeafRec &L : p->leaves[k])
                 p->low_max[k] = std::max(p->low_max[k], p->types[L.tab].low_size);
         }
@@ -849,7 +860,9 @@ static int run_forward(slos_plan_t p, const void *U, void *out, double *sum_p, v
         LayerLaunch ll{};
         ll.c64 = p->c64;
         ll.mode = k == n ? last_mode : SLOS_MODE_MID;
-        ll.compensated = p->comp && k >= p->opts.comp_from_layer;
+        ll.compensated = (p->comp && k >= p->opts.comp_from_layer)
+                             ? ((p->flags & SLOS_COMP_KNUTH) ? SLOS_COMP_TWOSUM : SLOS_COMP_BIASED)
+                             : SLOS_COMP_NONE;
         ll.rr = p->opts.outputs_per_lane;
         ll.threads = p->opts.block_threads;
         ll.low_max = p->low_max[k];
@@ -859,11 +872,13 @@ static int run_forward(slos_plan_t p, const void *U, void *out, double *sum_p, v
         // a workgroup shares one low block: LDS does not limit its wave count
         const int wpb_k = wpb;
         ll.threads = 64 * wpb_k;
-        uint64_t want = (lp.nleaves + wpb_k - 1) / wpb_k;
+        uint64_t want = lp.nleaves;  // one leaf per workgroup at a time
         ll.grid = (int)std::min<uint64_t>(want, (uint64_t)p->opts.grid_blocks);
         // a whole number of workgroups per XCD
         ll.grid = std::max(SLOS_XCDS, (ll.grid + SLOS_XCDS - 1) / SLOS_XCDS * SLOS_XCDS);
-        lp.xcd_chunk = (uint32_t)p->opts.xcd_chunk;
+        // a layer with few leaves deals smaller chunks, so that every XCD gets some
+        lp.xcd_chunk = (uint32_t)std::max<uint64_t>(
+            1, std::min<uint64_t>((uint64_t)p->opts.xcd_chunk, lp.nleaves / (4 * SLOS_XCDS)));
         lp.tickets = p->d_tickets + (size_t)k * SLOS_XCDS * SLOS_TICKET_STRIDE;
         lp.ticket_leaves = (uint32_t)p->opts.ticket_leaves;
 
@@ -1157,7 +1172,7 @@ int slos_batch_plan(int count, const int32_t *ms, const int32_t *inputs, int fla
             for (int k = 1; k <= n; ++k) {
                 std::vector<LeafRec> lv;
                 std::vector<uint8_t> hm;
-                P.gen_leaves(k, m - 1, k, hm, lv);
+                P.gen_leaves(k, m - 1, k, (uint64_t)o.leaf_max, hm, lv);
                 I.col[k - 1] = (uint8_t)photons[k - 1];
                 I.desc_off[k - 1] = (uint32_t)b->desc.size();
                 I.nleaves[k - 1] = (uint32_t)lv.size();

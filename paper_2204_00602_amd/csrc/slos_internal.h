@@ -66,7 +66,14 @@ static_assert(sizeof(LeafDescWide) == 336, "LeafDescWide must stay 336 bytes");
 
 // Bytes of readable slack after every layer buffer: the low-block staging
 // copies whole 16-byte chunks in 1 KiB wave-wide steps.
-#define SLOS_BUFFER_SLACK 2048u
+#define SLOS_BUFFER_SLACK 2048
+// accumulation modes of the c64 layer kernel
+#define SLOS_COMP_NONE 0
+#define SLOS_COMP_BIASED 1
+#define SLOS_COMP_TWOSUM 2
+// per-layer leaf cap: min(leaf_max, max(SLOS_MIN_LEAF, N_k / SLOS_TARGET_LEAVES))
+#define SLOS_MIN_LEAF 512
+#define SLOS_TARGET_LEAVES 2048u
 
 // Inner table of one (q, K) pair: for each low state x (colex rank within
 // F(q, K)) the list of its occupied low modes j with the colex rank of
@@ -130,7 +137,7 @@ struct LayerParams {
 struct LayerLaunch {
     int c64;          // 1: complex64, 0: complex128
     int mode;         // SlosLayerMode
-    int compensated;  // c64 only
+    int compensated;  // c64 only: SLOS_COMP_NONE / _BIASED / _TWOSUM
     int rr;           // outputs per lane per tile: 1, 2, 4
     int threads;      // workgroup size (multiple of 64, <= 256)
     int grid;         // workgroups

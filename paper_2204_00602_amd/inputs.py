@@ -13,7 +13,7 @@ with single photons, Sections 4.2.1-4.2.2 and the Appendix B.6 QML code):
   * batch_instances: m ~ U{6..14}, n ~ U{2..min(7, m)}, photons placed one at a
     time into a uniformly chosen mode with occupancy < 2.
   * uniform_fock_states: distinct outputs drawn uniformly from S_{m,n}
-    (stars and bars: a uniform n-subset of m+n-1 slots).
+    (stars and bars: a uniform (m-1)-subset of m+n-1 slots marks the bars).
 """
 from __future__ import annotations
 
@@ -76,23 +76,30 @@ def batch_instances(count: int, seed: int, m_range=(6, 14), n_max: int = 7):
 
 
 def uniform_fock_states(m: int, n: int, count: int, seed: int) -> np.ndarray:
-    """`count` distinct outputs drawn uniformly from S_{m,n} (count x m int32)."""
+    """`count` distinct outputs drawn uniformly from S_{m,n} (count x m int32).
+
+    Stars and bars: a uniform (m-1)-subset of the m+n-1 slots (the slots of the
+    m-1 smallest of m+n-1 uniform keys) marks the bars, and the gaps between
+    consecutive bars are the occupations.  Candidates are drawn in bulk and the
+    first occurrence of each state is kept, in draw order.
+    """
     rng = np.random.default_rng(seed)
     total = math.comb(m + n - 1, n)
     count = min(count, total)
-    seen = set()
-    rows = []
-    while len(rows) < count:
-        bars = np.sort(rng.choice(m + n - 1, size=m - 1, replace=False)) if m > 1 else np.zeros(0, int)
-        # stars and bars: gaps between the m-1 bar positions give the occupations
-        edges = np.concatenate(([-1], bars, [m + n - 1]))
-        occ = np.diff(edges) - 1
-        key = occ.tobytes()
-        if key in seen:
-            continue
-        seen.add(key)
-        rows.append(occ.astype(np.int32))
-    return np.asarray(rows, dtype=np.int32).reshape(-1, m)
+    if m == 1:
+        return np.full((count, 1), n, dtype=np.int32)
+    rows = np.zeros((0, m), dtype=np.int32)
+    while rows.shape[0] < count:
+        need = count - rows.shape[0]
+        draw = need + need // 4 + 64
+        keys = rng.random((draw, m + n - 1))
+        bars = np.sort(np.argpartition(keys, m - 2, axis=1)[:, :m - 1], axis=1)
+        edges = np.concatenate((np.full((draw, 1), -1), bars, np.full((draw, 1), m + n - 1)), axis=1)
+        occ = (np.diff(edges, axis=1) - 1).astype(np.int32)
+        allr = np.concatenate((rows, occ))
+        _, first = np.unique(allr, axis=0, return_index=True)
+        rows = allr[np.sort(first)]
+    return np.ascontiguousarray(rows[:count])
 
 
 def bunched_fock_states(m: int, n: int, count: int) -> np.ndarray:

@@ -19,6 +19,7 @@ SLOS_OK = 0
 SLOS_C64 = 0x1
 SLOS_C128 = 0x2
 SLOS_COMPENSATED = 0x100
+SLOS_COMP_KNUTH = 0x800
 SLOS_KEEP_LAYERS = 0x200
 SLOS_HOST_ONLY = 0x400
 MAX_MODES = 255
@@ -143,9 +144,11 @@ class Plan:
     usage (Appendix B.6) with the output order fixed to colex rank.
     """
 
-    def __init__(self, input_state: Sequence[int], dtype: str = "c64", compensated: bool = False,
+    def __init__(self, input_state: Sequence[int], dtype: str = "c64", compensated=False,
                  keep_layers: bool = False, host_only: bool = False,
                  options: Optional[dict] = None):
+        """compensated: False, True (biased-FMA error recovery) or "knuth"
+        (two-product + Knuth two-sum); complex64 only."""
         self.input_state = _state_arr(input_state)
         self.m = int(self.input_state.size)
         self.n = int(self.input_state.sum())
@@ -155,6 +158,8 @@ class Plan:
         flags = SLOS_C64 if dtype == "c64" else SLOS_C128
         if compensated:
             flags |= SLOS_COMPENSATED
+            if compensated == "knuth":
+                flags |= SLOS_COMP_KNUTH
         if keep_layers:
             flags |= SLOS_KEEP_LAYERS
         if host_only:
