@@ -82,7 +82,7 @@ typedef struct slos_options {
     int32_t block_threads;   /* threads per workgroup: 64, 128, 256 (default 256)    */
     int32_t grid_blocks;     /* cap on workgroups per layer launch (default 2048)    */
     int32_t outputs_per_lane;/* 1, 2 or 4 outputs per lane per tile (default 4 for
-                                c64, 2 for compensated c64 and for c128)             */
+                                c64, 2 for c128)                                     */
     int32_t xcd_chunk;       /* consecutive leaves dealt to one XCD at a time
                                 (default 128; fewer when a layer has few leaves)    */
     int32_t ticket_leaves;   /* consecutive leaves a workgroup takes per work ticket

@@ -329,11 +329,14 @@ __device__ __forceinline__ void tile_load(TileIn<T, RT> &in, const LayerParams &
     }
 }
 
+// lowb (compensated mode only) bounds the low terms of every output of the
+// leaf: sum over them of (|Re u|+|Im u|)(|Re x|+|Im x|).
 template <typename T, int MODE, int COMP, int RT, bool WIDE>
 __device__ __forceinline__ void tile_compute(const TileIn<T, RT> &in, const LayerParams &p, const DescRegs<WIDE> &dr,
                                              const Leaf &L, const typename Cx<T>::type *__restrict__ X,
                                              const typename Cx<T>::type *u_lds, const float *ul1_lds,
-                                             const typename Cx<T>::type *lowbuf, uint32_t t0, int lane, double &psum)
+                                             const typename Cx<T>::type *lowbuf, float lowb, uint32_t t0, int lane,
+                                             double &psum)
 {
     using C = typename Cx<T>::type;
     const uint32_t *__restrict__ pred = p.pred + L.pred_off;
@@ -341,7 +344,7 @@ __device__ __forceinline__ void tile_compute(const TileIn<T, RT> &in, const Laye
     // Visit every term (output i, mode j, predecessor value) of the tile:
     // high groups from registers (or, past kHS groups, straight from memory),
     // low terms from the staged block.
-    auto terms = [&](auto &&f) {
+    auto high_terms = [&](auto &&f) {
 #pragma unroll
         for (int g = 0; g < kHS; ++g) {
             if (g < L.nh) {
@@ -356,6 +359,9 @@ __device__ __forceinline__ void tile_compute(const TileIn<T, RT> &in, const Laye
 #pragma unroll
             for (int i = 0; i < RT; ++i) f(i, j, ld_off<C>(Xb, in.off[i]));
         }
+    };
+    auto terms = [&](auto &&f) {
+        high_terms(f);
 #pragma unroll
         for (int c = 0; c < kCS; ++c) {
             if (c < L.cmax) {
@@ -377,14 +383,14 @@ __device__ __forceinline__ void tile_compute(const TileIn<T, RT> &in, const Laye
 #pragma unroll
     for (int i = 0; i < RT; ++i) acc[i].zero();
     if constexpr (COMP == SLOS_COMP_BIASED) {
+        // bias bound: exact sum over the high terms (in registers) plus the
+        // leaf-wide bound of the low terms
         float bnd[RT];
 #pragma unroll
-        for (int i = 0; i < RT; ++i) bnd[i] = 0.f;
-        terms([&](int i, int j, const C x) { bnd[i] = __builtin_fmaf(ul1_lds[j], fabsf(x.x) + fabsf(x.y), bnd[i]); });
+        for (int i = 0; i < RT; ++i) bnd[i] = lowb;
+        high_terms([&](int i, int j, const C x) { bnd[i] = __builtin_fmaf(ul1_lds[j], fabsf(x.x) + fabsf(x.y), bnd[i]); });
 #pragma unroll
         for (int i = 0; i < RT; ++i) acc[i].start(bnd[i]);
-        // read the low terms from LDS again rather than keep them in registers
-        asm volatile("" ::: "memory");
     }
     terms([&](int i, int j, const C x) { acc[i].mac(u_lds[j], x); });
 
@@ -417,11 +423,12 @@ template <typename T, int MODE, int COMP, int RT, bool WIDE>
 __device__ __forceinline__ void tile(const LayerParams &p, const DescRegs<WIDE> &dr, const Leaf &L,
                                      const typename Cx<T>::type *__restrict__ X,
                                      const typename Cx<T>::type *u_lds, const float *ul1_lds,
-                                     const typename Cx<T>::type *lowbuf, uint32_t t0, int lane, double &psum)
+                                     const typename Cx<T>::type *lowbuf, float lowb, uint32_t t0, int lane,
+                                     double &psum)
 {
     TileIn<T, RT> in;
     tile_load<T, MODE, RT, WIDE>(in, p, dr, L, X, t0, lane);
-    tile_compute<T, MODE, COMP, RT, WIDE>(in, p, dr, L, X, u_lds, ul1_lds, lowbuf, t0, lane, psum);
+    tile_compute<T, MODE, COMP, RT, WIDE>(in, p, dr, L, X, u_lds, ul1_lds, lowbuf, lowb, t0, lane, psum);
 }
 
 // Stage the low block with all waves of the workgroup: 1 KiB chunk c of the
@@ -449,12 +456,15 @@ __device__ __forceinline__ const C *stage_low_team(const C *__restrict__ X, cons
 // come from per-XCD ticket counters in batches of p.ticket_leaves, so the
 // workgroups resident on an XCD work on neighbouring leaves of the colex order
 // and share that XCD's L2.
+// complex64 tiles are held to three waves per SIMD (168 VGPRs), the occupancy
+// the LDS of one low block per workgroup allows at the default leaf size
 template <typename T, int MODE, int COMP, int RR, bool WIDE>
-__global__ __launch_bounds__(256) void layer_kernel(LayerParams p)
+__global__ __launch_bounds__(256, sizeof(T) == 4 ? 3 : 1) void layer_kernel(LayerParams p)
 {
     using C = typename Cx<T>::type;
     __shared__ C u_lds[256];
     __shared__ float ul1_lds[COMP == SLOS_COMP_BIASED ? 256 : 1];  // |Re u_j| + |Im u_j|
+    __shared__ float red_lds[4];
     __shared__ uint32_t ticket_slot[2];
     const C *__restrict__ X = (const C *)p.X;
     const C *__restrict__ Um = (const C *)p.U;
@@ -513,14 +523,33 @@ __global__ __launch_bounds__(256) void layer_kernel(LayerParams p)
         DescRegs<WIDE> nxt{0u, 0u};
         if (nli < p.nleaves) nxt = load_desc<WIDE>(p.desc, nli, lane);
 
+        float lowb = 0.f;
+        if constexpr (COMP == SLOS_COMP_BIASED) {
+            // bound of every output's low terms: (low terms per output) x
+            // max_j (|Re u_j| + |Im u_j|) x max over the low block of |Re x| + |Im x|
+            float mx = 0.f, um = 0.f;
+            for (uint32_t x = threadIdx.x; x < L.low_size; x += blockDim.x)
+                mx = fmaxf(mx, fabsf(lowbuf[x].x) + fabsf(lowbuf[x].y));
+            for (int j = lane; j < p.m; j += 64) um = fmaxf(um, ul1_lds[j]);
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+                mx = fmaxf(mx, __shfl_xor(mx, o, 64));
+                um = fmaxf(um, __shfl_xor(um, o, 64));
+            }
+            if (lane == 0) red_lds[wv] = mx;
+            __syncthreads();
+            for (int w = 0; w < W; ++w) mx = fmaxf(mx, red_lds[w]);
+            lowb = (float)L.cmax * um * mx * 1.0001f;
+        }
+
         double psum = 0.0;
         const uint32_t full = L.size / (64u * RR);              // full tiles
         for (uint32_t t = (uint32_t)wv; t < full; t += (uint32_t)W)
-            tile<T, MODE, COMP, RR, WIDE>(p, cur, L, X, u_lds, ul1_lds, lowbuf, t * 64u * RR, lane, psum);
+            tile<T, MODE, COMP, RR, WIDE>(p, cur, L, X, u_lds, ul1_lds, lowbuf, lowb, t * 64u * RR, lane, psum);
         const uint32_t rows = (L.size - full * 64u * RR + 63u) / 64u;  // leftover rows of 64
         for (uint32_t r = (uint32_t)wv; r < rows; r += (uint32_t)W)
-            tile<T, MODE, COMP, 1, WIDE>(p, cur, L, X, u_lds, ul1_lds, lowbuf, full * 64u * RR + r * 64u, lane,
-                                         psum);
+            tile<T, MODE, COMP, 1, WIDE>(p, cur, L, X, u_lds, ul1_lds, lowbuf, lowb, full * 64u * RR + r * 64u,
+                                         lane, psum);
         if (MODE != SLOS_MODE_MID) {
             // one FP64 partial per (leaf, wave), summed later in a fixed order
 #pragma unroll
@@ -593,17 +622,17 @@ __global__ __launch_bounds__(256) void batch_kernel(BatchParams bp)
                 const uint32_t full = L.size / (64u * RR);
                 if (k == n) {
                     for (uint32_t t = 0; t < full; ++t)
-                        tile<T, SLOS_MODE_AMPL, SLOS_COMP_NONE, RR, false>(lp, d, L, X, u_lds, nullptr, lowbuf,
+                        tile<T, SLOS_MODE_AMPL, SLOS_COMP_NONE, RR, false>(lp, d, L, X, u_lds, nullptr, lowbuf, 0.f,
                                                                           t * 64u * RR, lane, psum);
                     for (uint32_t t0 = full * 64u * RR; t0 < L.size; t0 += 64u)
-                        tile<T, SLOS_MODE_AMPL, SLOS_COMP_NONE, 1, false>(lp, d, L, X, u_lds, nullptr, lowbuf, t0,
+                        tile<T, SLOS_MODE_AMPL, SLOS_COMP_NONE, 1, false>(lp, d, L, X, u_lds, nullptr, lowbuf, 0.f, t0,
                                                                          lane, psum);
                 } else {
                     for (uint32_t t = 0; t < full; ++t)
-                        tile<T, SLOS_MODE_MID, SLOS_COMP_NONE, RR, false>(lp, d, L, X, u_lds, nullptr, lowbuf,
+                        tile<T, SLOS_MODE_MID, SLOS_COMP_NONE, RR, false>(lp, d, L, X, u_lds, nullptr, lowbuf, 0.f,
                                                                          t * 64u * RR, lane, psum);
                     for (uint32_t t0 = full * 64u * RR; t0 < L.size; t0 += 64u)
-                        tile<T, SLOS_MODE_MID, SLOS_COMP_NONE, 1, false>(lp, d, L, X, u_lds, nullptr, lowbuf, t0,
+                        tile<T, SLOS_MODE_MID, SLOS_COMP_NONE, 1, false>(lp, d, L, X, u_lds, nullptr, lowbuf, 0.f, t0,
                                                                         lane, psum);
                 }
                 __builtin_amdgcn_s_waitcnt(0);

@@ -517,9 +517,7 @@ int slos_plan_ex(int m, int n, const int32_t *input_state, int flags, const slos
     if (o.comp_from_layer == 0) o.comp_from_layer = 1;
     if (o.block_threads == 0) o.block_threads = 256;
     if (o.grid_blocks == 0) o.grid_blocks = 2048;
-    // compensated tiles hold five floats per output: two outputs per lane keep
-    // three waves per SIMD
-    if (o.outputs_per_lane == 0) o.outputs_per_lane = (dt == SLOS_C64 && !(flags & SLOS_COMPENSATED)) ? 4 : 2;
+    if (o.outputs_per_lane == 0) o.outputs_per_lane = dt == SLOS_C64 ? 4 : 2;
     if (o.xcd_chunk == 0) o.xcd_chunk = 128;
     if (o.ticket_leaves == 0) o.ticket_leaves = 4;
     if (o.ticket_leaves < 1 || o.ticket_leaves > 4096)
