@@ -57,8 +57,9 @@ extern "C" {
                                   k >= comp_from_layer.  Each FMA's rounding error
                                   is recovered exactly (the two-sum of the running
                                   sum and the product, made exact by starting the
-                                  sum at a power-of-two bias >= 4 sum|u_j v_j|)
-                                  and summed in a second float; 4 flops per real
+                                  sum at a power-of-two bias >= 4 sum|products|,
+                                  from the previous layer's recorded maximum) and
+                                  summed in a second float; 4 flops per real
                                   product                                          */
 #define SLOS_COMP_KNUTH 0x800  /* with SLOS_COMPENSATED: FMA two-product plus
                                   Knuth's branch-free two-sum instead (10 flops per

@@ -64,8 +64,7 @@ __device__ __forceinline__ void cmac_comp(CompAcc &a, const float2 u, const floa
 }
 
 // Default compensated mode: biased FMA accumulation.  The sum starts at a
-// power of two sigma >= 4 * sum_i |a_i b_i| (a bound from the operands, taken
-// before the sum).  Every partial sum then stays within [3/4, 5/4] sigma, so
+// power of two sigma >= 4 * sum_i |a_i b_i| (a bound known before the sum).  Every partial sum then stays within [3/4, 5/4] sigma, so
 // for t = fma(a, b, s) the difference s - t is exact (Sterbenz) and
 // fma(a, b, s - t) is the FMA's rounding error, correct to one rounding of a
 // number below ulp(sigma).  Those errors go to a second float c, and the
@@ -112,12 +111,11 @@ template <> struct Acc<float, SLOS_COMP_TWOSUM> {
 template <> struct Acc<float, SLOS_COMP_BIASED> {
     float sr, si, cr, ci, sigma;
     __device__ __forceinline__ void zero() { sr = si = cr = ci = sigma = 0.f; }
-    // b >= sum over the terms of (|u.x| + |u.y|)(|v.x| + |v.y|)
-    __device__ __forceinline__ void start(float b)
+    __device__ __forceinline__ void start(float bias)
     {
-        sigma = bias_for(b);
-        sr = sigma;
-        si = sigma;
+        sigma = bias;
+        sr = bias;
+        si = bias;
     }
     __device__ __forceinline__ void mac(const float2 u, const float2 v)
     {
@@ -329,14 +327,14 @@ __device__ __forceinline__ void tile_load(TileIn<T, RT> &in, const LayerParams &
     }
 }
 
-// lowb (compensated mode only) bounds the low terms of every output of the
-// leaf: sum over them of (|Re u|+|Im u|)(|Re x|+|Im x|).
+// sigma: the bias of the compensated mode (see Acc<float, SLOS_COMP_BIASED>).
+// omax collects max |Re a| + |Im a| over the complex64 outputs of a mid layer,
+// the input bound of a compensated next layer.
 template <typename T, int MODE, int COMP, int RT, bool WIDE>
 __device__ __forceinline__ void tile_compute(const TileIn<T, RT> &in, const LayerParams &p, const DescRegs<WIDE> &dr,
                                              const Leaf &L, const typename Cx<T>::type *__restrict__ X,
-                                             const typename Cx<T>::type *u_lds, const float *ul1_lds,
-                                             const typename Cx<T>::type *lowbuf, float lowb, uint32_t t0, int lane,
-                                             double &psum)
+                                             const typename Cx<T>::type *u_lds, const typename Cx<T>::type *lowbuf,
+                                             float sigma, uint32_t t0, int lane, double &psum, float &omax)
 {
     using C = typename Cx<T>::type;
     const uint32_t *__restrict__ pred = p.pred + L.pred_off;
@@ -344,7 +342,7 @@ __device__ __forceinline__ void tile_compute(const TileIn<T, RT> &in, const Laye
     // Visit every term (output i, mode j, predecessor value) of the tile:
     // high groups from registers (or, past kHS groups, straight from memory),
     // low terms from the staged block.
-    auto high_terms = [&](auto &&f) {
+    auto terms = [&](auto &&f) {
 #pragma unroll
         for (int g = 0; g < kHS; ++g) {
             if (g < L.nh) {
@@ -359,9 +357,6 @@ __device__ __forceinline__ void tile_compute(const TileIn<T, RT> &in, const Laye
 #pragma unroll
             for (int i = 0; i < RT; ++i) f(i, j, ld_off<C>(Xb, in.off[i]));
         }
-    };
-    auto terms = [&](auto &&f) {
-        high_terms(f);
 #pragma unroll
         for (int c = 0; c < kCS; ++c) {
             if (c < L.cmax) {
@@ -382,16 +377,8 @@ __device__ __forceinline__ void tile_compute(const TileIn<T, RT> &in, const Laye
     Acc<T, COMP> acc[RT];
 #pragma unroll
     for (int i = 0; i < RT; ++i) acc[i].zero();
-    if constexpr (COMP == SLOS_COMP_BIASED) {
-        // bias bound: exact sum over the high terms (in registers) plus the
-        // leaf-wide bound of the low terms
-        float bnd[RT];
 #pragma unroll
-        for (int i = 0; i < RT; ++i) bnd[i] = lowb;
-        high_terms([&](int i, int j, const C x) { bnd[i] = __builtin_fmaf(ul1_lds[j], fabsf(x.x) + fabsf(x.y), bnd[i]); });
-#pragma unroll
-        for (int i = 0; i < RT; ++i) acc[i].start(bnd[i]);
-    }
+    for (int i = 0; i < RT; ++i) acc[i].start(sigma);
     terms([&](int i, int j, const C x) { acc[i].mac(u_lds[j], x); });
 
     // ---- store
@@ -401,6 +388,7 @@ __device__ __forceinline__ void tile_compute(const TileIn<T, RT> &in, const Laye
         const uint64_t o = L.out_base + in.xc[i];
         if (MODE == SLOS_MODE_MID) {
             const C a = acc[i].value();
+            if (sizeof(T) == 4) omax = fmaxf(omax, (float)(fabs(a.x) + fabs(a.y)));
             __builtin_nontemporal_store(a.x, &((T *)p.Y)[2 * o]);
             __builtin_nontemporal_store(a.y, &((T *)p.Y)[2 * o + 1]);
         } else {
@@ -422,13 +410,12 @@ __device__ __forceinline__ void tile_compute(const TileIn<T, RT> &in, const Laye
 template <typename T, int MODE, int COMP, int RT, bool WIDE>
 __device__ __forceinline__ void tile(const LayerParams &p, const DescRegs<WIDE> &dr, const Leaf &L,
                                      const typename Cx<T>::type *__restrict__ X,
-                                     const typename Cx<T>::type *u_lds, const float *ul1_lds,
-                                     const typename Cx<T>::type *lowbuf, float lowb, uint32_t t0, int lane,
-                                     double &psum)
+                                     const typename Cx<T>::type *u_lds, const typename Cx<T>::type *lowbuf,
+                                     float sigma, uint32_t t0, int lane, double &psum, float &omax)
 {
     TileIn<T, RT> in;
     tile_load<T, MODE, RT, WIDE>(in, p, dr, L, X, t0, lane);
-    tile_compute<T, MODE, COMP, RT, WIDE>(in, p, dr, L, X, u_lds, ul1_lds, lowbuf, lowb, t0, lane, psum);
+    tile_compute<T, MODE, COMP, RT, WIDE>(in, p, dr, L, X, u_lds, lowbuf, sigma, t0, lane, psum, omax);
 }
 
 // Stage the low block with all waves of the workgroup: 1 KiB chunk c of the
@@ -463,8 +450,6 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 3 : 1) void layer_kernel(Laye
 {
     using C = typename Cx<T>::type;
     __shared__ C u_lds[256];
-    __shared__ float ul1_lds[COMP == SLOS_COMP_BIASED ? 256 : 1];  // |Re u_j| + |Im u_j|
-    __shared__ float red_lds[4];
     __shared__ uint32_t ticket_slot[2];
     const C *__restrict__ X = (const C *)p.X;
     const C *__restrict__ Um = (const C *)p.U;
@@ -472,7 +457,6 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 3 : 1) void layer_kernel(Laye
         C v{0, 0};
         if (j < p.m) v = Um[(size_t)j * p.m + p.col];
         u_lds[j] = v;
-        if (COMP == SLOS_COMP_BIASED) ul1_lds[j] = (float)(fabs(v.x) + fabs(v.y));
     }
 
     const int lane = threadIdx.x & 63;
@@ -507,6 +491,20 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 3 : 1) void layer_kernel(Laye
     if (li < p.nleaves) cur = load_desc<WIDE>(p.desc, li, lane);
     uint32_t it = 0;
 
+    // Compensated bias of this layer: every output sums at most one term per
+    // mode, so sum |Re,Im products| <= (sum_j |Re u_j| + |Im u_j|) * vmax with
+    // vmax = max over A_{k-1} of |Re x| + |Im x| (recorded by the previous
+    // layer; 1 for the vacuum).
+    float sigma = 0.f, omax = 0.f;
+    if constexpr (COMP == SLOS_COMP_BIASED) {
+        float l1 = 0.f;
+        for (int j = lane; j < p.m; j += 64) l1 += (float)(fabs(u_lds[j].x) + fabs(u_lds[j].y));
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) l1 += __shfl_xor(l1, o, 64);
+        const float vin = p.vmax_in ? __uint_as_float(*p.vmax_in) : 1.0f;
+        sigma = bias_for(l1 * vin * 1.001f);
+    }
+
     while (li < p.nleaves) {
         const Leaf L = decode_head<WIDE>(cur);
         const C *lowbuf = stage_low_team<C>(X, L, slice, lane, wv, W);
@@ -523,33 +521,14 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 3 : 1) void layer_kernel(Laye
         DescRegs<WIDE> nxt{0u, 0u};
         if (nli < p.nleaves) nxt = load_desc<WIDE>(p.desc, nli, lane);
 
-        float lowb = 0.f;
-        if constexpr (COMP == SLOS_COMP_BIASED) {
-            // bound of every output's low terms: (low terms per output) x
-            // max_j (|Re u_j| + |Im u_j|) x max over the low block of |Re x| + |Im x|
-            float mx = 0.f, um = 0.f;
-            for (uint32_t x = threadIdx.x; x < L.low_size; x += blockDim.x)
-                mx = fmaxf(mx, fabsf(lowbuf[x].x) + fabsf(lowbuf[x].y));
-            for (int j = lane; j < p.m; j += 64) um = fmaxf(um, ul1_lds[j]);
-#pragma unroll
-            for (int o = 32; o > 0; o >>= 1) {
-                mx = fmaxf(mx, __shfl_xor(mx, o, 64));
-                um = fmaxf(um, __shfl_xor(um, o, 64));
-            }
-            if (lane == 0) red_lds[wv] = mx;
-            __syncthreads();
-            for (int w = 0; w < W; ++w) mx = fmaxf(mx, red_lds[w]);
-            lowb = (float)L.cmax * um * mx * 1.0001f;
-        }
-
         double psum = 0.0;
         const uint32_t full = L.size / (64u * RR);              // full tiles
         for (uint32_t t = (uint32_t)wv; t < full; t += (uint32_t)W)
-            tile<T, MODE, COMP, RR, WIDE>(p, cur, L, X, u_lds, ul1_lds, lowbuf, lowb, t * 64u * RR, lane, psum);
+            tile<T, MODE, COMP, RR, WIDE>(p, cur, L, X, u_lds, lowbuf, sigma, t * 64u * RR, lane, psum, omax);
         const uint32_t rows = (L.size - full * 64u * RR + 63u) / 64u;  // leftover rows of 64
         for (uint32_t r = (uint32_t)wv; r < rows; r += (uint32_t)W)
-            tile<T, MODE, COMP, 1, WIDE>(p, cur, L, X, u_lds, ul1_lds, lowbuf, lowb, full * 64u * RR + r * 64u,
-                                         lane, psum);
+            tile<T, MODE, COMP, 1, WIDE>(p, cur, L, X, u_lds, lowbuf, sigma, full * 64u * RR + r * 64u, lane, psum,
+                                         omax);
         if (MODE != SLOS_MODE_MID) {
             // one FP64 partial per (leaf, wave), summed later in a fixed order
 #pragma unroll
@@ -562,6 +541,12 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 3 : 1) void layer_kernel(Laye
         cur = nxt;
         li = nli;
         ++it;
+    }
+    if (sizeof(T) == 4 && MODE == SLOS_MODE_MID && p.vmax_out) {
+        // non-negative floats order like their bit patterns
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) omax = fmaxf(omax, __shfl_xor(omax, o, 64));
+        if (lane == 0) atomicMax(p.vmax_out, __float_as_uint(omax));
     }
 }
 
@@ -593,6 +578,7 @@ __global__ __launch_bounds__(256) void batch_kernel(BatchParams bp)
         const BatchInst &I = bp.inst[ii];
         const int m = (int)I.m, n = (int)I.n;
         double psum = 0.0;
+        float bmax = 0.f;  // unused: batches are not compensated
         if (n == 0 && threadIdx.x == 0) {
             // no photons: the single output is the vacuum, amplitude 1
             ((C *)bp.out)[I.out_off] = C{(T)1, (T)0};
@@ -622,18 +608,18 @@ __global__ __launch_bounds__(256) void batch_kernel(BatchParams bp)
                 const uint32_t full = L.size / (64u * RR);
                 if (k == n) {
                     for (uint32_t t = 0; t < full; ++t)
-                        tile<T, SLOS_MODE_AMPL, SLOS_COMP_NONE, RR, false>(lp, d, L, X, u_lds, nullptr, lowbuf, 0.f,
-                                                                          t * 64u * RR, lane, psum);
+                        tile<T, SLOS_MODE_AMPL, SLOS_COMP_NONE, RR, false>(lp, d, L, X, u_lds, lowbuf, 0.f,
+                                                                          t * 64u * RR, lane, psum, bmax);
                     for (uint32_t t0 = full * 64u * RR; t0 < L.size; t0 += 64u)
-                        tile<T, SLOS_MODE_AMPL, SLOS_COMP_NONE, 1, false>(lp, d, L, X, u_lds, nullptr, lowbuf, 0.f, t0,
-                                                                         lane, psum);
+                        tile<T, SLOS_MODE_AMPL, SLOS_COMP_NONE, 1, false>(lp, d, L, X, u_lds, lowbuf, 0.f, t0,
+                                                                         lane, psum, bmax);
                 } else {
                     for (uint32_t t = 0; t < full; ++t)
-                        tile<T, SLOS_MODE_MID, SLOS_COMP_NONE, RR, false>(lp, d, L, X, u_lds, nullptr, lowbuf, 0.f,
-                                                                         t * 64u * RR, lane, psum);
+                        tile<T, SLOS_MODE_MID, SLOS_COMP_NONE, RR, false>(lp, d, L, X, u_lds, lowbuf, 0.f,
+                                                                         t * 64u * RR, lane, psum, bmax);
                     for (uint32_t t0 = full * 64u * RR; t0 < L.size; t0 += 64u)
-                        tile<T, SLOS_MODE_MID, SLOS_COMP_NONE, 1, false>(lp, d, L, X, u_lds, nullptr, lowbuf, 0.f, t0,
-                                                                        lane, psum);
+                        tile<T, SLOS_MODE_MID, SLOS_COMP_NONE, 1, false>(lp, d, L, X, u_lds, lowbuf, 0.f, t0,
+                                                                        lane, psum, bmax);
                 }
                 __builtin_amdgcn_s_waitcnt(0);
                 __builtin_amdgcn_wave_barrier();

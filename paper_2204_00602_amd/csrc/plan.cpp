@@ -878,6 +878,12 @@ static int run_forward(slos_plan_t p, const void *U, void *out, double *sum_p, v
         lp.xcd_chunk = (uint32_t)std::max<uint64_t>(
             1, std::min<uint64_t>((uint64_t)p->opts.xcd_chunk, lp.nleaves / (4 * SLOS_XCDS)));
         lp.tickets = p->d_tickets + (size_t)k * SLOS_XCDS * SLOS_TICKET_STRIDE;
+        const bool comp_k = ll.compensated == SLOS_COMP_BIASED;
+        const bool comp_next = k < n && p->comp && !(p->flags & SLOS_COMP_KNUTH) && k + 1 >= p->opts.comp_from_layer;
+        lp.vmax_in = (comp_k && k >= 2)
+                         ? p->d_tickets + (size_t)(k - 1) * SLOS_XCDS * SLOS_TICKET_STRIDE + SLOS_VMAX_SLOT
+                         : nullptr;
+        lp.vmax_out = comp_next ? lp.tickets + SLOS_VMAX_SLOT : nullptr;
         lp.ticket_leaves = (uint32_t)p->opts.ticket_leaves;
 
         int e = slos_launch_layer(lp, ll, stream);

@@ -95,7 +95,9 @@ static_assert(sizeof(InnerType) == 32, "InnerType must stay 32 bytes");
 #define SLOS_PRED_MASK 0x00FFFFFFu
 
 #define SLOS_XCDS 8   // MI355X: 8 accelerator complex dies, workgroups dealt round-robin
-#define SLOS_TICKET_STRIDE 64  // uint32 slots between ticket counters: one per 256-byte line
+#define SLOS_TICKET_STRIDE 64
+// u32 index, within a layer's first ticket line, of that layer's recorded max
+#define SLOS_VMAX_SLOT 32  // uint32 slots between ticket counters: one per 256-byte line
 
 enum SlosLayerMode {
     SLOS_MODE_MID = 0,    // store A_k
@@ -132,6 +134,11 @@ struct LayerParams {
     // always work on neighbouring leaves and share the L2.
     uint32_t *tickets;
     uint32_t ticket_leaves;  // consecutive leaves per ticket
+    // Compensated layers: max over A_{k-1} of |Re x| + |Im x| as float bits
+    // (NULL: the vacuum, 1), and where this layer records the same for A_k
+    // (NULL: not recorded).  Both live in the zeroed ticket area.
+    const uint32_t *vmax_in;
+    uint32_t *vmax_out;
 };
 
 struct LayerLaunch {
