@@ -306,19 +306,42 @@ __device__ __forceinline__ void tile_load(TileIn<T, RT> &in, const LayerParams &
         in.off[i] = in.xc[i] * (uint32_t)sizeof(C);
     }
     const uint32_t *__restrict__ pred = p.pred + L.pred_off;
+    if constexpr (sizeof(T) == 8) {
+        // complex128: a fixed number of loads, whatever the leaf.  Slots past
+        // the leaf's groups or terms read element 0 (one line for the whole
+        // wave) and are not used; straight-line loads let the compiler wait
+        // for each one just before its first use.  (Measured faster for
+        // complex128, slower for complex64.)
 #pragma unroll
-    for (int g = 0; g < kHS; ++g) {
-        if (g < L.nh) {
-            const C *Xb = X + group_base<WIDE>(dr, L, g);
+        for (int g = 0; g < kHS; ++g) {
+            const bool live = g < L.nh;
+            const C *Xb = live ? X + group_base<WIDE>(dr, L, g) : X;
 #pragma unroll
-            for (int i = 0; i < RT; ++i) in.v[g][i] = ld_off<C>(Xb, in.off[i]);
+            for (int i = 0; i < RT; ++i) in.v[g][i] = ld_off<C>(Xb, live ? in.off[i] : 0u);
         }
-    }
 #pragma unroll
-    for (int c = 0; c < kCS; ++c) {
-        if (c < L.cmax) {
+        for (int c = 0; c < kCS; ++c) {
+            const bool live = c < L.cmax;
 #pragma unroll
-            for (int i = 0; i < RT; ++i) in.e[c][i] = ld_off<uint32_t>(pred, ((uint32_t)c * L.size + in.xc[i]) * 4u);
+            for (int i = 0; i < RT; ++i)
+                in.e[c][i] = ld_off<uint32_t>(pred, live ? ((uint32_t)c * L.size + in.xc[i]) * 4u : 0u);
+        }
+    } else {
+#pragma unroll
+        for (int g = 0; g < kHS; ++g) {
+            if (g < L.nh) {
+                const C *Xb = X + group_base<WIDE>(dr, L, g);
+#pragma unroll
+                for (int i = 0; i < RT; ++i) in.v[g][i] = ld_off<C>(Xb, in.off[i]);
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < kCS; ++c) {
+            if (c < L.cmax) {
+#pragma unroll
+                for (int i = 0; i < RT; ++i)
+                    in.e[c][i] = ld_off<uint32_t>(pred, ((uint32_t)c * L.size + in.xc[i]) * 4u);
+            }
         }
     }
     if (MODE != SLOS_MODE_MID) {
@@ -444,9 +467,10 @@ __device__ __forceinline__ const C *stage_low_team(const C *__restrict__ X, cons
 // workgroups resident on an XCD work on neighbouring leaves of the colex order
 // and share that XCD's L2.
 // complex64 tiles are held to three waves per SIMD (168 VGPRs), the occupancy
-// the LDS of one low block per workgroup allows at the default leaf size
+// the LDS of one low block per workgroup allows at the default leaf size;
+// complex128 tiles of up to two outputs per lane to four (128 VGPRs)
 template <typename T, int MODE, int COMP, int RR, bool WIDE>
-__global__ __launch_bounds__(256, sizeof(T) == 4 ? 3 : 1) void layer_kernel(LayerParams p)
+__global__ __launch_bounds__(256, sizeof(T) == 4 ? 3 : (RR <= 2 ? 4 : 1)) void layer_kernel(LayerParams p)
 {
     using C = typename Cx<T>::type;
     __shared__ C u_lds[256];
