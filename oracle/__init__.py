@@ -139,6 +139,24 @@ def partial_certificate(probs, states, K: int) -> float:
     return float(np.sum(np.asarray(probs)[mask]))
 
 
+def colex_sorted(states) -> np.ndarray:
+    """The rows of `states` in colex order: lexicographic on the occupation
+    vector read from the last mode (the output order of the strong simulation)."""
+    states = np.asarray(states)
+    return states[np.lexsort(states.T)]
+
+
+def inverse_cdf_sample(probs, r) -> np.ndarray:
+    """Weak simulation from the strong one (the sampler the paper builds on
+    SLOS, Section 3.2): for each uniform r in [0, 1), the index of the first
+    output, in the given order, whose cumulative probability exceeds
+    r * sum(P).  Cumulative sums in extended precision."""
+    c = np.cumsum(np.asarray(probs, dtype=np.longdouble))
+    t = np.asarray(r, dtype=np.longdouble) * c[-1]
+    idx = np.searchsorted(c, t, side="right")
+    return np.minimum(idx, len(c) - 1).astype(np.int64)
+
+
 def haar_pk_mean(K: int, m: int, n: int) -> float:
     """Haar average of P(K): K(K+1)..(K+n-1) / (m(m+1)..(m+n-1)) (Eq. eqhaarpk)."""
     num = 1.0

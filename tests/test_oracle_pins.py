@@ -355,3 +355,45 @@ def test_grad_U_matches_direct_finite_differences():
             dre = (loss(U + E) - loss(U - E)) / (2 * h)
             dim = (loss(U + 1j * E) - loss(U - 1j * E)) / (2 * h)
             assert G[j, i] == pytest.approx(complex(dre, dim), abs=1e-8)
+
+
+# ---------------------------------------------------------------- weak simulation
+
+def test_colex_sorted_small_listing():
+    S = oracle.colex_sorted(oracle.fock_states(3, 2))
+    expected = [[2, 0, 0], [1, 1, 0], [0, 2, 0], [1, 0, 1], [0, 1, 1], [0, 0, 2]]
+    assert S.tolist() == expected
+
+
+@pytest.mark.parametrize("m,n", [(4, 3), (6, 3), (5, 4)])
+def test_empty_top_modes_form_a_colex_prefix(m, n):
+    """Eq. eqpk's event (modes K..m-1 empty) is the first C(K+n-1, n) states in colex order."""
+    S = oracle.colex_sorted(oracle.fock_states(m, n))
+    for K in range(1, m + 1):
+        mask = np.all(S[:, K:] == 0, axis=1)
+        c = math.comb(K + n - 1, n)
+        assert mask[:c].all() and not mask[c:].any()
+
+
+def test_inverse_cdf_sample_hand_distribution():
+    P = [0.1, 0.0, 0.5, 0.4]
+    r = [0.0, 0.05, 0.1, 0.35, 0.65, 0.999999]
+    assert oracle.inverse_cdf_sample(P, r).tolist() == [0, 0, 2, 2, 3, 3]
+    # unnormalised weights sample the same way
+    assert oracle.inverse_cdf_sample([2.0, 0.0, 10.0, 8.0], r).tolist() == [0, 0, 2, 2, 3, 3]
+
+
+def test_inverse_cdf_sample_frequencies_match_probabilities():
+    """Sampled frequencies of the m=5, n=3 distribution of a Haar U agree with P
+    within 5 standard deviations, and zero-probability states never appear."""
+    U = inputs.haar_unitary(5, 17)
+    T = np.array([1, 1, 1, 0, 0])
+    S = oracle.colex_sorted(oracle.fock_states(5, 3))
+    P = oracle.probabilities(U, T, S)
+    r = np.random.default_rng(3).random(200_000)
+    counts = np.bincount(oracle.inverse_cdf_sample(P, r), minlength=len(P))
+    sd = np.sqrt(len(r) * P * (1 - P)) + 1e-9
+    assert np.all(np.abs(counts - len(r) * P) <= 5 * sd + 1)
+    Z = np.zeros(6)
+    Z[4] = 1.0
+    assert set(oracle.inverse_cdf_sample(Z, r[:1000]).tolist()) == {4}
