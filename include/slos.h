@@ -149,6 +149,36 @@ int slos_amplitudes(slos_plan_t plan, const void *U, void *out, double *sum_p, v
  */
 int slos_probs(slos_plan_t plan, const void *U, void *probs, double *sum_p, void *stream);
 
+/* ---- weak simulation from the strong one ------------------------------------ */
+
+/*
+ * Cumulative probability table of `probs` (device, M values in colex order:
+ * fp32 for a C64 plan, fp64 for C128, e.g. the output of slos_probs; need not
+ * be normalised).  FP64 sums of blocks of SLOS_CDF_BLOCK (1024) states and
+ * their exclusive prefix, kept by the plan (one table per plan; a later call
+ * replaces it).  Deterministic.  slos_marginals and slos_sample read this table
+ * together with the same `probs`.
+ */
+int slos_cdf(slos_plan_t plan, const void *probs, void *stream);
+
+/*
+ * Partial certificates (Section 4.2.2, Eq. eqpk): pk[K-1] = P(K), the total
+ * probability that modes K..m-1 (0-based) are empty, for K = 1..m, in FP64
+ * (device, m doubles).  In colex order those states are the first C(K+n-1, n),
+ * so P(K) is a prefix sum.  Needs slos_cdf on the same `probs` first.
+ */
+int slos_marginals(slos_plan_t plan, const void *probs, double *pk, void *stream);
+
+/*
+ * Sampling (the sampler built on a strong back-end, Section 3.2): for each of
+ * `count` uniforms r[i] in [0, 1) (device FP64, supplied by the caller),
+ * ranks[i] (device int64) = colex rank of the first output whose cumulative
+ * probability exceeds r[i] * sum P.  States of zero probability are never
+ * returned.  Needs slos_cdf on the same `probs` first.
+ */
+int slos_sample(slos_plan_t plan, const void *probs, const double *r, int64_t count, int64_t *ranks,
+                void *stream);
+
 /* ---- differentiation ---------------------------------------------------------- */
 
 /*

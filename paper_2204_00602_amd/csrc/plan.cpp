@@ -164,6 +164,8 @@ struct slos_plan_s {
     double *d_partials = nullptr;
     int64_t n_partials = 0;
     uint32_t *d_tickets = nullptr;    // SLOS_XCDS ticket counters per layer
+    double *d_cdf = nullptr;          // block prefix of the last slos_cdf input (nb + 1)
+    int64_t *d_pk_ends = nullptr;     // C(K+n-1, n) for K = 1..m
     // differentiation (SLOS_KEEP_LAYERS plans)
     std::vector<std::vector<BwdUnit>> units;   // per layer
     std::vector<uint32_t> succ;                // inner successor tables
@@ -379,6 +381,10 @@ struct slos_plan_s {
         f(d_partials);
         f(d_tickets);
         d_tickets = nullptr;
+        f(d_cdf);
+        d_cdf = nullptr;
+        f(d_pk_ends);
+        d_pk_ends = nullptr;
         f(d_units);
         f(d_succ);
         f(d_hbase);
@@ -737,6 +743,17 @@ int slos_plan_ex(int m, int n, const int32_t *input_state, int flags, const slos
         delete p;
         return rc;
     }
+    {
+        const uint64_t nb = (p->Nk[n] + SLOS_CDF_BLOCK - 1) / SLOS_CDF_BLOCK;
+        std::vector<int64_t> ends(m);
+        for (int K = 1; K <= m; ++K) ends[K - 1] = (int64_t)p->B(K + n - 1, n);
+        if ((rc = alloc_dev((void **)&p->d_cdf, (nb + 1) * sizeof(double), "cumulative probability table")) ||
+            (rc = dev_upload(&p->d_pk_ends, ends.data(), ends.size(), "marginal bounds"))) {
+            p->free_device();
+            delete p;
+            return rc;
+        }
+    }
     if (p->keep && n > 0) {
         std::vector<BwdUnit> allu;
         p->unit_off.assign(n + 2, 0);
@@ -1022,6 +1039,38 @@ int slos_amplitudes(slos_plan_t p, const void *U, void *out, double *sum_p, void
 int slos_probs(slos_plan_t p, const void *U, void *probs, double *sum_p, void *stream)
 {
     return run_forward(p, U, probs, sum_p, stream, SLOS_MODE_PROB);
+}
+
+int slos_cdf(slos_plan_t p, const void *probs, void *stream)
+{
+    int rc = check_plan(p);
+    if (rc) return rc;
+    if (!probs) return fail(SLOS_ERR_INVALID_ARG, "probs is NULL");
+    int e = slos_launch_cdf(probs, p->c64 ? 1 : 0, (int64_t)p->Nk[p->n], p->d_cdf, stream);
+    if (e) return hip_fail((hipError_t)e, "cumulative probability kernels");
+    return SLOS_OK;
+}
+
+int slos_marginals(slos_plan_t p, const void *probs, double *pk, void *stream)
+{
+    int rc = check_plan(p);
+    if (rc) return rc;
+    if (!probs || !pk) return fail(SLOS_ERR_INVALID_ARG, "probs and pk must be device pointers");
+    int e = slos_launch_marginals(probs, p->c64 ? 1 : 0, p->d_cdf, p->d_pk_ends, p->m, pk, stream);
+    if (e) return hip_fail((hipError_t)e, "marginal kernel");
+    return SLOS_OK;
+}
+
+int slos_sample(slos_plan_t p, const void *probs, const double *r, int64_t count, int64_t *ranks, void *stream)
+{
+    int rc = check_plan(p);
+    if (rc) return rc;
+    if (count < 0) return fail(SLOS_ERR_INVALID_ARG, "count = %lld is negative", (long long)count);
+    if (count == 0) return SLOS_OK;
+    if (!probs || !r || !ranks) return fail(SLOS_ERR_INVALID_ARG, "probs, r and ranks must be device pointers");
+    int e = slos_launch_sample(probs, p->c64 ? 1 : 0, (int64_t)p->Nk[p->n], p->d_cdf, r, count, ranks, stream);
+    if (e) return hip_fail((hipError_t)e, "sampling kernel");
+    return SLOS_OK;
 }
 
 } // extern "C"

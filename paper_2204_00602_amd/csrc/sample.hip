@@ -1,0 +1,185 @@
+// HIP kernels (gfx950): weak simulation from the strong one.
+//
+// The sampler the paper builds on its strong back-ends (Section 3.2) draws
+// outputs S with probability P(S).  From the full distribution in colex order
+// this is an inverse-CDF lookup: for a uniform r in [0, 1) the sample is the
+// first S whose cumulative probability exceeds r * sum P.  The same prefix sums
+// give the partial certificate of Eq. eqpk: P(K), the probability that modes
+// K..m-1 are empty, is the sum over the first C(K+n-1, n) states (those states
+// form a colex prefix).
+//
+// Layout: P is cut into blocks of SLOS_CDF_BLOCK states.  cdf_block_kernel sums
+// each block in FP64 (one wave per block, fixed order); cdf_scan_kernel turns
+// the block sums into an exclusive prefix bp[0..nb] (bp[nb] = sum P) in one
+// workgroup, in a fixed order, so the result is reproducible.  A sample finds
+// its block with a 64-way search over bp and then its state with wave scans of
+// the block in 64-state chunks.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "slos_internal.h"
+
+namespace {
+
+constexpr int kChunks = SLOS_CDF_BLOCK / 64;
+
+template <typename T>
+__global__ __launch_bounds__(256) void cdf_block_kernel(const T *__restrict__ P, int64_t M, int64_t nb,
+                                                        double *__restrict__ bp)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t gw = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
+    for (int64_t b = gw; b < nb; b += nw) {
+        const int64_t base = b * SLOS_CDF_BLOCK;
+        double s = 0.0;
+#pragma unroll 4
+        for (int i = 0; i < kChunks; ++i) {
+            const int64_t x = base + i * 64 + lane;
+            if (x < M) s += (double)__builtin_nontemporal_load(&P[x]);
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+        if (lane == 0) bp[b] = s;
+    }
+}
+
+// In place: bp[0..nb) block sums -> exclusive prefix, bp[nb] = total.
+__global__ __launch_bounds__(1024) void cdf_scan_kernel(double *__restrict__ bp, int64_t nb)
+{
+    __shared__ double part[1024];
+    const int t = threadIdx.x;
+    const int64_t per = (nb + 1023) / 1024;
+    const int64_t lo = min((int64_t)t * per, nb), hi = min(lo + per, nb);
+    double s = 0.0;
+    for (int64_t i = lo; i < hi; ++i) s += bp[i];
+    part[t] = s;
+    __syncthreads();
+    if (t == 0) {
+        double run = 0.0;
+        for (int i = 0; i < 1024; ++i) {
+            const double v = part[i];
+            part[i] = run;
+            run += v;
+        }
+        bp[nb] = run;
+    }
+    __syncthreads();
+    double run = part[t];
+    for (int64_t i = lo; i < hi; ++i) {
+        const double v = bp[i];
+        bp[i] = run;
+        run += v;
+    }
+}
+
+// pk[K-1] = sum of P over the first ends[K-1] states, K = 1..m; one wave per K.
+template <typename T>
+__global__ __launch_bounds__(256) void marginal_kernel(const T *__restrict__ P, const double *__restrict__ bp,
+                                                       const int64_t *__restrict__ ends, int m,
+                                                       double *__restrict__ pk)
+{
+    const int lane = threadIdx.x & 63;
+    const int K = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (K >= m) return;
+    const int64_t e = ends[K];
+    const int64_t b = e / SLOS_CDF_BLOCK;
+    double s = 0.0;
+    for (int64_t x = b * SLOS_CDF_BLOCK + lane; x < e; x += 64) s += (double)P[x];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if (lane == 0) pk[K] = bp[b] + s;
+}
+
+// One wave per sample: ranks[s] = first state whose cumulative P exceeds r[s] * total.
+template <typename T>
+__global__ __launch_bounds__(256) void sample_kernel(const T *__restrict__ P, int64_t M, const double *__restrict__ bp,
+                                                     int64_t nb, const double *__restrict__ r, int64_t count,
+                                                     int64_t *__restrict__ ranks)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t gw = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
+    const double total = bp[nb];
+    for (int64_t sidx = gw; sidx < count; sidx += nw) {
+        const double t = r[sidx] * total;
+        // largest block b in [0, nb) with bp[b] <= t: 64-way search (bp is
+        // non-decreasing and bp[0] = 0 <= t, so the predicate holds on a prefix)
+        int64_t lo = 0, hi = nb;
+        while (hi - lo > 1) {
+            const int64_t step = (hi - lo + 63) / 64;
+            const int64_t pos = lo + (int64_t)lane * step;
+            const bool ok = pos < hi && bp[pos] <= t;
+            const uint64_t bal = __ballot(ok);
+            const int last = bal ? 63 - __builtin_clzll(bal) : 0;  // lane 0 holds for r >= 0
+            lo = lo + (int64_t)last * step;
+            hi = min(lo + step, hi);
+        }
+        // first state of block lo whose running sum exceeds t
+        const int64_t base = lo * SLOS_CDF_BLOCK;
+        double run = bp[lo];
+        int64_t found = -1, last_pos = -1;
+        for (int i = 0; i < kChunks && found < 0; ++i) {
+            const int64_t x = base + i * 64 + lane;
+            const double v = x < M ? (double)P[x] : 0.0;
+            double c = v;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const double u = __shfl_up(c, o, 64);
+                if (lane >= o) c += u;
+            }
+            const uint64_t cross = __ballot(run + c > t && v > 0.0);
+            const uint64_t pos = __ballot(v > 0.0);
+            if (cross) found = base + i * 64 + __builtin_ctzll(cross);
+            if (pos) last_pos = base + i * 64 + 63 - __builtin_clzll(pos);
+            run += __shfl(c, 63, 64);
+        }
+        // rounding can leave the crossing past the block's recomputed sum:
+        // take the block's last state of non-zero probability
+        if (found < 0) found = last_pos >= 0 ? last_pos : min(base, M - 1);
+        if (lane == 0) ranks[sidx] = found;
+    }
+}
+
+} // namespace
+
+int slos_launch_cdf(const void *P, int c64, int64_t M, double *bp, void *stream)
+{
+    const int64_t nb = (M + SLOS_CDF_BLOCK - 1) / SLOS_CDF_BLOCK;
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((nb + 3) / 4, 8192));
+    hipStream_t s = (hipStream_t)stream;
+    if (c64)
+        hipLaunchKernelGGL(cdf_block_kernel<float>, dim3(grid), dim3(256), 0, s, (const float *)P, M, nb, bp);
+    else
+        hipLaunchKernelGGL(cdf_block_kernel<double>, dim3(grid), dim3(256), 0, s, (const double *)P, M, nb, bp);
+    hipLaunchKernelGGL(cdf_scan_kernel, dim3(1), dim3(1024), 0, s, bp, nb);
+    return (int)hipGetLastError();
+}
+
+int slos_launch_marginals(const void *P, int c64, const double *bp, const int64_t *ends, int m, double *pk,
+                          void *stream)
+{
+    const int grid = (m + 3) / 4;
+    hipStream_t s = (hipStream_t)stream;
+    if (c64)
+        hipLaunchKernelGGL(marginal_kernel<float>, dim3(grid), dim3(256), 0, s, (const float *)P, bp, ends, m, pk);
+    else
+        hipLaunchKernelGGL(marginal_kernel<double>, dim3(grid), dim3(256), 0, s, (const double *)P, bp, ends, m, pk);
+    return (int)hipGetLastError();
+}
+
+int slos_launch_sample(const void *P, int c64, int64_t M, const double *bp, const double *r, int64_t count,
+                       int64_t *ranks, void *stream)
+{
+    const int64_t nb = (M + SLOS_CDF_BLOCK - 1) / SLOS_CDF_BLOCK;
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((count + 3) / 4, 8192));
+    hipStream_t s = (hipStream_t)stream;
+    if (c64)
+        hipLaunchKernelGGL(sample_kernel<float>, dim3(grid), dim3(256), 0, s, (const float *)P, M, bp, nb, r, count,
+                           ranks);
+    else
+        hipLaunchKernelGGL(sample_kernel<double>, dim3(grid), dim3(256), 0, s, (const double *)P, M, bp, nb, r,
+                           count, ranks);
+    return (int)hipGetLastError();
+}

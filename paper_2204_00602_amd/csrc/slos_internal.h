@@ -67,6 +67,8 @@ static_assert(sizeof(LeafDescWide) == 336, "LeafDescWide must stay 336 bytes");
 // Bytes of readable slack after every layer buffer: the low-block staging
 // copies whole 16-byte chunks in 1 KiB wave-wide steps.
 #define SLOS_BUFFER_SLACK 2048
+// states per block of the cumulative-probability table (multiple of 64)
+#define SLOS_CDF_BLOCK 1024
 // accumulation modes of the c64 layer kernel
 #define SLOS_COMP_NONE 0
 #define SLOS_COMP_BIASED 1
@@ -251,3 +253,9 @@ struct BatchParams {
 int slos_launch_batch(const BatchParams &p, int c64, int rr, int threads, int grid, void *stream);
 int slos_prepare_batch_kernels(void);
 
+// weak simulation (sample.hip)
+int slos_launch_cdf(const void *P, int c64, int64_t M, double *bp, void *stream);
+int slos_launch_marginals(const void *P, int c64, const double *bp, const int64_t *ends, int m, double *pk,
+                          void *stream);
+int slos_launch_sample(const void *P, int c64, int64_t M, const double *bp, const double *r, int64_t count,
+                       int64_t *ranks, void *stream);

@@ -74,6 +74,9 @@ def lib():
     L.slos_amplitudes.argtypes = [vp, vp, vp, vp, vp]
     L.slos_probs.argtypes = [vp, vp, vp, vp, vp]
     L.slos_backward.argtypes = [vp, vp, vp, vp, vp]
+    L.slos_cdf.argtypes = [vp, vp, vp]
+    L.slos_marginals.argtypes = [vp, vp, vp, vp]
+    L.slos_sample.argtypes = [vp, vp, vp, ctypes.c_int64, vp, vp]
     L.slos_mesh_unitary.argtypes = [ctypes.c_int, ctypes.c_int, vp, vp, ctypes.c_int, vp]
     L.slos_mesh_backward.argtypes = [ctypes.c_int, ctypes.c_int, vp, vp, vp, ctypes.c_int, vp]
     L.slos_batch_plan.argtypes = [ctypes.c_int, i32p, i32p, ctypes.c_int, ctypes.POINTER(Options),
@@ -90,7 +93,7 @@ def lib():
     L.slos_last_error.restype = ctypes.c_char_p
     for name in ("slos_fock_count", "slos_fock_rank", "slos_fock_unrank", "slos_plan",
                  "slos_plan_ex", "slos_plan_info", "slos_plan_leaf", "slos_amplitudes",
-                 "slos_probs", "slos_plan_set_timing", "slos_plan_layer_ms", "slos_backward",
+                 "slos_probs", "slos_cdf", "slos_marginals", "slos_sample", "slos_plan_set_timing", "slos_plan_layer_ms", "slos_backward",
                  "slos_mesh_unitary", "slos_mesh_backward", "slos_batch_plan", "slos_batch_offsets",
                  "slos_batch_amplitudes", "slos_batch_capture", "slos_batch_replay"):
         getattr(L, name).restype = ctypes.c_int
@@ -279,6 +282,38 @@ class Plan:
         _check(self._lib.slos_backward(self._h, U.data_ptr(), grad_a.data_ptr(), grad_U.data_ptr(),
                                        _stream_ptr(stream)))
         return grad_U
+
+    # ---- weak simulation ----------------------------------------------------
+    def _check_probs(self, probs):
+        import torch
+        rdt = torch.float32 if self.dtype == "c64" else torch.float64
+        if probs.dtype != rdt or probs.numel() != self.num_outputs or probs.device.type != "cuda" \
+                or not probs.is_contiguous():
+            raise ValueError(f"probs must be a contiguous {rdt} device tensor of {self.num_outputs} values")
+
+    def cdf(self, probs, stream=None):
+        """Build the plan's cumulative table for `probs` (see slos_cdf)."""
+        self._check_probs(probs)
+        _check(self._lib.slos_cdf(self._h, probs.data_ptr(), _stream_ptr(stream)))
+
+    def marginals(self, probs, stream=None):
+        """P(K) for K = 1..m (Eq. eqpk) as an FP64 device tensor; call cdf(probs) first."""
+        import torch
+        self._check_probs(probs)
+        pk = torch.empty(self.m, dtype=torch.float64, device=probs.device)
+        _check(self._lib.slos_marginals(self._h, probs.data_ptr(), pk.data_ptr(), _stream_ptr(stream)))
+        return pk
+
+    def sample(self, probs, r, stream=None):
+        """Colex ranks of the outputs drawn for uniforms r (FP64 device tensor); call cdf(probs) first."""
+        import torch
+        self._check_probs(probs)
+        if r.dtype != torch.float64 or r.device.type != "cuda" or not r.is_contiguous():
+            raise ValueError("r must be a contiguous float64 device tensor")
+        ranks = torch.empty(r.numel(), dtype=torch.int64, device=r.device)
+        _check(self._lib.slos_sample(self._h, probs.data_ptr(), r.data_ptr(), r.numel(), ranks.data_ptr(),
+                                     _stream_ptr(stream)))
+        return ranks
 
     def rank(self, state) -> int:
         s = _state_arr(state, self.m)

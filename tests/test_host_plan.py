@@ -173,3 +173,12 @@ def test_batch_plan_validation():
                              ctypes.byref(h)) == -1
     assert L.slos_batch_plan(2, ms.ctypes.data_as(i32p), ok.ctypes.data_as(i32p), 0, None, ctypes.byref(h)) == -4
     L.slos_batch_destroy(None)
+
+
+def test_sampling_calls_validate_arguments():
+    L = slos.lib()
+    assert L.slos_cdf(None, None, None) == -1
+    assert L.slos_marginals(None, None, None, None) == -1
+    assert L.slos_sample(None, None, None, 1, None, None) == -1
+    p = slos.Plan([1, 1, 0], "c64", host_only=True)
+    assert L.slos_cdf(p._h, None, None) == -1
