@@ -186,6 +186,46 @@ def time_gradient(torch, slos, steps, warmup, batch=64, m=12, n=6, targets=200):
     }
 
 
+def time_sampling(torch, slos, T, U_np, steps, warmup, samples=1 << 20):
+    """Weak simulation from the strong one at m=24, n=12 (complex64 P): the
+    cumulative table (reads P once), P(K) for every K (Eq. eqpk) and 2^20
+    inverse-CDF samples from seeded uniforms.  P is resident before timing."""
+    plan = slos.Plan(T, "c64")
+    Ud = torch.from_numpy(U_np).to(torch.complex64).cuda()
+    P = plan.probs(Ud)
+    r = torch.from_numpy(np.random.default_rng(7).random(samples)).cuda()
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    t_cdf = t_pk = t_smp = 0.0
+    for it in range(warmup + steps):
+        ev[0].record(stream)
+        plan.cdf(P, stream=stream)
+        ev[1].record(stream)
+        pk = plan.marginals(P, stream=stream)
+        ev[2].record(stream)
+        ranks = plan.sample(P, r, stream=stream)
+        ev[3].record(stream)
+        torch.cuda.synchronize()
+        if it >= warmup:
+            t_cdf += ev[0].elapsed_time(ev[1])
+            t_pk += ev[1].elapsed_time(ev[2])
+            t_smp += ev[2].elapsed_time(ev[3])
+    t_cdf, t_pk, t_smp = t_cdf / steps, t_pk / steps, t_smp / steps
+    pbytes = 4 * plan.num_outputs
+    res = {
+        "workload": f"m=24 n=12 complex64 P ({plan.num_outputs} states): cumulative table, P(K) for K=1..24, "
+                    f"{samples} inverse-CDF samples",
+        "cdf_ms": t_cdf, "cdf_GBps": pbytes / (t_cdf * 1e-3) / 1e9,
+        "cdf_roofline_frac": pbytes / (t_cdf * 1e-3) / 1e9 / HBM_PEAK_GBPS,
+        "marginals_ms": t_pk, "sample_ms": t_smp, "samples_per_s": samples / (t_smp * 1e-3),
+        "P_K_last": float(pk[-1].item()), "rank_max": int(ranks.max().item()),
+    }
+    plan.close()
+    del P
+    torch.cuda.empty_cache()
+    return res
+
+
 def cpu_baseline(U_np, T, target_s=20.0):
     """The oracle, untuned, on a bounded sample of the workload's outputs."""
     import oracle
@@ -325,6 +365,11 @@ def main():
         print("[bench] gradient workload: mesh m=12 n=6, 64 phase sets", file=sys.stderr, flush=True)
         line["gradient"] = time_gradient(torch, slos, max(3, args.steps // 4), 1)
         print(f"[bench] gradient: {line['gradient']['ms_per_batch']:.3f} ms/batch", file=sys.stderr, flush=True)
+        print("[bench] weak simulation: cumulative table, P(K), 2^20 samples", file=sys.stderr, flush=True)
+        line["sampling"] = time_sampling(torch, slos, T, U, args.steps, args.warmup)
+        sm = line["sampling"]
+        print(f"[bench] sampling: cdf {sm['cdf_ms']:.3f} ms, P(K) {sm['marginals_ms']:.3f} ms, "
+              f"samples {sm['sample_ms']:.3f} ms", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(U, T)

@@ -164,7 +164,7 @@ struct slos_plan_s {
     double *d_partials = nullptr;
     int64_t n_partials = 0;
     uint32_t *d_tickets = nullptr;    // SLOS_XCDS ticket counters per layer
-    double *d_cdf = nullptr;          // block prefix of the last slos_cdf input (nb + 1)
+    double *d_cdf = nullptr;          // block prefix of the last slos_cdf input (nb + 1), then run prefixes
     int64_t *d_pk_ends = nullptr;     // C(K+n-1, n) for K = 1..m
     // differentiation (SLOS_KEEP_LAYERS plans)
     std::vector<std::vector<BwdUnit>> units;   // per layer
@@ -745,9 +745,11 @@ int slos_plan_ex(int m, int n, const int32_t *input_state, int flags, const slos
     }
     {
         const uint64_t nb = (p->Nk[n] + SLOS_CDF_BLOCK - 1) / SLOS_CDF_BLOCK;
+        const uint64_t nsup = (nb + SLOS_CDF_BLOCK - 1) / SLOS_CDF_BLOCK;
         std::vector<int64_t> ends(m);
         for (int K = 1; K <= m; ++K) ends[K - 1] = (int64_t)p->B(K + n - 1, n);
-        if ((rc = alloc_dev((void **)&p->d_cdf, (nb + 1) * sizeof(double), "cumulative probability table")) ||
+        if ((rc = alloc_dev((void **)&p->d_cdf, (nb + 1 + nsup + 1) * sizeof(double),
+                            "cumulative probability table")) ||
             (rc = dev_upload(&p->d_pk_ends, ends.data(), ends.size(), "marginal bounds"))) {
             p->free_device();
             delete p;

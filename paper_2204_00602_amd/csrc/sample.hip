@@ -9,9 +9,11 @@
 // form a colex prefix).
 //
 // Layout: P is cut into blocks of SLOS_CDF_BLOCK states.  cdf_block_kernel sums
-// each block in FP64 (one wave per block, fixed order); cdf_scan_kernel turns
-// the block sums into an exclusive prefix bp[0..nb] (bp[nb] = sum P) in one
-// workgroup, in a fixed order, so the result is reproducible.  A sample finds
+// each block in FP64 (one wave per block, fixed order); runs of SLOS_CDF_BLOCK
+// block sums are summed again, those few run sums are scanned in one
+// workgroup, and cdf_fix_kernel turns the block sums into the exclusive prefix
+// bp[0..nb] (bp[nb] = sum P), every step in a fixed order, so the table is
+// reproducible.  A sample finds
 // its block with a 64-way search over bp and then its state with wave scans of
 // the block in 64-state chunks.
 #include <hip/hip_runtime.h>
@@ -34,44 +36,93 @@ __global__ __launch_bounds__(256) void cdf_block_kernel(const T *__restrict__ P,
     for (int64_t b = gw; b < nb; b += nw) {
         const int64_t base = b * SLOS_CDF_BLOCK;
         double s = 0.0;
-#pragma unroll 4
-        for (int i = 0; i < kChunks; ++i) {
+        T v[kChunks];
+#pragma unroll
+        for (int i = 0; i < kChunks; ++i) {  // all loads in flight, then a fixed-order sum
             const int64_t x = base + i * 64 + lane;
-            if (x < M) s += (double)__builtin_nontemporal_load(&P[x]);
+            v[i] = x < M ? __builtin_nontemporal_load(&P[x]) : (T)0;
         }
+#pragma unroll
+        for (int i = 0; i < kChunks; ++i) s += (double)v[i];
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
         if (lane == 0) bp[b] = s;
     }
 }
 
-// In place: bp[0..nb) block sums -> exclusive prefix, bp[nb] = total.
-__global__ __launch_bounds__(1024) void cdf_scan_kernel(double *__restrict__ bp, int64_t nb)
+// Sum of each run of SLOS_CDF_BLOCK consecutive entries of v[0..nv): one wave per run.
+__global__ __launch_bounds__(256) void cdf_super_kernel(const double *__restrict__ v, int64_t nv, int64_t nsup,
+                                                        double *__restrict__ out)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t gw = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
+    for (int64_t b = gw; b < nsup; b += nw) {
+        double s = 0.0;
+        for (int i = 0; i < kChunks; ++i) {
+            const int64_t x = b * SLOS_CDF_BLOCK + i * 64 + lane;
+            if (x < nv) s += v[x];
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+        if (lane == 0) out[b] = s;
+    }
+}
+
+// In place, one workgroup: v[0..nv) -> exclusive prefix, v[nv] = total.
+__global__ __launch_bounds__(1024) void cdf_scan_kernel(double *__restrict__ v, int64_t nv)
 {
     __shared__ double part[1024];
     const int t = threadIdx.x;
-    const int64_t per = (nb + 1023) / 1024;
-    const int64_t lo = min((int64_t)t * per, nb), hi = min(lo + per, nb);
+    const int64_t per = (nv + 1023) / 1024;
+    const int64_t lo = min((int64_t)t * per, nv), hi = min(lo + per, nv);
     double s = 0.0;
-    for (int64_t i = lo; i < hi; ++i) s += bp[i];
+    for (int64_t i = lo; i < hi; ++i) s += v[i];
     part[t] = s;
     __syncthreads();
     if (t == 0) {
         double run = 0.0;
         for (int i = 0; i < 1024; ++i) {
-            const double v = part[i];
+            const double x = part[i];
             part[i] = run;
-            run += v;
+            run += x;
         }
-        bp[nb] = run;
+        v[nv] = run;
     }
     __syncthreads();
     double run = part[t];
     for (int64_t i = lo; i < hi; ++i) {
-        const double v = bp[i];
-        bp[i] = run;
-        run += v;
+        const double x = v[i];
+        v[i] = run;
+        run += x;
     }
+}
+
+// Block sums -> exclusive prefix: each wave takes one run of SLOS_CDF_BLOCK
+// block sums, starts from that run's prefix sp[run] and scans it in chunks of
+// 64 (wave scans in a fixed order).  bp[nb] = total.
+__global__ __launch_bounds__(256) void cdf_fix_kernel(double *__restrict__ bp, int64_t nb,
+                                                      const double *__restrict__ sp, int64_t nsup)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t gw = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
+    for (int64_t b = gw; b < nsup; b += nw) {
+        double run = sp[b];
+        for (int i = 0; i < kChunks; ++i) {
+            const int64_t x = b * SLOS_CDF_BLOCK + i * 64 + lane;
+            const double v = x < nb ? bp[x] : 0.0;
+            double c = v;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const double u = __shfl_up(c, o, 64);
+                if (lane >= o) c += u;
+            }
+            if (x < nb) bp[x] = run + (c - v);
+            run += __shfl(c, 63, 64);
+        }
+    }
+    if (gw == 0 && lane == 0) bp[nb] = sp[nsup];
 }
 
 // pk[K-1] = sum of P over the first ends[K-1] states, K = 1..m; one wave per K.
@@ -147,13 +198,18 @@ __global__ __launch_bounds__(256) void sample_kernel(const T *__restrict__ P, in
 int slos_launch_cdf(const void *P, int c64, int64_t M, double *bp, void *stream)
 {
     const int64_t nb = (M + SLOS_CDF_BLOCK - 1) / SLOS_CDF_BLOCK;
+    const int64_t nsup = (nb + SLOS_CDF_BLOCK - 1) / SLOS_CDF_BLOCK;
+    double *sp = bp + nb + 1;  // nsup + 1 run prefixes after the table
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((nb + 3) / 4, 8192));
+    const int gsup = (int)std::max<int64_t>(1, std::min<int64_t>((nsup + 3) / 4, 8192));
     hipStream_t s = (hipStream_t)stream;
     if (c64)
         hipLaunchKernelGGL(cdf_block_kernel<float>, dim3(grid), dim3(256), 0, s, (const float *)P, M, nb, bp);
     else
         hipLaunchKernelGGL(cdf_block_kernel<double>, dim3(grid), dim3(256), 0, s, (const double *)P, M, nb, bp);
-    hipLaunchKernelGGL(cdf_scan_kernel, dim3(1), dim3(1024), 0, s, bp, nb);
+    hipLaunchKernelGGL(cdf_super_kernel, dim3(gsup), dim3(256), 0, s, (const double *)bp, nb, nsup, sp);
+    hipLaunchKernelGGL(cdf_scan_kernel, dim3(1), dim3(1024), 0, s, sp, nsup);
+    hipLaunchKernelGGL(cdf_fix_kernel, dim3(gsup), dim3(256), 0, s, bp, nb, (const double *)sp, nsup);
     return (int)hipGetLastError();
 }
 
