@@ -157,6 +157,42 @@ def inverse_cdf_sample(probs, r) -> np.ndarray:
     return np.minimum(idx, len(c) - 1).astype(np.int64)
 
 
+def postselect(probs, states, group_of_mode, count_min, count_max):
+    """Post-selection over mode groups (heralds and post-selection functions of
+    a Processor, Section 3.2.7 and Appendix Processor): state S is kept iff for
+    every group g, count_min[g] <= sum of s_j over the modes j of group g <=
+    count_max[g] (group -1: unconstrained mode).  Returns (kept mask, sum of P
+    over the kept states)."""
+    states = np.asarray(states)
+    gm = np.asarray(group_of_mode)
+    keep = np.ones(states.shape[0], dtype=bool)
+    for g in range(len(count_min)):
+        c = states[:, gm == g].sum(axis=1)
+        keep &= (c >= count_min[g]) & (c <= count_max[g])
+    return keep, float(np.sum(np.asarray(probs, dtype=np.float64)[keep]))
+
+
+def analyze(U, inputs, outputs, expected, group_of_mode, count_min, count_max):
+    """Analyzer quantities for logical input/output states: per input, the
+    post-selected probability perf(in) and the table P(out | in) / perf(in)
+    over the listed outputs; performance = mean perf(in), fidelity = mean of
+    the table entry of each input's expected output.  Returns (table,
+    performance, fidelity)."""
+    m = len(group_of_mode)
+    n = int(np.sum(inputs[0]))
+    S = fock_states(m, n)
+    table = np.zeros((len(inputs), len(outputs)))
+    perfs, fids = [], []
+    for a, T in enumerate(inputs):
+        P = probabilities(U, T, S)
+        _, perf = postselect(P, S, group_of_mode, count_min, count_max)
+        Po = probabilities(U, T, np.asarray(outputs))
+        table[a] = Po / perf
+        perfs.append(perf)
+        fids.append(table[a, expected[a]])
+    return table, float(np.mean(perfs)), float(np.mean(fids))
+
+
 def haar_pk_mean(K: int, m: int, n: int) -> float:
     """Haar average of P(K): K(K+1)..(K+n-1) / (m(m+1)..(m+n-1)) (Eq. eqhaarpk)."""
     num = 1.0

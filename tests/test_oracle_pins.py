@@ -397,3 +397,48 @@ def test_inverse_cdf_sample_frequencies_match_probabilities():
     Z = np.zeros(6)
     Z[4] = 1.0
     assert set(oracle.inverse_cdf_sample(Z, r[:1000]).tolist()) == {4}
+
+
+# ---------------------------------------------------------------- post-selection
+
+def _cnot_groups(heralded):
+    # Analysis code of the CNOT section: one photon in modes {1,2}, one in {3,4};
+    # the Processor appendix adds empty auxiliary modes 0 and 5 (heralds)
+    if heralded:
+        return [2, 0, 0, 1, 1, 3], [1, 1, 0, 0], [1, 1, 0, 0]
+    return [-1, 0, 0, 1, 1, -1], [1, 1], [1, 1]
+
+
+@pytest.mark.parametrize("heralded", [False, True])
+def test_cnot_analyzer_matches_printed_table(golden_dir, heralded):
+    """Fig. ralph_cnot_simul_result: the truth table, performance 1/9, fidelity 100%."""
+    g = json.load(open(os.path.join(golden_dir, "ralph_cnot.json")))
+    U = _cnot_unitary(g)
+    names = sorted(g["logical_states"])
+    ins = [np.array(g["logical_states"][k], np.int32) for k in names]
+    expected = [names.index(g["expected_map"][k]) for k in names]
+    gm, lo, hi = _cnot_groups(heralded)
+    table, perf, fid = oracle.analyze(U, ins, ins, expected, gm, lo, hi)
+    want = np.zeros((4, 4))
+    for a, b in enumerate(expected):
+        want[a, b] = 1.0
+    assert np.allclose(table, want, atol=1e-14)
+    assert perf == pytest.approx(g["performance"][0] / g["performance"][1], abs=1e-15)
+    assert fid == pytest.approx(1.0, abs=1e-14)
+
+
+def test_postselect_partitions_the_distribution():
+    """Accepting nothing-constrained keeps everything; the events {mode 0 holds c},
+    c = 0..n, partition S and their sums add up to sum P."""
+    U = inputs.haar_unitary(5, 8)
+    T = np.array([1, 0, 1, 1, 0])
+    S = oracle.fock_states(5, 3)
+    P = oracle.probabilities(U, T, S)
+    keep, tot = oracle.postselect(P, S, [-1] * 5, [], [])
+    assert keep.all() and tot == pytest.approx(1.0, abs=1e-13)
+    parts = [oracle.postselect(P, S, [0, -1, -1, -1, -1], [c], [c]) for c in range(4)]
+    assert sum(t for _, t in parts) == pytest.approx(1.0, abs=1e-13)
+    assert np.array_equal(sum(k.astype(int) for k, _ in parts), np.ones(len(S), int))
+    # an empty top-mode group is Eq. eqpk's event
+    _, pk = oracle.postselect(P, S, [-1, -1, 0, 0, 0], [0], [0])
+    assert pk == pytest.approx(oracle.partial_certificate(P, S, 2), abs=1e-15)
