@@ -179,6 +179,28 @@ int slos_marginals(slos_plan_t plan, const void *probs, double *pk, void *stream
 int slos_sample(slos_plan_t plan, const void *probs, const double *r, int64_t count, int64_t *ranks,
                 void *stream);
 
+/* ---- post-selection ------------------------------------------------------------ */
+
+/*
+ * Heralds and post-selection (Section 3.2.7, the CNOT analysis; Processor
+ * appendix) as a conjunction over groups of modes: output S is kept iff for
+ * every group g, count_min[g] <= sum of s_j over the modes j with
+ * group_of_mode[j] == g <= count_max[g].  group_of_mode: host, m ints, -1 for
+ * an unconstrained mode (NULL: no constraint); count_min/count_max: host,
+ * ngroups ints each, 0 <= min <= max <= 255; ngroups <= 16.
+ * probs: device, M values (fp32 for C64, fp64 for C128), colex order.
+ * kept_sum (device, 1 double) = sum of P over the kept outputs (the
+ * performance of a post-selected gate), summed in FP64 in a fixed order.
+ * masked (device, M values, or NULL) receives P with the dropped outputs set
+ * to 0 (e.g. for slos_cdf / slos_sample over the post-selected distribution).
+ * ranks (device int64, nranks) / table (device FP64, nranks): table[i] =
+ * P(ranks[i]) / kept_sum when output ranks[i] is kept, else 0: the rows of
+ * the Analyzer's conditional table.
+ */
+int slos_postselect(slos_plan_t plan, const void *probs, const int32_t *group_of_mode, int ngroups,
+                    const int32_t *count_min, const int32_t *count_max, double *kept_sum, void *masked,
+                    const int64_t *ranks, int64_t nranks, double *table, void *stream);
+
 /* ---- differentiation ---------------------------------------------------------- */
 
 /*

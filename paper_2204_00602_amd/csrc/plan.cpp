@@ -166,6 +166,7 @@ struct slos_plan_s {
     uint32_t *d_tickets = nullptr;    // SLOS_XCDS ticket counters per layer
     double *d_cdf = nullptr;          // block prefix of the last slos_cdf input (nb + 1), then run prefixes
     int64_t *d_pk_ends = nullptr;     // C(K+n-1, n) for K = 1..m
+    double *d_ps_partials = nullptr;  // post-selection partial sums + reduction stage
     // differentiation (SLOS_KEEP_LAYERS plans)
     std::vector<std::vector<BwdUnit>> units;   // per layer
     std::vector<uint32_t> succ;                // inner successor tables
@@ -385,6 +386,8 @@ struct slos_plan_s {
         d_cdf = nullptr;
         f(d_pk_ends);
         d_pk_ends = nullptr;
+        f(d_ps_partials);
+        d_ps_partials = nullptr;
         f(d_units);
         f(d_succ);
         f(d_hbase);
@@ -750,7 +753,9 @@ int slos_plan_ex(int m, int n, const int32_t *input_state, int flags, const slos
         for (int K = 1; K <= m; ++K) ends[K - 1] = (int64_t)p->B(K + n - 1, n);
         if ((rc = alloc_dev((void **)&p->d_cdf, (nb + 1 + nsup + 1) * sizeof(double),
                             "cumulative probability table")) ||
-            (rc = dev_upload(&p->d_pk_ends, ends.data(), ends.size(), "marginal bounds"))) {
+            (rc = dev_upload(&p->d_pk_ends, ends.data(), ends.size(), "marginal bounds")) ||
+            (rc = alloc_dev((void **)&p->d_ps_partials, (SLOS_PS_MAX_WAVES + SLOS_REDUCE_STAGE) * sizeof(double),
+                            "post-selection partial sums"))) {
             p->free_device();
             delete p;
             return rc;
@@ -1060,6 +1065,57 @@ int slos_marginals(slos_plan_t p, const void *probs, double *pk, void *stream)
     if (!probs || !pk) return fail(SLOS_ERR_INVALID_ARG, "probs and pk must be device pointers");
     int e = slos_launch_marginals(probs, p->c64 ? 1 : 0, p->d_cdf, p->d_pk_ends, p->m, pk, stream);
     if (e) return hip_fail((hipError_t)e, "marginal kernel");
+    return SLOS_OK;
+}
+
+int slos_postselect(slos_plan_t p, const void *probs, const int32_t *group_of_mode, int ngroups,
+                    const int32_t *count_min, const int32_t *count_max, double *kept_sum, void *masked,
+                    const int64_t *ranks, int64_t nranks, double *table, void *stream)
+{
+    int rc = check_plan(p);
+    if (rc) return rc;
+    if (!probs || !kept_sum) return fail(SLOS_ERR_INVALID_ARG, "probs and kept_sum must be device pointers");
+    if (ngroups < 0 || ngroups > SLOS_PS_MAX_GROUPS)
+        return fail(SLOS_ERR_INVALID_ARG, "ngroups = %d outside [0, %d]", ngroups, SLOS_PS_MAX_GROUPS);
+    if (ngroups > 0 && (!group_of_mode || !count_min || !count_max))
+        return fail(SLOS_ERR_INVALID_ARG, "groups need group_of_mode, count_min and count_max");
+    if (nranks < 0 || (nranks > 0 && (!ranks || !table)))
+        return fail(SLOS_ERR_INVALID_ARG, "nranks must be >= 0, with ranks and table when > 0");
+    PostselectParams ps{};
+    ps.P = probs;
+    ps.masked = masked;
+    ps.M = (int64_t)p->Nk[p->n];
+    ps.binom = p->d_binom;
+    ps.bstride = p->B.stride;
+    ps.m = p->m;
+    ps.n = p->n;
+    ps.ngroups = ngroups;
+    for (int j = 0; j < p->m; ++j) {
+        const int g = group_of_mode ? group_of_mode[j] : -1;
+        if (g < -1 || g >= ngroups)
+            return fail(SLOS_ERR_INVALID_ARG, "group_of_mode[%d] = %d outside [-1, ngroups)", j, g);
+        ps.group[j] = (int8_t)g;
+    }
+    for (int g = 0; g < ngroups; ++g) {
+        if (count_min[g] < 0 || count_max[g] > 255 || count_min[g] > count_max[g])
+            return fail(SLOS_ERR_INVALID_ARG, "group %d: need 0 <= count_min <= count_max <= 255", g);
+        ps.cmin[g] = (uint8_t)count_min[g];
+        ps.cmax[g] = (uint8_t)count_max[g];
+    }
+    const uint64_t M = (uint64_t)ps.M;
+    const uint64_t threads = std::min<uint64_t>((M + 63) / 64, (uint64_t)SLOS_PS_MAX_WAVES * 64);
+    ps.run = (M + threads - 1) / threads;
+    ps.partials = p->d_ps_partials;
+    int e = slos_launch_postselect(ps, p->c64 ? 1 : 0, stream);
+    if (e) return hip_fail((hipError_t)e, "post-selection kernel");
+    const uint64_t waves = (((M + ps.run - 1) / ps.run + 255) / 256) * 4;
+    e = slos_launch_reduce(p->d_ps_partials, (int64_t)waves, p->d_ps_partials + SLOS_PS_MAX_WAVES, kept_sum,
+                           stream);
+    if (e) return hip_fail((hipError_t)e, "post-selection sum");
+    if (nranks > 0) {
+        e = slos_launch_postselect_table(ps, p->c64 ? 1 : 0, ranks, nranks, kept_sum, table, stream);
+        if (e) return hip_fail((hipError_t)e, "post-selection table kernel");
+    }
     return SLOS_OK;
 }
 

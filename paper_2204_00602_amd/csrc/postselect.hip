@@ -1,0 +1,158 @@
+// HIP kernels (gfx950): post-selection over mode groups.
+//
+// A Processor keeps only the outputs that pass its heralds and post-selection
+// function (Section 3.2.7, the CNOT analysis, and the Processor appendix).  Here
+// the predicate is a conjunction over groups of modes: output S is kept iff
+// for every group g, count_min[g] <= sum_{j in g} s_j <= count_max[g].  The
+// kernels sum P over the kept outputs (the gate's performance), optionally
+// write P masked to the kept outputs, and turn a list of output ranks into the
+// post-selected conditional probabilities P(S) / sum_kept P.
+//
+// Each thread walks a contiguous run of colex ranks: it unranks the first
+// state with the binomial table and then steps to the colex successor, which
+// moves one photon from the lowest occupied mode a to a + 1 and the other
+// photons of mode a to mode 0.  The occupation vector and the group counts live
+// in the thread's LDS row.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "slos_internal.h"
+
+namespace {
+
+__device__ __forceinline__ uint64_t binom_at(const PostselectParams &p, int a, int b)
+{
+    return p.binom[(size_t)a * p.bstride + b];
+}
+
+// Occupations of colex rank `rank` of F(m, n) into t[0..m); rank = sum_r C(d_r + r - 1, r)
+// over the sorted photon modes d_1 <= .. <= d_n.
+__device__ void unrank(const PostselectParams &p, uint64_t rank, uint8_t *t)
+{
+    for (int j = 0; j < p.m; ++j) t[j] = 0;
+    int c = p.m + p.n - 2;
+    for (int r = p.n; r >= 1; --r) {
+        while (c >= r && binom_at(p, c, r) > rank) --c;
+        if (c < r - 1) c = r - 1;
+        rank -= (c >= r) ? binom_at(p, c, r) : 0;
+        t[c - (r - 1)] += 1;
+        --c;
+    }
+}
+
+__device__ __forceinline__ bool kept(const PostselectParams &p, const uint8_t *cnt)
+{
+    bool ok = true;
+    for (int g = 0; g < p.ngroups; ++g) ok = ok && cnt[g] >= p.cmin[g] && cnt[g] <= p.cmax[g];
+    return ok;
+}
+
+__device__ __forceinline__ void count_groups(const PostselectParams &p, const uint8_t *t, uint8_t *cnt)
+{
+    for (int g = 0; g < p.ngroups; ++g) cnt[g] = 0;
+    for (int j = 0; j < p.m; ++j)
+        if (p.group[j] >= 0) cnt[p.group[j]] += t[j];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void postselect_kernel(PostselectParams p)
+{
+    extern __shared__ unsigned char lds[];
+    uint8_t *t = lds + (size_t)threadIdx.x * (p.m + SLOS_PS_MAX_GROUPS);
+    uint8_t *cnt = t + p.m;
+    const int lane = threadIdx.x & 63;
+    const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t s0 = tid * p.run;
+    const uint64_t s1 = min(s0 + p.run, (uint64_t)p.M);
+    const T *P = (const T *)p.P;
+    T *out = (T *)p.masked;
+    double acc = 0.0;
+    if (s0 < s1) {
+        unrank(p, s0, t);
+        count_groups(p, t, cnt);
+        for (uint64_t s = s0; s < s1; ++s) {
+            const T v = P[s];
+            const bool ok = kept(p, cnt);
+            if (ok) acc += (double)v;
+            if (out) out[s] = ok ? v : (T)0;
+            if (s + 1 < s1) {
+                int a = 0;
+                while (t[a] == 0) ++a;  // a < m - 1: s is not the last state
+                const int c = t[a];
+                t[a] = 0;
+                t[a + 1] += 1;
+                t[0] += (uint8_t)(c - 1);
+                if (p.group[a] >= 0) cnt[p.group[a]] -= (uint8_t)c;
+                if (p.group[a + 1] >= 0) cnt[p.group[a + 1]] += 1;
+                if (p.group[0] >= 0) cnt[p.group[0]] += (uint8_t)(c - 1);
+            }
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if (lane == 0) p.partials[tid / 64] = acc;
+}
+
+// table[i] = P[ranks[i]] / sum_kept if output ranks[i] is kept, else 0.
+template <typename T>
+__global__ __launch_bounds__(64) void postselect_table_kernel(PostselectParams p, const int64_t *ranks,
+                                                              int64_t nranks, const double *sum, double *table)
+{
+    extern __shared__ unsigned char lds[];
+    uint8_t *t = lds + (size_t)threadIdx.x * (p.m + SLOS_PS_MAX_GROUPS);
+    uint8_t *cnt = t + p.m;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nranks) return;
+    const int64_t r = ranks[i];
+    if (r < 0 || r >= p.M) {
+        table[i] = 0.0;
+        return;
+    }
+    unrank(p, (uint64_t)r, t);
+    count_groups(p, t, cnt);
+    const double v = (double)((const T *)p.P)[r];
+    table[i] = kept(p, cnt) ? v / *sum : 0.0;
+}
+
+template <typename K>
+hipError_t allow_lds(K kernel, size_t bytes)
+{
+    static bool done = false;  // per instantiation
+    if (done || bytes <= 65536) return hipSuccess;
+    hipError_t e = hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e == hipSuccess) done = true;
+    return e;
+}
+
+} // namespace
+
+int slos_launch_postselect(const PostselectParams &p, int c64, void *stream)
+{
+    hipStream_t s = (hipStream_t)stream;
+    const uint64_t threads = (p.M + p.run - 1) / p.run;
+    const int grid = (int)((threads + 255) / 256);
+    const size_t lds = 256 * (size_t)(p.m + SLOS_PS_MAX_GROUPS);
+    hipError_t e = c64 ? allow_lds(postselect_kernel<float>, lds) : allow_lds(postselect_kernel<double>, lds);
+    if (e != hipSuccess) return (int)e;
+    if (c64)
+        hipLaunchKernelGGL(postselect_kernel<float>, dim3(grid), dim3(256), lds, s, p);
+    else
+        hipLaunchKernelGGL(postselect_kernel<double>, dim3(grid), dim3(256), lds, s, p);
+    return (int)hipGetLastError();
+}
+
+int slos_launch_postselect_table(const PostselectParams &p, int c64, const int64_t *ranks, int64_t nranks,
+                                 const double *sum, double *table, void *stream)
+{
+    hipStream_t s = (hipStream_t)stream;
+    const int grid = (int)((nranks + 63) / 64);
+    const size_t lds = 64 * (size_t)(p.m + SLOS_PS_MAX_GROUPS);
+    if (c64)
+        hipLaunchKernelGGL(postselect_table_kernel<float>, dim3(grid), dim3(64), lds, s, p, ranks, nranks, sum,
+                           table);
+    else
+        hipLaunchKernelGGL(postselect_table_kernel<double>, dim3(grid), dim3(64), lds, s, p, ranks, nranks, sum,
+                           table);
+    return (int)hipGetLastError();
+}

@@ -259,3 +259,22 @@ int slos_launch_marginals(const void *P, int c64, const double *bp, const int64_
                           void *stream);
 int slos_launch_sample(const void *P, int c64, int64_t M, const double *bp, const double *r, int64_t count,
                        int64_t *ranks, void *stream);
+
+// post-selection (postselect.hip)
+#define SLOS_PS_MAX_GROUPS 16
+#define SLOS_PS_MAX_WAVES 8192  // partial sums per post-selection launch
+struct PostselectParams {
+    const void *P;          // M probabilities (fp32 or fp64), colex order
+    void *masked;           // P masked to the kept outputs, or NULL
+    int64_t M;
+    const uint64_t *binom;  // binom[a * bstride + b] = C(a, b)
+    int bstride;
+    int m, n, ngroups;
+    uint64_t run;           // consecutive ranks per thread
+    double *partials;       // one FP64 partial per wave
+    int8_t group[256];      // group of each mode, -1: unconstrained
+    uint8_t cmin[SLOS_PS_MAX_GROUPS], cmax[SLOS_PS_MAX_GROUPS];
+};
+int slos_launch_postselect(const PostselectParams &p, int c64, void *stream);
+int slos_launch_postselect_table(const PostselectParams &p, int c64, const int64_t *ranks, int64_t nranks,
+                                 const double *sum, double *table, void *stream);

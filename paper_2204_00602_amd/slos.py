@@ -77,6 +77,7 @@ def lib():
     L.slos_cdf.argtypes = [vp, vp, vp]
     L.slos_marginals.argtypes = [vp, vp, vp, vp]
     L.slos_sample.argtypes = [vp, vp, vp, ctypes.c_int64, vp, vp]
+    L.slos_postselect.argtypes = [vp, vp, i32p, ctypes.c_int, i32p, i32p, vp, vp, vp, ctypes.c_int64, vp, vp]
     L.slos_mesh_unitary.argtypes = [ctypes.c_int, ctypes.c_int, vp, vp, ctypes.c_int, vp]
     L.slos_mesh_backward.argtypes = [ctypes.c_int, ctypes.c_int, vp, vp, vp, ctypes.c_int, vp]
     L.slos_batch_plan.argtypes = [ctypes.c_int, i32p, i32p, ctypes.c_int, ctypes.POINTER(Options),
@@ -93,7 +94,7 @@ def lib():
     L.slos_last_error.restype = ctypes.c_char_p
     for name in ("slos_fock_count", "slos_fock_rank", "slos_fock_unrank", "slos_plan",
                  "slos_plan_ex", "slos_plan_info", "slos_plan_leaf", "slos_amplitudes",
-                 "slos_probs", "slos_cdf", "slos_marginals", "slos_sample", "slos_plan_set_timing", "slos_plan_layer_ms", "slos_backward",
+                 "slos_probs", "slos_cdf", "slos_marginals", "slos_sample", "slos_postselect", "slos_plan_set_timing", "slos_plan_layer_ms", "slos_backward",
                  "slos_mesh_unitary", "slos_mesh_backward", "slos_batch_plan", "slos_batch_offsets",
                  "slos_batch_amplitudes", "slos_batch_capture", "slos_batch_replay"):
         getattr(L, name).restype = ctypes.c_int
@@ -314,6 +315,32 @@ class Plan:
         _check(self._lib.slos_sample(self._h, probs.data_ptr(), r.data_ptr(), r.numel(), ranks.data_ptr(),
                                      _stream_ptr(stream)))
         return ranks
+
+    def postselect(self, probs, group_of_mode, count_min, count_max, masked=False, ranks=None, stream=None):
+        """Keep the outputs whose mode groups hold count_min[g]..count_max[g]
+        photons (see slos_postselect).  Returns (kept_sum, masked P or None,
+        conditional table for `ranks` or None) as device tensors."""
+        import torch
+        self._check_probs(probs)
+        gm = np.ascontiguousarray(np.asarray(group_of_mode, dtype=np.int32).reshape(-1))
+        lo = np.ascontiguousarray(np.asarray(count_min, dtype=np.int32).reshape(-1))
+        hi = np.ascontiguousarray(np.asarray(count_max, dtype=np.int32).reshape(-1))
+        if gm.size != self.m or lo.size != hi.size:
+            raise ValueError("group_of_mode needs m entries and count_min/count_max one per group")
+        i32p = ctypes.POINTER(ctypes.c_int32)
+        kept = torch.zeros(1, dtype=torch.float64, device=probs.device)
+        out = torch.empty_like(probs) if masked else None
+        table = None
+        rptr, nr = None, 0
+        if ranks is not None:
+            ranks = torch.as_tensor(ranks, dtype=torch.int64, device=probs.device).contiguous()
+            table = torch.empty(ranks.numel(), dtype=torch.float64, device=probs.device)
+            rptr, nr = ranks.data_ptr(), ranks.numel()
+        _check(self._lib.slos_postselect(self._h, probs.data_ptr(), gm.ctypes.data_as(i32p), int(lo.size),
+                                         lo.ctypes.data_as(i32p), hi.ctypes.data_as(i32p), kept.data_ptr(),
+                                         None if out is None else out.data_ptr(), rptr, nr,
+                                         None if table is None else table.data_ptr(), _stream_ptr(stream)))
+        return kept, out, table
 
     def rank(self, state) -> int:
         s = _state_arr(state, self.m)

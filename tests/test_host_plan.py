@@ -182,3 +182,12 @@ def test_sampling_calls_validate_arguments():
     assert L.slos_sample(None, None, None, 1, None, None) == -1
     p = slos.Plan([1, 1, 0], "c64", host_only=True)
     assert L.slos_cdf(p._h, None, None) == -1
+
+
+def test_postselect_validates_arguments():
+    import ctypes
+    L = slos.lib()
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    assert L.slos_postselect(None, None, None, 0, None, None, None, None, None, 0, None, None) == -1
+    p = slos.Plan([1, 1, 0], "c64", host_only=True)
+    assert L.slos_postselect(p._h, None, None, 0, None, None, None, None, None, 0, None, None) == -1
