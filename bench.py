@@ -195,8 +195,10 @@ def time_sampling(torch, slos, T, U_np, steps, warmup, samples=1 << 20):
     P = plan.probs(Ud)
     r = torch.from_numpy(np.random.default_rng(7).random(samples)).cuda()
     stream = torch.cuda.current_stream()
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
-    t_cdf = t_pk = t_smp = 0.0
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+    t_cdf = t_pk = t_smp = t_ps = 0.0
+    # heralds/post-selection: one photon in modes {0,1}, at most one in {2,3}, modes 22-23 empty
+    gm = [0, 0, 1, 1] + [-1] * 18 + [2, 2]
     for it in range(warmup + steps):
         ev[0].record(stream)
         plan.cdf(P, stream=stream)
@@ -205,19 +207,24 @@ def time_sampling(torch, slos, T, U_np, steps, warmup, samples=1 << 20):
         ev[2].record(stream)
         ranks = plan.sample(P, r, stream=stream)
         ev[3].record(stream)
+        kept, _, _ = plan.postselect(P, gm, [1, 0, 0], [1, 1, 0], stream=stream)
+        ev[4].record(stream)
         torch.cuda.synchronize()
         if it >= warmup:
             t_cdf += ev[0].elapsed_time(ev[1])
             t_pk += ev[1].elapsed_time(ev[2])
             t_smp += ev[2].elapsed_time(ev[3])
-    t_cdf, t_pk, t_smp = t_cdf / steps, t_pk / steps, t_smp / steps
+            t_ps += ev[3].elapsed_time(ev[4])
+    t_cdf, t_pk, t_smp, t_ps = t_cdf / steps, t_pk / steps, t_smp / steps, t_ps / steps
     pbytes = 4 * plan.num_outputs
     res = {
         "workload": f"m=24 n=12 complex64 P ({plan.num_outputs} states): cumulative table, P(K) for K=1..24, "
-                    f"{samples} inverse-CDF samples",
+                    f"{samples} inverse-CDF samples, post-selection over 3 mode groups",
         "cdf_ms": t_cdf, "cdf_GBps": pbytes / (t_cdf * 1e-3) / 1e9,
         "cdf_roofline_frac": pbytes / (t_cdf * 1e-3) / 1e9 / HBM_PEAK_GBPS,
         "marginals_ms": t_pk, "sample_ms": t_smp, "samples_per_s": samples / (t_smp * 1e-3),
+        "postselect_ms": t_ps, "postselect_GBps": pbytes / (t_ps * 1e-3) / 1e9,
+        "postselect_kept": float(kept.item()),
         "P_K_last": float(pk[-1].item()), "rank_max": int(ranks.max().item()),
     }
     plan.close()
@@ -369,7 +376,8 @@ def main():
         line["sampling"] = time_sampling(torch, slos, T, U, args.steps, args.warmup)
         sm = line["sampling"]
         print(f"[bench] sampling: cdf {sm['cdf_ms']:.3f} ms, P(K) {sm['marginals_ms']:.3f} ms, "
-              f"samples {sm['sample_ms']:.3f} ms", file=sys.stderr, flush=True)
+              f"samples {sm['sample_ms']:.3f} ms, post-selection {sm['postselect_ms']:.3f} ms",
+              file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(U, T)

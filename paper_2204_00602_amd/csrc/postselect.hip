@@ -11,8 +11,9 @@
 // Each thread walks a contiguous run of colex ranks: it unranks the first
 // state with the binomial table and then steps to the colex successor, which
 // moves one photon from the lowest occupied mode a to a + 1 and the other
-// photons of mode a to mode 0.  The occupation vector and the group counts live
-// in the thread's LDS row.
+// photons of mode a to mode 0 (so the next lowest occupied mode is known
+// without a search).  The occupation vector and the group counts live in the
+// thread's LDS row; a count of out-of-range groups decides each state.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -20,6 +21,8 @@
 #include "slos_internal.h"
 
 namespace {
+
+constexpr int kPsHead = 256 + 2 * SLOS_PS_MAX_GROUPS;  // LDS bytes of the group table and count bounds
 
 __device__ __forceinline__ uint64_t binom_at(const PostselectParams &p, int a, int b)
 {
@@ -59,7 +62,17 @@ template <typename T>
 __global__ __launch_bounds__(256) void postselect_kernel(PostselectParams p)
 {
     extern __shared__ unsigned char lds[];
-    uint8_t *t = lds + (size_t)threadIdx.x * (p.m + SLOS_PS_MAX_GROUPS);
+    // the group table in LDS (per-lane lookups), then one row per thread:
+    // occupations t[0..m) and group counts cnt[0..SLOS_PS_MAX_GROUPS)
+    int8_t *grp = (int8_t *)lds;
+    uint8_t *lo = lds + 256, *hi = lo + SLOS_PS_MAX_GROUPS;
+    for (int j = threadIdx.x; j < 256; j += blockDim.x) grp[j] = p.group[j];
+    if (threadIdx.x < SLOS_PS_MAX_GROUPS) {
+        lo[threadIdx.x] = p.cmin[threadIdx.x];
+        hi[threadIdx.x] = p.cmax[threadIdx.x];
+    }
+    __syncthreads();
+    uint8_t *t = lds + kPsHead + (size_t)threadIdx.x * (p.m + SLOS_PS_MAX_GROUPS);
     uint8_t *cnt = t + p.m;
     const int lane = threadIdx.x & 63;
     const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -71,21 +84,36 @@ __global__ __launch_bounds__(256) void postselect_kernel(PostselectParams p)
     if (s0 < s1) {
         unrank(p, s0, t);
         count_groups(p, t, cnt);
+        // number of groups whose count is out of range; the state is kept iff 0
+        int viol = 0;
+        for (int g = 0; g < p.ngroups; ++g) viol += (cnt[g] < lo[g] || cnt[g] > hi[g]) ? 1 : 0;
+        auto move = [&](int j, int d) {
+            const int g = grp[j];
+            if (g >= 0) {
+                const int c0 = cnt[g], c1 = c0 + d;
+                viol += ((c1 < lo[g] || c1 > hi[g]) ? 1 : 0) - ((c0 < lo[g] || c0 > hi[g]) ? 1 : 0);
+                cnt[g] = (uint8_t)c1;
+            }
+        };
+        int a = 0;  // lowest occupied mode
+        while (a < p.m - 1 && t[a] == 0) ++a;
         for (uint64_t s = s0; s < s1; ++s) {
             const T v = P[s];
-            const bool ok = kept(p, cnt);
+            const bool ok = viol == 0;
             if (ok) acc += (double)v;
             if (out) out[s] = ok ? v : (T)0;
             if (s + 1 < s1) {
-                int a = 0;
-                while (t[a] == 0) ++a;  // a < m - 1: s is not the last state
+                // a < m - 1 since s is not the last state; modes below a are
+                // empty, so afterwards the lowest occupied mode is 0 if photons
+                // went back to mode 0, else a + 1
                 const int c = t[a];
                 t[a] = 0;
                 t[a + 1] += 1;
                 t[0] += (uint8_t)(c - 1);
-                if (p.group[a] >= 0) cnt[p.group[a]] -= (uint8_t)c;
-                if (p.group[a + 1] >= 0) cnt[p.group[a + 1]] += 1;
-                if (p.group[0] >= 0) cnt[p.group[0]] += (uint8_t)(c - 1);
+                move(a, -c);
+                move(a + 1, 1);
+                move(0, c - 1);
+                a = c > 1 ? 0 : a + 1;
             }
         }
     }
@@ -132,7 +160,7 @@ int slos_launch_postselect(const PostselectParams &p, int c64, void *stream)
     hipStream_t s = (hipStream_t)stream;
     const uint64_t threads = (p.M + p.run - 1) / p.run;
     const int grid = (int)((threads + 255) / 256);
-    const size_t lds = 256 * (size_t)(p.m + SLOS_PS_MAX_GROUPS);
+    const size_t lds = kPsHead + 256 * (size_t)(p.m + SLOS_PS_MAX_GROUPS);
     hipError_t e = c64 ? allow_lds(postselect_kernel<float>, lds) : allow_lds(postselect_kernel<double>, lds);
     if (e != hipSuccess) return (int)e;
     if (c64)
