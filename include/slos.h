@@ -88,6 +88,8 @@ typedef struct slos_options {
                                 (default 128; fewer when a layer has few leaves)    */
     int32_t ticket_leaves;   /* consecutive leaves a workgroup takes per work ticket
                                 (default 4)                                          */
+    int32_t max_batch;       /* unitaries per *_many call, 1..65535 (default 1): the
+                                plan holds layer buffers for that many instances   */
 } slos_options_t;
 
 /* ---- Fock-space arithmetic (host only; no device needed) ------------------ */
@@ -148,6 +150,16 @@ int slos_amplitudes(slos_plan_t plan, const void *U, void *out, double *sum_p, v
  * C64 plan and fp64 for C128 (device).  sum_p as in slos_amplitudes.
  */
 int slos_probs(slos_plan_t plan, const void *U, void *probs, double *sum_p, void *stream);
+
+/*
+ * The same input state through `batch` unitaries in one pass (one launch per
+ * layer; instance b is blockIdx.y).  U: device, batch x m x m (instance b at
+ * U + b*m*m); out / probs: device, batch x M (instance b at b*M); sum_p:
+ * device, batch doubles, or NULL.  1 <= batch <= the plan's max_batch option.
+ * Instance b's result equals slos_amplitudes / slos_probs on U_b.
+ */
+int slos_amplitudes_many(slos_plan_t plan, int batch, const void *U, void *out, double *sum_p, void *stream);
+int slos_probs_many(slos_plan_t plan, int batch, const void *U, void *probs, double *sum_p, void *stream);
 
 /* ---- weak simulation from the strong one ------------------------------------ */
 
@@ -214,6 +226,10 @@ int slos_postselect(slos_plan_t plan, const void *probs, const int32_t *group_of
  * SLOS_ERR_NOT_KEPT) and m <= 64.  Deterministic: no atomics.
  */
 int slos_backward(slos_plan_t plan, const void *U, const void *grad_a, void *grad_U, void *stream);
+
+/* slos_backward for the `batch` instances of the last slos_amplitudes_many /
+ * slos_probs_many call: grad_a batch x M, grad_U batch x m x m. */
+int slos_backward_many(slos_plan_t plan, int batch, const void *U, const void *grad_a, void *grad_U, void *stream);
 
 /*
  * Rectangular MZI mesh (Section 2: any unitary decomposes into beam splitters

@@ -31,6 +31,25 @@ class SlosAmplitudes(torch.autograd.Function):
         return gU, None
 
 
+class SlosAmplitudesMany(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, U, plan):
+        a = plan.amplitudes_many(U)
+        ctx.plan = plan
+        ctx.token = plan.forward_count
+        ctx.save_for_backward(U)
+        return a
+
+    @staticmethod
+    def backward(ctx, grad_a):
+        (U,) = ctx.saved_tensors
+        if ctx.plan.forward_count != ctx.token:
+            raise RuntimeError("the plan ran another forward pass before this backward; "
+                               "use one plan per differentiated amplitude call")
+        gU = ctx.plan.backward_many(U, grad_a.to(U.dtype).contiguous())
+        return gU, None
+
+
 class MeshUnitary(torch.autograd.Function):
     @staticmethod
     def forward(ctx, phases, m, dtype):
@@ -46,6 +65,12 @@ class MeshUnitary(torch.autograd.Function):
 def amplitudes(plan, U):
     """Differentiable a(S) for all S (plan built with keep_layers=True)."""
     return SlosAmplitudes.apply(U, plan)
+
+
+def amplitudes_many(plan, U):
+    """Differentiable a(S) for a batch of unitaries (batch x m x m) through one
+    plan built with keep_layers=True and max_batch >= batch: batch x M."""
+    return SlosAmplitudesMany.apply(U, plan)
 
 
 def mesh(phases, m: int, dtype: str = "c64"):

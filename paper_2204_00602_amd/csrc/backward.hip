@@ -28,9 +28,13 @@ template <typename T>
 __global__ __launch_bounds__(256) void seed_kernel(const LeafDescHead *__restrict__ heads, uint64_t nleaves,
                                                    uint32_t stride_bytes, const double *__restrict__ lowfac,
                                                    const typename Cb<T>::type *__restrict__ ga,
-                                                   typename Cb<T>::type *__restrict__ gn)
+                                                   typename Cb<T>::type *__restrict__ gn, uint64_t ga_stride,
+                                                   uint64_t gn_stride)
 {
     using C = typename Cb<T>::type;
+    // instance blockIdx.y: element offsets
+    ga += blockIdx.y * ga_stride;
+    gn += blockIdx.y * gn_stride;
     const int lane = threadIdx.x & 63;
     const uint64_t gw = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     const uint64_t nw = (uint64_t)gridDim.x * (blockDim.x >> 6);
@@ -51,6 +55,15 @@ __global__ __launch_bounds__(64) void bwd_layer_kernel(BwdParams p)
     using C = typename Cb<T>::type;
     __shared__ C uc[256];                  // conj(U[j, i_k])
     extern __shared__ double2 part[];      // [m][64] gradient partials of this wave
+    if (blockIdx.y) {
+        // instance blockIdx.y of a batch of unitaries through one plan
+        const uint64_t b = blockIdx.y;
+        p.gk = (const char *)p.gk + b * p.gk_stride;
+        p.gkm1 = (char *)p.gkm1 + b * p.gkm1_stride;
+        p.Akm1 = (const char *)p.Akm1 + b * p.a_stride;
+        p.U = (const char *)p.U + b * p.u_stride;
+        p.partials = (char *)p.partials + b * p.partials_stride;
+    }
     const C *__restrict__ gk = (const C *)p.gk;
     C *__restrict__ gkm1 = (C *)p.gkm1;
     const C *__restrict__ A = (const C *)p.Akm1;
@@ -114,9 +127,12 @@ __global__ __launch_bounds__(64) void bwd_layer_kernel(BwdParams p)
 
 // colsum[j] = sum over units of partials[unit][j], fixed order
 __global__ __launch_bounds__(256) void colsum_kernel(const double2 *__restrict__ partials, uint64_t nunits, int m,
-                                                     double2 *__restrict__ colsum)
+                                                     double2 *__restrict__ colsum, uint64_t partials_stride,
+                                                     uint64_t colsum_stride)
 {
     __shared__ double2 sh[256];
+    partials += blockIdx.y * partials_stride;  // instance blockIdx.y (element strides)
+    colsum += blockIdx.y * colsum_stride;
     const int j = blockIdx.x;
     double2 s{0.0, 0.0};
     for (uint64_t u = threadIdx.x; u < nunits; u += 256) {
@@ -139,9 +155,11 @@ __global__ __launch_bounds__(256) void colsum_kernel(const double2 *__restrict__
 // G_U[j, i] = sum over layers k with i_k = i of colsum_k[j], in order of k
 template <typename T>
 __global__ void gradu_kernel(const double2 *__restrict__ colsum, const int32_t *__restrict__ photons, int n, int m,
-                             typename Cb<T>::type *__restrict__ GU)
+                             typename Cb<T>::type *__restrict__ GU, uint64_t colsum_stride, uint64_t gu_stride)
 {
     using C = typename Cb<T>::type;
+    colsum += blockIdx.y * colsum_stride;  // instance blockIdx.y (element strides)
+    GU += blockIdx.y * gu_stride;
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= m * m) return;
     const int j = idx / m, i = idx % m;
@@ -329,15 +347,16 @@ __global__ void mesh_backward_kernel(int m, int nmzi, const double *__restrict__
 } // namespace
 
 int slos_launch_seed(const void *heads, uint64_t nleaves, uint32_t stride, const double *lowfac, const void *ga,
-                     void *gn, int c64, void *stream)
+                     void *gn, int c64, void *stream, int batch, uint64_t ga_stride, uint64_t gn_stride)
 {
     const int grid = (int)(nleaves < 1024 ? (nleaves + 3) / 4 : 256);
+    const dim3 g(grid > 0 ? grid : 1, batch > 1 ? batch : 1);
     if (c64)
-        hipLaunchKernelGGL(seed_kernel<float>, dim3(grid > 0 ? grid : 1), dim3(256), 0, (hipStream_t)stream,
-                           (const LeafDescHead *)heads, nleaves, stride, lowfac, (const float2 *)ga, (float2 *)gn);
+        hipLaunchKernelGGL(seed_kernel<float>, g, dim3(256), 0, (hipStream_t)stream, (const LeafDescHead *)heads,
+                           nleaves, stride, lowfac, (const float2 *)ga, (float2 *)gn, ga_stride, gn_stride);
     else
-        hipLaunchKernelGGL(seed_kernel<double>, dim3(grid > 0 ? grid : 1), dim3(256), 0, (hipStream_t)stream,
-                           (const LeafDescHead *)heads, nleaves, stride, lowfac, (const double2 *)ga, (double2 *)gn);
+        hipLaunchKernelGGL(seed_kernel<double>, g, dim3(256), 0, (hipStream_t)stream, (const LeafDescHead *)heads,
+                           nleaves, stride, lowfac, (const double2 *)ga, (double2 *)gn, ga_stride, gn_stride);
     return (int)hipGetLastError();
 }
 
@@ -352,36 +371,39 @@ static hipError_t allow_lds(K kernel, bool &done)
     return e;
 }
 
-int slos_launch_bwd_layer(const BwdParams &p, int c64, int grid, void *stream)
+int slos_launch_bwd_layer(const BwdParams &p, int c64, int grid, void *stream, int batch)
 {
     static bool a32 = false, a64 = false;
     hipError_t e = c64 ? allow_lds(bwd_layer_kernel<float>, a32) : allow_lds(bwd_layer_kernel<double>, a64);
     if (e != hipSuccess) return (int)e;
     const size_t lds = (size_t)p.m * 64 * sizeof(double2);
+    const dim3 g(grid, batch > 1 ? batch : 1);
     if (c64)
-        hipLaunchKernelGGL(bwd_layer_kernel<float>, dim3(grid), dim3(64), lds, (hipStream_t)stream, p);
+        hipLaunchKernelGGL(bwd_layer_kernel<float>, g, dim3(64), lds, (hipStream_t)stream, p);
     else
-        hipLaunchKernelGGL(bwd_layer_kernel<double>, dim3(grid), dim3(64), lds, (hipStream_t)stream, p);
+        hipLaunchKernelGGL(bwd_layer_kernel<double>, g, dim3(64), lds, (hipStream_t)stream, p);
     return (int)hipGetLastError();
 }
 
-int slos_launch_colsum(const void *partials, uint64_t nunits, int m, void *colsum, void *stream)
+int slos_launch_colsum(const void *partials, uint64_t nunits, int m, void *colsum, void *stream, int batch,
+                       uint64_t partials_stride, uint64_t colsum_stride)
 {
-    hipLaunchKernelGGL(colsum_kernel, dim3(m), dim3(256), 0, (hipStream_t)stream, (const double2 *)partials,
-                       nunits, m, (double2 *)colsum);
+    hipLaunchKernelGGL(colsum_kernel, dim3(m, batch > 1 ? batch : 1), dim3(256), 0, (hipStream_t)stream,
+                       (const double2 *)partials, nunits, m, (double2 *)colsum, partials_stride, colsum_stride);
     return (int)hipGetLastError();
 }
 
-int slos_launch_gradu(const void *colsum, const int32_t *photons, int n, int m, void *GU, int c64, void *stream)
+int slos_launch_gradu(const void *colsum, const int32_t *photons, int n, int m, void *GU, int c64, void *stream,
+                      int batch, uint64_t colsum_stride, uint64_t gu_stride)
 {
     const int total = m * m;
-    const int grid = (total + 255) / 256;
+    const dim3 g((total + 255) / 256, batch > 1 ? batch : 1);
     if (c64)
-        hipLaunchKernelGGL(gradu_kernel<float>, dim3(grid), dim3(256), 0, (hipStream_t)stream,
-                           (const double2 *)colsum, photons, n, m, (float2 *)GU);
+        hipLaunchKernelGGL(gradu_kernel<float>, g, dim3(256), 0, (hipStream_t)stream, (const double2 *)colsum,
+                           photons, n, m, (float2 *)GU, colsum_stride, gu_stride);
     else
-        hipLaunchKernelGGL(gradu_kernel<double>, dim3(grid), dim3(256), 0, (hipStream_t)stream,
-                           (const double2 *)colsum, photons, n, m, (double2 *)GU);
+        hipLaunchKernelGGL(gradu_kernel<double>, g, dim3(256), 0, (hipStream_t)stream, (const double2 *)colsum,
+                           photons, n, m, (double2 *)GU, colsum_stride, gu_stride);
     return (int)hipGetLastError();
 }
 

@@ -473,6 +473,17 @@ template <typename T, int MODE, int COMP, int RR, bool WIDE>
 __global__ __launch_bounds__(256, sizeof(T) == 4 ? 3 : (RR <= 2 ? 4 : 1)) void layer_kernel(LayerParams p)
 {
     using C = typename Cx<T>::type;
+    if (blockIdx.y) {
+        // instance blockIdx.y of a batch of unitaries through one plan
+        const uint64_t b = blockIdx.y;
+        p.X = (const char *)p.X + b * p.x_stride;
+        p.Y = (char *)p.Y + b * p.y_stride;
+        p.U = (const char *)p.U + b * p.u_stride;
+        p.partials += b * p.partials_stride;
+        p.tickets += b * p.ticket_stride;
+        if (p.vmax_in) p.vmax_in += b * p.ticket_stride;
+        if (p.vmax_out) p.vmax_out += b * p.ticket_stride;
+    }
     __shared__ C u_lds[256];
     __shared__ uint32_t ticket_slot[2];
     const C *__restrict__ X = (const C *)p.X;
@@ -681,8 +692,11 @@ __device__ __forceinline__ double block_sum(double s)
 }
 
 __global__ __launch_bounds__(256) void reduce_stage1(const double *__restrict__ part, int64_t count,
-                                                     double *__restrict__ stage)
+                                                     double *__restrict__ stage, int64_t stride)
 {
+    // batch entry blockIdx.y: partials at part + y * stride, stage row y
+    part += (int64_t)blockIdx.y * stride;
+    stage += (int64_t)blockIdx.y * kReduceBlocks;
     const int64_t seg = (count + kReduceBlocks - 1) / kReduceBlocks;
     const int64_t lo = (int64_t)blockIdx.x * seg;
     const int64_t hi = lo + seg < count ? lo + seg : count;
@@ -694,6 +708,8 @@ __global__ __launch_bounds__(256) void reduce_stage1(const double *__restrict__ 
 
 __global__ __launch_bounds__(256) void reduce_stage2(const double *__restrict__ stage, double *__restrict__ out)
 {
+    stage += (int64_t)blockIdx.x * kReduceBlocks;
+    out += blockIdx.x;
     const double s = block_sum(threadIdx.x < kReduceBlocks ? stage[threadIdx.x] : 0.0);
     if (threadIdx.x == 0) *out = s;
 }
@@ -728,7 +744,8 @@ hipError_t launch_one(const LayerParams &p, const LayerLaunch &l, hipStream_t s)
         attr_set = true;
     }
     const size_t lds = (size_t)p.lds_wave_bytes;  // one low block per workgroup
-    hipLaunchKernelGGL((layer_kernel<T, MODE, COMP, RR, WIDE>), dim3(l.grid), dim3(l.threads), lds, s, p);
+    hipLaunchKernelGGL((layer_kernel<T, MODE, COMP, RR, WIDE>), dim3(l.grid, l.batch > 1 ? l.batch : 1),
+                       dim3(l.threads), lds, s, p);
     return hipGetLastError();
 }
 
@@ -772,12 +789,14 @@ int slos_launch_layer(const LayerParams &p, const LayerLaunch &l, void *stream)
     return (int)launch_mode<double, SLOS_COMP_NONE>(p, l, s);
 }
 
-int slos_launch_reduce(const double *partials, int64_t count, double *stage, double *out, void *stream)
+int slos_launch_reduce(const double *partials, int64_t count, double *stage, double *out, void *stream, int batch,
+                       int64_t stride)
 {
-    hipLaunchKernelGGL(reduce_stage1, dim3(kReduceBlocks), dim3(256), 0, (hipStream_t)stream, partials, count, stage);
+    hipLaunchKernelGGL(reduce_stage1, dim3(kReduceBlocks, batch), dim3(256), 0, (hipStream_t)stream, partials, count,
+                       stage, stride);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return (int)e;
-    hipLaunchKernelGGL(reduce_stage2, dim3(1), dim3(256), 0, (hipStream_t)stream, stage, out);
+    hipLaunchKernelGGL(reduce_stage2, dim3(batch), dim3(256), 0, (hipStream_t)stream, stage, out);
     return (int)hipGetLastError();
 }
 

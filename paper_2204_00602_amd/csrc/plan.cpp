@@ -163,6 +163,11 @@ struct slos_plan_s {
     std::vector<uint64_t> keep_off;   // element offsets of A_k in d_keep
     double *d_partials = nullptr;
     int64_t n_partials = 0;
+    int batch_cap = 1;                // instances per call (opts.max_batch)
+    uint64_t keep_stride = 0;         // elements per instance in d_keep
+    uint64_t buf_stride[2] = {0, 0};  // elements per instance in d_buf[b]
+    uint64_t g_stride = 0;            // elements per instance in d_g[b]
+    uint64_t bpart_stride = 0;        // double2 per instance in d_bpart
     uint32_t *d_tickets = nullptr;    // SLOS_XCDS ticket counters per layer
     double *d_cdf = nullptr;          // block prefix of the last slos_cdf input (nb + 1), then run prefixes
     int64_t *d_pk_ends = nullptr;     // C(K+n-1, n) for K = 1..m
@@ -529,6 +534,9 @@ int slos_plan_ex(int m, int n, const int32_t *input_state, int flags, const slos
     if (o.outputs_per_lane == 0) o.outputs_per_lane = dt == SLOS_C64 ? 4 : 2;
     if (o.xcd_chunk == 0) o.xcd_chunk = 128;
     if (o.ticket_leaves == 0) o.ticket_leaves = 4;
+    if (o.max_batch == 0) o.max_batch = 1;
+    if (o.max_batch < 1 || o.max_batch > 65535)
+        return fail(SLOS_ERR_INVALID_ARG, "max_batch = %d outside [1, 65535]", o.max_batch);
     if (o.ticket_leaves < 1 || o.ticket_leaves > 4096)
         return fail(SLOS_ERR_INVALID_ARG, "ticket_leaves = %d outside [1, 4096]", o.ticket_leaves);
     if (o.xcd_chunk < 1 || o.xcd_chunk > (1 << 24))
@@ -554,6 +562,7 @@ int slos_plan_ex(int m, int n, const int32_t *input_state, int flags, const slos
     p->keep = (flags & SLOS_KEEP_LAYERS) != 0;
     p->host_only = (flags & SLOS_HOST_ONLY) != 0;
     p->opts = o;
+    p->batch_cap = o.max_batch;
 
     try {
         double tf = 1.0;
@@ -715,33 +724,42 @@ int slos_plan_ex(int m, int n, const int32_t *input_state, int flags, const slos
             tot += (p->Nk[k] + 15) / 16 * 16;  // 128-byte aligned layers
         }
         p->keep_off[n] = tot;
-        if ((rc = alloc_dev(&p->d_keep, tot * es + SLOS_BUFFER_SLACK, "kept layers"))) {
+        p->keep_stride = tot;
+        if ((rc = alloc_dev(&p->d_keep, tot * es * p->batch_cap + SLOS_BUFFER_SLACK, "kept layers"))) {
             p->free_device();
             delete p;
             return rc;
         }
-        e = hipMemcpy(p->d_keep, p->d_vac, es, hipMemcpyDeviceToDevice);
-        if (e != hipSuccess) {
-            rc = hip_fail(e, "kept vacuum layer");
-            p->free_device();
-            delete p;
-            return rc;
+        for (int b = 0; b < p->batch_cap; ++b) {
+            e = hipMemcpy((char *)p->d_keep + (size_t)b * tot * es, p->d_vac, es, hipMemcpyDeviceToDevice);
+            if (e != hipSuccess) {
+                rc = hip_fail(e, "kept vacuum layer");
+                p->free_device();
+                delete p;
+                return rc;
+            }
         }
     } else {
         uint64_t need[2] = {0, 0};
         for (int k = 1; k < n; ++k) need[k & 1] = std::max(need[k & 1], p->Nk[k]);
+        for (int b = 0; b < 2; ++b) {
+            need[b] = (need[b] + 31) / 32 * 32;  // 256-byte aligned instances
+            p->buf_stride[b] = need[b];
+        }
         for (int b = 0; b < 2; ++b)
-            if (need[b] && (rc = alloc_dev(&p->d_buf[b], need[b] * es + SLOS_BUFFER_SLACK, "layer buffer"))) {
+            if (need[b] && (rc = alloc_dev(&p->d_buf[b], need[b] * es * p->batch_cap + SLOS_BUFFER_SLACK,
+                                           "layer buffer"))) {
                 p->free_device();
                 delete p;
                 return rc;
             }
     }
     p->n_partials = n > 0 ? (int64_t)p->leaves[n].size() * (p->opts.block_threads / 64) : 1;
-    if ((rc = alloc_dev((void **)&p->d_partials, (size_t)(p->n_partials + SLOS_REDUCE_STAGE) * sizeof(double),
-                        "partial sums")) ||
+    if ((rc = alloc_dev((void **)&p->d_partials,
+                        (size_t)(p->n_partials + SLOS_REDUCE_STAGE) * p->batch_cap * sizeof(double), "partial sums")) ||
         (rc = alloc_dev((void **)&p->d_tickets,
-                        (size_t)(n + 1) * SLOS_XCDS * SLOS_TICKET_STRIDE * sizeof(uint32_t), "ticket counters"))) {
+                        (size_t)(n + 1) * SLOS_XCDS * SLOS_TICKET_STRIDE * p->batch_cap * sizeof(uint32_t),
+                        "ticket counters"))) {
         p->free_device();
         delete p;
         return rc;
@@ -774,15 +792,18 @@ int slos_plan_ex(int m, int n, const int32_t *input_state, int flags, const slos
         }
         p->bpart_off[n + 1] = bp;
         uint64_t gmax = *std::max_element(p->Nk.begin(), p->Nk.end());
+        gmax = (gmax + 31) / 32 * 32;
+        p->g_stride = gmax;
+        p->bpart_stride = std::max<uint64_t>(bp, 1);
         std::vector<int32_t> ph(p->photons.begin(), p->photons.end());
         if ((rc = dev_upload(&p->d_units, allu.data(), allu.size(), "reverse units")) ||
             (rc = dev_upload(&p->d_succ, p->succ.data(), p->succ.size(), "successor tables")) ||
             (rc = dev_upload(&p->d_hbase, p->hbase.data(), p->hbase.size(), "successor bases")) ||
             (rc = dev_upload(&p->d_photons, ph.data(), ph.size(), "photon list")) ||
-            (rc = alloc_dev(&p->d_g[0], gmax * es, "adjoint layer")) ||
-            (rc = alloc_dev(&p->d_g[1], gmax * es, "adjoint layer")) ||
-            (rc = alloc_dev(&p->d_bpart, std::max<uint64_t>(bp, 1) * 16, "gradient partials")) ||
-            (rc = alloc_dev(&p->d_colsum, (size_t)n * m * 16, "gradient columns"))) {
+            (rc = alloc_dev(&p->d_g[0], gmax * es * p->batch_cap, "adjoint layer")) ||
+            (rc = alloc_dev(&p->d_g[1], gmax * es * p->batch_cap, "adjoint layer")) ||
+            (rc = alloc_dev(&p->d_bpart, p->bpart_stride * 16 * p->batch_cap, "gradient partials")) ||
+            (rc = alloc_dev(&p->d_colsum, (size_t)n * m * 16 * p->batch_cap, "gradient columns"))) {
             p->free_device();
             delete p;
             return rc;
@@ -833,22 +854,31 @@ int slos_plan_leaf(slos_plan_t p, int k, int64_t idx, int64_t *out_base, int32_t
     return SLOS_OK;
 }
 
-static int run_forward(slos_plan_t p, const void *U, void *out, double *sum_p, void *stream, int last_mode)
+static int run_forward(slos_plan_t p, int batch, const void *U, void *out, double *sum_p, void *stream,
+                       int last_mode)
 {
     int rc = check_plan(p);
     if (rc) return rc;
     if (!U || !out) return fail(SLOS_ERR_INVALID_ARG, "U and out must be device pointers");
+    if (batch < 1 || batch > p->batch_cap)
+        return fail(SLOS_ERR_INVALID_ARG, "batch = %d outside [1, max_batch = %d]", batch, p->batch_cap);
     const int n = p->n;
+    // bytes of one instance's output
+    const size_t out_bytes = (size_t)p->Nk[n] * (last_mode == SLOS_MODE_PROB ? p->elem() / 2 : p->elem());
     if (n == 0) {
-        int e = slos_launch_vacuum(out, p->c64, last_mode, sum_p, stream);
-        if (e) return hip_fail((hipError_t)e, "vacuum kernel");
+        for (int b = 0; b < batch; ++b) {
+            int e = slos_launch_vacuum((char *)out + b * out_bytes, p->c64, last_mode, sum_p ? sum_p + b : nullptr,
+                                       stream);
+            if (e) return hip_fail((hipError_t)e, "vacuum kernel");
+        }
         return SLOS_OK;
     }
     const size_t es = p->elem();
     const int wpb = p->opts.block_threads / 64;
     hipStream_t hs = (hipStream_t)stream;
+    const uint64_t tstride = (uint64_t)(n + 1) * SLOS_XCDS * SLOS_TICKET_STRIDE;
     {
-        int e = slos_launch_zero_u32(p->d_tickets, (n + 1) * SLOS_XCDS * SLOS_TICKET_STRIDE, stream);
+        int e = slos_launch_zero_u32(p->d_tickets, (int)(tstride * batch), stream);
         if (e) return hip_fail((hipError_t)e, "ticket reset kernel");
     }
     if (p->timing) {
@@ -861,10 +891,17 @@ static int run_forward(slos_plan_t p, const void *U, void *out, double *sum_p, v
         if (p->keep) {
             lp.X = (const char *)p->d_keep + p->keep_off[k - 1] * es;
             lp.Y = k == n ? out : (void *)((char *)p->d_keep + p->keep_off[k] * es);
+            lp.x_stride = p->keep_stride * es;
+            lp.y_stride = k == n ? out_bytes : p->keep_stride * es;
         } else {
             lp.X = k == 1 ? p->d_vac : p->d_buf[(k - 1) & 1];
             lp.Y = k == n ? out : p->d_buf[k & 1];
+            lp.x_stride = k == 1 ? 0 : p->buf_stride[(k - 1) & 1] * es;  // every instance reads the one vacuum
+            lp.y_stride = k == n ? out_bytes : p->buf_stride[k & 1] * es;
         }
+        lp.u_stride = (uint64_t)p->m * p->m * es;
+        lp.partials_stride = (uint64_t)p->n_partials;
+        lp.ticket_stride = tstride;
         lp.U = U;
         lp.leaves = p->d_leaves + p->leaf_off[k];
         lp.desc = p->d_desc + p->desc_off[k];
@@ -886,6 +923,7 @@ static int run_forward(slos_plan_t p, const void *U, void *out, double *sum_p, v
                              ? ((p->flags & SLOS_COMP_KNUTH) ? SLOS_COMP_TWOSUM : SLOS_COMP_BIASED)
                              : SLOS_COMP_NONE;
         ll.rr = p->opts.outputs_per_lane;
+        ll.batch = batch;
         ll.threads = p->opts.block_threads;
         ll.low_max = p->low_max[k];
         ll.wide = p->desc_wide[k];
@@ -915,7 +953,8 @@ static int run_forward(slos_plan_t p, const void *U, void *out, double *sum_p, v
         if (p->timing && (e = (int)hipEventRecord(p->events[k], hs)))
             return hip_fail((hipError_t)e, "timing event");
         if (k == n && sum_p) {
-            e = slos_launch_reduce(p->d_partials, p->n_partials, p->d_partials + p->n_partials, sum_p, stream);
+            e = slos_launch_reduce(p->d_partials, p->n_partials, p->d_partials + p->n_partials * p->batch_cap, sum_p,
+                                   stream, batch, p->n_partials);
             if (e) return hip_fail((hipError_t)e, "sum reduction kernel");
             if (p->timing) {
                 if ((e = (int)hipEventRecord(p->events[n + 1], hs)))
@@ -970,28 +1009,31 @@ int slos_plan_layer_ms(slos_plan_t p, float *ms, int count)
     return SLOS_OK;
 }
 
-int slos_backward(slos_plan_t p, const void *U, const void *grad_a, void *grad_U, void *stream)
+static int run_backward(slos_plan_t p, int batch, const void *U, const void *grad_a, void *grad_U, void *stream)
 {
     int rc = check_plan(p);
     if (rc) return rc;
     if (!p->keep) return fail(SLOS_ERR_NOT_KEPT, "slos_backward needs a plan built with SLOS_KEEP_LAYERS");
     if (!U || !grad_a || !grad_U) return fail(SLOS_ERR_INVALID_ARG, "U, grad_a and grad_U must be device pointers");
+    if (batch < 1 || batch > p->batch_cap)
+        return fail(SLOS_ERR_INVALID_ARG, "batch = %d outside [1, max_batch = %d]", batch, p->batch_cap);
     const int n = p->n, m = p->m;
     if (m > SLOS_BWD_MAX_MODES)
         return fail(SLOS_ERR_INVALID_ARG, "slos_backward supports m <= %d", SLOS_BWD_MAX_MODES);
     const int c64 = p->c64 ? 1 : 0;
+    const size_t es = p->elem();
+    const uint64_t mm = (uint64_t)m * m;
     int e;
     if (n == 0) {
         // a(vacuum) = 1 does not depend on U
-        if ((e = slos_launch_zero_u32((uint32_t *)grad_U, (int)((size_t)m * m * p->elem() / 4), stream)))
+        if ((e = slos_launch_zero_u32((uint32_t *)grad_U, (int)(mm * es * batch / 4), stream)))
             return hip_fail((hipError_t)e, "zero kernel");
         return SLOS_OK;
     }
-    const size_t es = p->elem();
     const size_t rec = p->desc_wide[n] ? sizeof(LeafDescWide) : sizeof(LeafDescNarrow);
     // g_n = c_S g_a
     if ((e = slos_launch_seed(p->d_desc + p->desc_off[n], p->leaves[n].size(), (uint32_t)rec, p->d_lowfac, grad_a,
-                              p->d_g[n & 1], c64, stream)))
+                              p->d_g[n & 1], c64, stream, batch, p->Nk[n], p->g_stride)))
         return hip_fail((hipError_t)e, "seed kernel");
     for (int k = n; k >= 1; --k) {
         BwdParams bp{};
@@ -1006,15 +1048,30 @@ int slos_backward(slos_plan_t p, const void *U, const void *grad_a, void *grad_U
         bp.partials = (char *)p->d_bpart + p->bpart_off[k] * 16;
         bp.m = m;
         bp.col = p->photons[k - 1];
+        bp.gk_stride = bp.gkm1_stride = p->g_stride * es;
+        bp.a_stride = p->keep_stride * es;
+        bp.u_stride = mm * es;
+        bp.partials_stride = p->bpart_stride * 16;
         const int grid = (int)std::max<uint64_t>(1, std::min<uint64_t>(bp.nunits, 4096));
-        if ((e = slos_launch_bwd_layer(bp, c64, grid, stream))) return hip_fail((hipError_t)e, "reverse layer");
+        if ((e = slos_launch_bwd_layer(bp, c64, grid, stream, batch)))
+            return hip_fail((hipError_t)e, "reverse layer");
         if ((e = slos_launch_colsum(bp.partials, bp.nunits, m, (char *)p->d_colsum + (size_t)(k - 1) * m * 16,
-                                    stream)))
+                                    stream, batch, p->bpart_stride, (uint64_t)n * m)))
             return hip_fail((hipError_t)e, "column sum kernel");
     }
-    if ((e = slos_launch_gradu(p->d_colsum, p->d_photons, n, m, grad_U, c64, stream)))
+    if ((e = slos_launch_gradu(p->d_colsum, p->d_photons, n, m, grad_U, c64, stream, batch, (uint64_t)n * m, mm)))
         return hip_fail((hipError_t)e, "gradient assembly");
     return SLOS_OK;
+}
+
+int slos_backward(slos_plan_t p, const void *U, const void *grad_a, void *grad_U, void *stream)
+{
+    return run_backward(p, 1, U, grad_a, grad_U, stream);
+}
+
+int slos_backward_many(slos_plan_t p, int batch, const void *U, const void *grad_a, void *grad_U, void *stream)
+{
+    return run_backward(p, batch, U, grad_a, grad_U, stream);
 }
 
 int slos_mesh_unitary(int m, int batch, const double *phases, void *U, int dtype, void *stream)
@@ -1040,12 +1097,22 @@ int slos_mesh_backward(int m, int batch, const double *phases, const void *grad_
 
 int slos_amplitudes(slos_plan_t p, const void *U, void *out, double *sum_p, void *stream)
 {
-    return run_forward(p, U, out, sum_p, stream, SLOS_MODE_AMPL);
+    return run_forward(p, 1, U, out, sum_p, stream, SLOS_MODE_AMPL);
 }
 
 int slos_probs(slos_plan_t p, const void *U, void *probs, double *sum_p, void *stream)
 {
-    return run_forward(p, U, probs, sum_p, stream, SLOS_MODE_PROB);
+    return run_forward(p, 1, U, probs, sum_p, stream, SLOS_MODE_PROB);
+}
+
+int slos_amplitudes_many(slos_plan_t p, int batch, const void *U, void *out, double *sum_p, void *stream)
+{
+    return run_forward(p, batch, U, out, sum_p, stream, SLOS_MODE_AMPL);
+}
+
+int slos_probs_many(slos_plan_t p, int batch, const void *U, void *probs, double *sum_p, void *stream)
+{
+    return run_forward(p, batch, U, probs, sum_p, stream, SLOS_MODE_PROB);
 }
 
 int slos_cdf(slos_plan_t p, const void *probs, void *stream)

@@ -141,12 +141,20 @@ struct LayerParams {
     // (NULL: not recorded).  Both live in the zeroed ticket area.
     const uint32_t *vmax_in;
     uint32_t *vmax_out;
+    // Many unitaries through one plan: instance b = blockIdx.y reads X + b *
+    // x_stride and U + b * u_stride, writes Y + b * y_stride (bytes), and uses
+    // partials + b * partials_stride and tickets (with the vmax slots) +
+    // b * ticket_stride.
+    uint64_t x_stride, y_stride, u_stride;
+    uint64_t partials_stride;
+    uint64_t ticket_stride;
 };
 
 struct LayerLaunch {
     int c64;          // 1: complex64, 0: complex128
     int mode;         // SlosLayerMode
     int compensated;  // c64 only: SLOS_COMP_NONE / _BIASED / _TWOSUM
+    int batch;        // instances (gridDim.y); 0 or 1: one
     int rr;           // outputs per lane per tile: 1, 2, 4
     int threads;      // workgroup size (multiple of 64, <= 256)
     int grid;         // workgroups
@@ -168,7 +176,8 @@ static inline uint32_t slos_lds_wave_bytes(uint32_t low_max, uint32_t es)
 int slos_launch_layer(const LayerParams &p, const LayerLaunch &l, void *stream);
 // stage: SLOS_REDUCE_STAGE doubles of scratch
 #define SLOS_REDUCE_STAGE 256
-int slos_launch_reduce(const double *partials, int64_t count, double *stage, double *out, void *stream);
+int slos_launch_reduce(const double *partials, int64_t count, double *stage, double *out, void *stream,
+                       int batch = 1, int64_t stride = 0);
 int slos_launch_vacuum(void *out, int c64, int mode, double *sum_p, void *stream);
 int slos_launch_zero_u32(uint32_t *buf, int count, void *stream);
 
@@ -202,16 +211,20 @@ struct BwdParams {
     void *partials;          // double2 [nunits][m]
     int m;
     int col;                 // i_k
+    // instance b = blockIdx.y: byte offsets b * stride of gk, gkm1, Akm1, U, partials
+    uint64_t gk_stride, gkm1_stride, a_stride, u_stride, partials_stride;
 };
 
 #define SLOS_BWD_MAX_MODES 64   // the reverse layer keeps m x 64 FP64 partials in LDS
 #define SLOS_MESH_MAX_MODES 64  // the mesh kernels keep two m x m FP64 matrices in LDS
 
 int slos_launch_seed(const void *heads, uint64_t nleaves, uint32_t stride, const double *lowfac, const void *ga,
-                     void *gn, int c64, void *stream);
-int slos_launch_bwd_layer(const BwdParams &p, int c64, int grid, void *stream);
-int slos_launch_colsum(const void *partials, uint64_t nunits, int m, void *colsum, void *stream);
-int slos_launch_gradu(const void *colsum, const int32_t *photons, int n, int m, void *GU, int c64, void *stream);
+                     void *gn, int c64, void *stream, int batch = 1, uint64_t ga_stride = 0, uint64_t gn_stride = 0);
+int slos_launch_bwd_layer(const BwdParams &p, int c64, int grid, void *stream, int batch = 1);
+int slos_launch_colsum(const void *partials, uint64_t nunits, int m, void *colsum, void *stream, int batch = 1,
+                       uint64_t partials_stride = 0, uint64_t colsum_stride = 0);
+int slos_launch_gradu(const void *colsum, const int32_t *photons, int n, int m, void *GU, int c64, void *stream,
+                      int batch = 1, uint64_t colsum_stride = 0, uint64_t gu_stride = 0);
 int slos_launch_mesh_forward(int m, int batch, const double *phases, void *U, int c64, void *stream);
 int slos_launch_mesh_backward(int m, int batch, const double *phases, const void *GU, double *gphases, int c64,
                               void *stream);

@@ -41,7 +41,7 @@ class Options(ctypes.Structure):
     _fields_ = [("leaf_max", ctypes.c_int32), ("comp_from_layer", ctypes.c_int32),
                 ("block_threads", ctypes.c_int32), ("grid_blocks", ctypes.c_int32),
                 ("outputs_per_lane", ctypes.c_int32), ("xcd_chunk", ctypes.c_int32),
-                ("ticket_leaves", ctypes.c_int32)]
+                ("ticket_leaves", ctypes.c_int32), ("max_batch", ctypes.c_int32)]
 
 
 _lib = None
@@ -74,6 +74,9 @@ def lib():
     L.slos_amplitudes.argtypes = [vp, vp, vp, vp, vp]
     L.slos_probs.argtypes = [vp, vp, vp, vp, vp]
     L.slos_backward.argtypes = [vp, vp, vp, vp, vp]
+    L.slos_amplitudes_many.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp]
+    L.slos_probs_many.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp]
+    L.slos_backward_many.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp]
     L.slos_cdf.argtypes = [vp, vp, vp]
     L.slos_marginals.argtypes = [vp, vp, vp, vp]
     L.slos_sample.argtypes = [vp, vp, vp, ctypes.c_int64, vp, vp]
@@ -94,7 +97,8 @@ def lib():
     L.slos_last_error.restype = ctypes.c_char_p
     for name in ("slos_fock_count", "slos_fock_rank", "slos_fock_unrank", "slos_plan",
                  "slos_plan_ex", "slos_plan_info", "slos_plan_leaf", "slos_amplitudes",
-                 "slos_probs", "slos_cdf", "slos_marginals", "slos_sample", "slos_postselect", "slos_plan_set_timing", "slos_plan_layer_ms", "slos_backward",
+                 "slos_probs", "slos_cdf", "slos_marginals", "slos_sample", "slos_postselect", "slos_amplitudes_many",
+                 "slos_probs_many", "slos_backward_many", "slos_plan_set_timing", "slos_plan_layer_ms", "slos_backward",
                  "slos_mesh_unitary", "slos_mesh_backward", "slos_batch_plan", "slos_batch_offsets",
                  "slos_batch_amplitudes", "slos_batch_capture", "slos_batch_replay"):
         getattr(L, name).restype = ctypes.c_int
@@ -266,6 +270,47 @@ class Plan:
             sp = sum_p.data_ptr()
         _check(self._lib.slos_probs(self._h, U.data_ptr(), out.data_ptr(), sp, _stream_ptr(stream)))
         return out
+
+    def _check_many(self, U):
+        import torch
+        if not isinstance(U, torch.Tensor) or U.device.type != "cuda" or U.dtype != self._complex_dtype():
+            raise TypeError(f"U must be a {self._complex_dtype()} CUDA (HIP) tensor")
+        if U.dim() != 3 or tuple(U.shape[1:]) != (self.m, self.m) or not U.is_contiguous():
+            raise ValueError(f"U must be a contiguous batch x {self.m} x {self.m} tensor")
+        b = U.shape[0]
+        if b < 1 or b > self.options.get("max_batch", 1):
+            raise ValueError(f"batch {b} outside [1, max_batch]")
+        return b
+
+    def amplitudes_many(self, U, out=None, sum_p=None, stream=None):
+        """a(S) for a batch of unitaries (batch x m x m): out is batch x M."""
+        import torch
+        b = self._check_many(U)
+        self.forward_count = getattr(self, "forward_count", 0) + 1
+        if out is None:
+            out = torch.empty((b, self.num_outputs), dtype=self._complex_dtype(), device=U.device)
+        elif out.dtype != self._complex_dtype() or out.numel() != b * self.num_outputs or not out.is_contiguous():
+            raise ValueError("out has the wrong dtype, size or layout")
+        if sum_p is not None and (sum_p.dtype != torch.float64 or sum_p.numel() != b):
+            raise TypeError("sum_p must be a float64 tensor with one entry per instance")
+        _check(self._lib.slos_amplitudes_many(self._h, b, U.data_ptr(), out.data_ptr(),
+                                              None if sum_p is None else sum_p.data_ptr(), _stream_ptr(stream)))
+        return out
+
+    def backward_many(self, U, grad_a, grad_U=None, stream=None):
+        """Gradients with respect to each U of a batch (see backward)."""
+        import torch
+        b = self._check_many(U)
+        if not (self.flags & SLOS_KEEP_LAYERS):
+            raise SlosError(-6, "plan was built without keep_layers=True")
+        if grad_a.dtype != self._complex_dtype() or grad_a.numel() != b * self.num_outputs:
+            raise ValueError("grad_a has the wrong dtype or size")
+        grad_a = grad_a.contiguous()
+        if grad_U is None:
+            grad_U = torch.empty_like(U)
+        _check(self._lib.slos_backward_many(self._h, b, U.data_ptr(), grad_a.data_ptr(), grad_U.data_ptr(),
+                                            _stream_ptr(stream)))
+        return grad_U
 
     def backward(self, U, grad_a, grad_U=None, stream=None):
         """Gradient with respect to U of a real loss, given its gradient with

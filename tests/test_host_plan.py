@@ -132,7 +132,7 @@ def test_plan_argument_validation():
 
 def test_plan_options_validation():
     for opts in ({"leaf_max": 70000}, {"block_threads": 96}, {"outputs_per_lane": 3},
-                 {"grid_blocks": -1}, {"comp_from_layer": -2}):
+                 {"grid_blocks": -1}, {"comp_from_layer": -2}, {"max_batch": 70000}, {"max_batch": -3}):
         with pytest.raises(slos.SlosError) as e:
             slos.Plan([1, 1, 0], "c64", host_only=True, options=opts)
         assert e.value.code == -1
@@ -191,3 +191,11 @@ def test_postselect_validates_arguments():
     assert L.slos_postselect(None, None, None, 0, None, None, None, None, None, 0, None, None) == -1
     p = slos.Plan([1, 1, 0], "c64", host_only=True)
     assert L.slos_postselect(p._h, None, None, 0, None, None, None, None, None, 0, None, None) == -1
+
+
+def test_many_calls_validate_arguments():
+    L = slos.lib()
+    assert L.slos_amplitudes_many(None, 1, None, None, None, None) == -1
+    assert L.slos_backward_many(None, 1, None, None, None, None) == -1
+    p = slos.Plan([1, 1, 0], "c64", host_only=True, options={"max_batch": 4})
+    assert L.slos_probs_many(p._h, 2, None, None, None, None) == -1
