@@ -145,7 +145,8 @@ def time_batched(torch, slos, steps, warmup, count=4096, seed=4):
 def time_gradient(torch, slos, steps, warmup, batch=64, m=12, n=6, targets=200):
     """Gradient of sum_b sum_S (P_b(S) - P_t(S))^2 over 200 seeded targets with
     respect to the 132 phases of a Clements mesh (m=12, n=6), for 64 phase sets:
-    mesh -> amplitudes (complex64) -> loss -> adjoint -> mesh adjoint."""
+    mesh -> amplitudes of all 64 unitaries through one plan (complex64) -> loss
+    -> adjoint of all 64 -> mesh adjoint, through torch.autograd."""
     from paper_2204_00602_amd import autograd as ag, inputs
     k = slos.mesh_mzi_count(m)
     T = inputs.first_modes_input(m, n)
@@ -153,18 +154,16 @@ def time_gradient(torch, slos, steps, warmup, batch=64, m=12, n=6, targets=200):
     teacher = torch.from_numpy(inputs.mesh_phases(batch, k, 55)).cuda()
     idx = torch.tensor([slos.fock_rank(s) for s in inputs.uniform_fock_states(m, n, targets, 505)],
                        device="cuda")
-    plans = [slos.Plan(T, "c64", keep_layers=True) for _ in range(batch)]
+    plan = slos.Plan(T, "c64", keep_layers=True, options={"max_batch": batch})
     with torch.no_grad():
         Ut = slos.mesh_unitary(teacher, m, "c64")
-        p_t = torch.stack([plans[b].probs(Ut[b].contiguous())[idx] for b in range(batch)]).to(torch.float64)
+        p_t = (plan.amplitudes_many(Ut.contiguous())[:, idx].abs() ** 2).to(torch.float64)
 
     def step():
         ph = phases.clone().requires_grad_(True)
         U = ag.mesh(ph, m, "c64")
-        loss = 0.0
-        for b in range(batch):
-            a = ag.amplitudes(plans[b], U[b].contiguous())
-            loss = loss + (((a[idx].abs() ** 2).to(torch.float64) - p_t[b]) ** 2).sum()
+        a = ag.amplitudes_many(plan, U.contiguous())
+        loss = (((a[:, idx].abs() ** 2).to(torch.float64) - p_t) ** 2).sum()
         loss.backward()
         return ph.grad
 
@@ -177,11 +176,11 @@ def time_gradient(torch, slos, steps, warmup, batch=64, m=12, n=6, targets=200):
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / steps
     finite = bool(torch.isfinite(g).all().item())
-    for p in plans:
-        p.close()
+    plan.close()
     return {
         "workload": f"Clements mesh m={m} ({k} MZIs, {2 * k} phases), n={n}, batch {batch} phase sets, "
-                    f"{targets} seeded targets, complex64 forward + adjoint, torch.autograd",
+                    f"{targets} seeded targets, complex64 forward + adjoint of all {batch} unitaries "
+                    f"through one plan, torch.autograd",
         "ms_per_batch": ms, "gradient_evals_per_s": batch / (ms * 1e-3), "finite": finite,
     }
 
