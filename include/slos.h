@@ -90,6 +90,10 @@ typedef struct slos_options {
                                 (default 4)                                          */
     int32_t max_batch;       /* unitaries per *_many call, 1..65535 (default 1): the
                                 plan holds layer buffers for that many instances   */
+    int32_t wide_descriptors;/* 1: use the 32-group, 64-bit-delta leaf descriptors on
+                                every layer; 0 (default): only where a leaf needs
+                                them (more than 16 occupied high modes, or a layer
+                                of 2^32 states or more)                             */
 } slos_options_t;
 
 /* ---- Fock-space arithmetic (host only; no device needed) ------------------ */
@@ -164,9 +168,9 @@ int slos_probs_many(slos_plan_t plan, int batch, const void *U, void *probs, dou
 /* ---- weak simulation from the strong one ------------------------------------ */
 
 /*
- * Cumulative probability table of `probs` (device, M values in colex order:
- * fp32 for a C64 plan, fp64 for C128, e.g. the output of slos_probs; need not
- * be normalised).  FP64 sums of blocks of SLOS_CDF_BLOCK (1024) states and
+ * Cumulative probability table of `probs` (device, 16-byte aligned, M values in
+ * colex order: fp32 for a C64 plan, fp64 for C128, e.g. the output of
+ * slos_probs; need not be normalised).  FP64 sums of blocks of SLOS_CDF_BLOCK (1024) states and
  * their exclusive prefix, kept by the plan (one table per plan; a later call
  * replaces it).  Deterministic.  slos_marginals and slos_sample read this table
  * together with the same `probs`.

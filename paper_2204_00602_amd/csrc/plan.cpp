@@ -535,6 +535,8 @@ int slos_plan_ex(int m, int n, const int32_t *input_state, int flags, const slos
     if (o.xcd_chunk == 0) o.xcd_chunk = 128;
     if (o.ticket_leaves == 0) o.ticket_leaves = 4;
     if (o.max_batch == 0) o.max_batch = 1;
+    if (o.wide_descriptors < 0 || o.wide_descriptors > 1)
+        return fail(SLOS_ERR_INVALID_ARG, "wide_descriptors must be 0 or 1");
     if (o.max_batch < 1 || o.max_batch > 65535)
         return fail(SLOS_ERR_INVALID_ARG, "max_batch = %d outside [1, 65535]", o.max_batch);
     if (o.ticket_leaves < 1 || o.ticket_leaves > 4096)
@@ -643,7 +645,7 @@ int slos_plan_ex(int m, int n, const int32_t *input_state, int flags, const slos
         std::vector<uint8_t> modes;
         for (int k = 1; k <= n; ++k) {
             // narrow unless a leaf has more than 16 groups or a 64-bit delta
-            int wide = 0;
+            int wide = p->opts.wide_descriptors > 0 ? 1 : 0;
             for (const LeafRec &L : p->leaves[k]) {
                 LeafDescHead h;
                 p->describe(k, L, h, deltas, modes);
@@ -1120,6 +1122,7 @@ int slos_cdf(slos_plan_t p, const void *probs, void *stream)
     int rc = check_plan(p);
     if (rc) return rc;
     if (!probs) return fail(SLOS_ERR_INVALID_ARG, "probs is NULL");
+    if ((uintptr_t)probs % 16) return fail(SLOS_ERR_INVALID_ARG, "probs must be 16-byte aligned");
     int e = slos_launch_cdf(probs, p->c64 ? 1 : 0, (int64_t)p->Nk[p->n], p->d_cdf, stream);
     if (e) return hip_fail((hipError_t)e, "cumulative probability kernels");
     return SLOS_OK;

@@ -26,6 +26,9 @@ namespace {
 
 constexpr int kChunks = SLOS_CDF_BLOCK / 64;
 
+typedef float cdf_f4 __attribute__((ext_vector_type(4)));
+typedef double cdf_d2 __attribute__((ext_vector_type(2)));
+
 template <typename T>
 __global__ __launch_bounds__(256) void cdf_block_kernel(const T *__restrict__ P, int64_t M, int64_t nb,
                                                         double *__restrict__ bp)
@@ -33,17 +36,33 @@ __global__ __launch_bounds__(256) void cdf_block_kernel(const T *__restrict__ P,
     const int lane = threadIdx.x & 63;
     const int64_t gw = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
+    constexpr int per = SLOS_CDF_BLOCK / 64;  // states per lane, contiguous
     for (int64_t b = gw; b < nb; b += nw) {
         const int64_t base = b * SLOS_CDF_BLOCK;
         double s = 0.0;
-        T v[kChunks];
+        if (base + SLOS_CDF_BLOCK <= M) {
+            // whole block: 16-byte loads, all in flight, then a fixed-order sum
+            const T *q = P + base + (int64_t)lane * per;
+            if constexpr (sizeof(T) == 4) {
+                cdf_f4 v[per / 4];
 #pragma unroll
-        for (int i = 0; i < kChunks; ++i) {  // all loads in flight, then a fixed-order sum
-            const int64_t x = base + i * 64 + lane;
-            v[i] = x < M ? __builtin_nontemporal_load(&P[x]) : (T)0;
+                for (int i = 0; i < per / 4; ++i) v[i] = __builtin_nontemporal_load((const cdf_f4 *)q + i);
+#pragma unroll
+                for (int i = 0; i < per / 4; ++i)
+                    s += ((double)v[i].x + (double)v[i].y) + ((double)v[i].z + (double)v[i].w);
+            } else {
+                cdf_d2 v[per / 2];
+#pragma unroll
+                for (int i = 0; i < per / 2; ++i) v[i] = __builtin_nontemporal_load((const cdf_d2 *)q + i);
+#pragma unroll
+                for (int i = 0; i < per / 2; ++i) s += v[i].x + v[i].y;
+            }
+        } else {
+            for (int i = 0; i < per; ++i) {
+                const int64_t x = base + (int64_t)lane * per + i;
+                if (x < M) s += (double)P[x];
+            }
         }
-#pragma unroll
-        for (int i = 0; i < kChunks; ++i) s += (double)v[i];
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
         if (lane == 0) bp[b] = s;

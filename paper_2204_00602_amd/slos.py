@@ -41,7 +41,8 @@ class Options(ctypes.Structure):
     _fields_ = [("leaf_max", ctypes.c_int32), ("comp_from_layer", ctypes.c_int32),
                 ("block_threads", ctypes.c_int32), ("grid_blocks", ctypes.c_int32),
                 ("outputs_per_lane", ctypes.c_int32), ("xcd_chunk", ctypes.c_int32),
-                ("ticket_leaves", ctypes.c_int32), ("max_batch", ctypes.c_int32)]
+                ("ticket_leaves", ctypes.c_int32), ("max_batch", ctypes.c_int32),
+                ("wide_descriptors", ctypes.c_int32)]
 
 
 _lib = None

@@ -103,6 +103,8 @@ def test_config2_m12_n6_all_outputs(dtype):
     {"leaf_max": 300, "outputs_per_lane": 2, "block_threads": 128, "grid_blocks": 3},
     {"leaf_max": 1, "outputs_per_lane": 4, "grid_blocks": 1},
     {"leaf_max": 65536},
+    {"wide_descriptors": 1},
+    {"wide_descriptors": 1, "leaf_max": 5, "outputs_per_lane": 2},
 ])
 def test_tilings_and_launch_shapes_agree(opts):
     T, U = haar_case(9, [2, 0, 1, 0, 0, 2, 0, 0, 1], 9)
@@ -111,6 +113,19 @@ def test_tilings_and_launch_shapes_agree(opts):
     p, out, s = run(T, U, "c128", options=opts)
     check_c128(gather(p, out, S), ref, S.shape[0])
     assert abs(s - 1.0) <= 1e-12
+
+
+@pytest.mark.parametrize("comp", [False, True, "knuth"])
+def test_wide_descriptors_every_variant(comp):
+    """The 32-group descriptor form (normally only for > 16 occupied high modes
+    or layers of 2^32 states) forced on a small case, c64 variants and c128."""
+    T, U = haar_case(12, [1] * 6 + [0] * 6, 2)
+    S = oracle.fock_states(12, 6)
+    Pref = oracle.probabilities(U, T, S)
+    p, out, s = run(T, U, "c64", compensated=comp, options={"wide_descriptors": 1})
+    check_c64_probs(np.abs(gather(p, out, S).astype(np.complex128)) ** 2, Pref, S.shape[0])
+    p, out, s = run(T, U, "c128", options={"wide_descriptors": 1}, probs=True)
+    assert np.abs(gather(p, out, S) - Pref).max() <= 1e-12 * max(1.0, Pref.max())
 
 
 @pytest.mark.parametrize("comp", [False, True])
