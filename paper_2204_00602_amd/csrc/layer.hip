@@ -578,10 +578,20 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 3 : (RR <= 2 ? 4 : 1)) void l
         ++it;
     }
     if (sizeof(T) == 4 && MODE == SLOS_MODE_MID && p.vmax_out) {
-        // non-negative floats order like their bit patterns
+        // one atomic per workgroup, and only if it raises the recorded value
+        // (all workgroups of a layer share the slot); non-negative floats
+        // order like their bit patterns
+        __shared__ float wmax[4];
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) omax = fmaxf(omax, __shfl_xor(omax, o, 64));
-        if (lane == 0) atomicMax(p.vmax_out, __float_as_uint(omax));
+        if (lane == 0) wmax[wv] = omax;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            for (int w = 1; w < W; ++w) omax = fmaxf(omax, wmax[w]);
+            const uint32_t bits = __float_as_uint(omax);
+            if (bits > __hip_atomic_load(p.vmax_out, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+                atomicMax(p.vmax_out, bits);
+        }
     }
 }
 
