@@ -7,11 +7,14 @@
 // the normalisation a(S) = A_n[S] sqrt(prod s_j!) / sqrt(prod t_i!) (Eq.
 // eqperm), |a|^2 and an FP64 per-wave partial of sum_S P(S).
 //
-// Work unit: one leaf per wave (see LeafRec).  The wave computes, with scalar
-// arithmetic, the base rank in A_{k-1} of every predecessor block reached
-// through a high mode; those reads are contiguous (lane x reads base + x).
-// Predecessors through the q low modes come from the per-(q, K) inner table.
-// U's column i_k is staged in LDS; u[255] = 0 pads short term lists.
+// Work unit: one leaf per workgroup at a time (see LeafRec and the host-built
+// leaf descriptors).  The workgroup stages the leaf's low block in LDS and
+// deals the leaf's tiles to its waves.  Every predecessor block reached
+// through a high mode is contiguous (lane x reads base + x), its base taken
+// from the descriptor; predecessors through the q low modes come from the
+// per-(q, K) inner table and the staged block.  U's column i_k is staged in
+// LDS; u[255] = 0 pads short term lists.  The batch kernel further down runs
+// whole small instances per workgroup, one leaf per wave.
 #include <hip/hip_runtime.h>
 
 #include "slos_internal.h"

@@ -124,8 +124,8 @@ struct LayerParams {
     int col;                // input mode i_k of the photon added at this layer
     double norm_t;          // 1 / sqrt(prod_i t_i!)
     double *partials;       // one FP64 partial sum of P per leaf (last layer)
-    uint32_t low_max;       // LDS elements reserved per wave for a low block
-    uint32_t lds_wave_bytes;// LDS bytes per wave (low block staging slice)
+    uint32_t low_max;       // largest low block of the layer (elements)
+    uint32_t lds_wave_bytes;// LDS bytes of one low-block staging slice
     // Leaves are dealt to XCDs in chunks of xcd_chunk consecutive leaves
     // (chunk c to the workgroups with blockIdx.x % SLOS_XCDS == c % SLOS_XCDS,
     // which the dispatcher places on one XCD): each L2 sees contiguous runs of
@@ -158,7 +158,7 @@ struct LayerLaunch {
     int rr;           // outputs per lane per tile: 1, 2, 4
     int threads;      // workgroup size (multiple of 64, <= 256)
     int grid;         // workgroups
-    uint32_t low_max; // largest low block of the layer (elements): LDS per wave
+    uint32_t low_max; // largest low block of the layer (elements): one LDS slice
     int wide;         // 1: LeafDescWide descriptors
 };
 
