@@ -232,6 +232,30 @@ def time_sampling(torch, slos, T, U_np, steps, warmup, samples=1 << 20):
     return res
 
 
+def time_select(torch, slos, T, U_np, steps, warmup, count=10_000):
+    """Amplitudes of 10,000 uniformly drawn outputs of the m=24, n=12 workload
+    alone (the recurrence over the 2^12-state sub-lattice below each target),
+    complex64 and complex128; targets uploaded from host memory in the call."""
+    from paper_2204_00602_amd import inputs
+    S = inputs.uniform_fock_states(M_MODES, N_PHOTONS, count, SAMPLE_SEED)
+    res = {"workload": f"m=24 n=12, {count} seeded uniform outputs (seed {SAMPLE_SEED}), one workgroup each"}
+    for dt in ("c64", "c128"):
+        plan = slos.Plan(T, dt)
+        Ud = torch.from_numpy(U_np).to(torch.complex64 if dt == "c64" else torch.complex128).cuda()
+        for _ in range(warmup):
+            plan.select(Ud, S)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            plan.select(Ud, S)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        res[dt] = {"ms": ms, "amplitudes_per_s": count / (ms * 1e-3)}
+        plan.close()
+        torch.cuda.empty_cache()
+    return res
+
+
 def cpu_baseline(U_np, T, target_s=20.0):
     """The oracle, untuned, on a bounded sample of the workload's outputs."""
     import oracle
@@ -377,6 +401,11 @@ def main():
         print(f"[bench] sampling: cdf {sm['cdf_ms']:.3f} ms, P(K) {sm['marginals_ms']:.3f} ms, "
               f"samples {sm['sample_ms']:.3f} ms, post-selection {sm['postselect_ms']:.3f} ms",
               file=sys.stderr, flush=True)
+    if not args.no_extras and not args.only:
+        print("[bench] selected outputs: 10,000 targets", file=sys.stderr, flush=True)
+        line["selected"] = time_select(torch, slos, T, U, max(3, args.steps // 4), 1)
+        print(f"[bench] selected: c64 {line['selected']['c64']['ms']:.3f} ms, "
+              f"c128 {line['selected']['c128']['ms']:.3f} ms", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(U, T)

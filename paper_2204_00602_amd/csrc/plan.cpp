@@ -172,6 +172,8 @@ struct slos_plan_s {
     double *d_cdf = nullptr;          // block prefix of the last slos_cdf input (nb + 1), then run prefixes
     int64_t *d_pk_ends = nullptr;     // C(K+n-1, n) for K = 1..m
     double *d_ps_partials = nullptr;  // post-selection partial sums + reduction stage
+    SelectTarget *d_sel = nullptr;    // target descriptors of the last slos_select call
+    size_t sel_cap = 0;
     // differentiation (SLOS_KEEP_LAYERS plans)
     std::vector<std::vector<BwdUnit>> units;   // per layer
     std::vector<uint32_t> succ;                // inner successor tables
@@ -393,6 +395,9 @@ struct slos_plan_s {
         d_pk_ends = nullptr;
         f(d_ps_partials);
         d_ps_partials = nullptr;
+        f(d_sel);
+        d_sel = nullptr;
+        sel_cap = 0;
         f(d_units);
         f(d_succ);
         f(d_hbase);
@@ -1186,6 +1191,81 @@ int slos_postselect(slos_plan_t p, const void *probs, const int32_t *group_of_mo
         e = slos_launch_postselect_table(ps, p->c64 ? 1 : 0, ranks, nranks, kept_sum, table, stream);
         if (e) return hip_fail((hipError_t)e, "post-selection table kernel");
     }
+    return SLOS_OK;
+}
+
+int slos_select(slos_plan_t p, const void *U, const int32_t *targets, int64_t count, void *out, void *stream)
+{
+    int rc = check_plan(p);
+    if (rc) return rc;
+    if (count < 0) return fail(SLOS_ERR_INVALID_ARG, "count = %lld is negative", (long long)count);
+    if (count == 0) return SLOS_OK;
+    if (!U || !targets || !out) return fail(SLOS_ERR_INVALID_ARG, "U, targets and out must not be NULL");
+    const int m = p->m, n = p->n;
+    const size_t es = p->elem();
+    // largest sub-lattice whose amplitudes, layers and masks fit a workgroup's LDS
+    const uint64_t r_cap = SLOS_LDS_DYNAMIC_MAX / (es + 5);
+    std::vector<SelectTarget> h;
+    uint32_t r_max = 1;
+    try {
+        h.resize((size_t)count);
+    } catch (std::bad_alloc &) {
+        return fail(SLOS_ERR_OOM, "host allocation of %lld target descriptors failed", (long long)count);
+    }
+    for (int64_t i = 0; i < count; ++i) {
+        const int32_t *s = targets + (size_t)i * m;
+        SelectTarget t{};
+        uint64_t R = 1;
+        int tot = 0;
+        double f = 1.0;
+        for (int j = 0; j < m; ++j) {
+            if (s[j] < 0) return fail(SLOS_ERR_INVALID_ARG, "target %lld has a negative occupation", (long long)i);
+            if (s[j] == 0) continue;
+            tot += s[j];
+            if (tot > n) break;
+            t.mode[t.nocc] = (uint8_t)j;
+            t.mult[t.nocc] = (uint8_t)s[j];
+            ++t.nocc;
+            R *= (uint64_t)s[j] + 1;
+            for (int v = 2; v <= s[j]; ++v) f *= v;
+            if (R > r_cap) break;
+        }
+        if (R > r_cap)
+            return fail(SLOS_ERR_INVALID_ARG,
+                        "target %lld: prod(s_j + 1) exceeds %llu states (one workgroup's LDS)", (long long)i,
+                        (unsigned long long)r_cap);
+        if (tot != n)
+            return fail(SLOS_ERR_INVALID_ARG, "target %lld does not hold n = %d photons", (long long)i, n);
+        t.R = (uint32_t)R;
+        t.fac = std::sqrt(f) * p->norm_t;
+        r_max = std::max(r_max, t.R);
+        h[(size_t)i] = t;
+    }
+    if ((size_t)count > p->sel_cap) {
+        if (p->d_sel) (void)hipFree(p->d_sel);
+        p->d_sel = nullptr;
+        p->sel_cap = 0;
+        if ((rc = alloc_dev((void **)&p->d_sel, (size_t)count * sizeof(SelectTarget), "target descriptors")))
+            return rc;
+        p->sel_cap = (size_t)count;
+    }
+    // the descriptors are read by the kernel: upload in order on the stream, then wait
+    hipError_t e = hipMemcpyAsync(p->d_sel, h.data(), (size_t)count * sizeof(SelectTarget), hipMemcpyHostToDevice,
+                                  (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "target upload");
+    SelectParams sp{};
+    sp.U = U;
+    sp.targets = p->d_sel;
+    sp.count = count;
+    sp.out = out;
+    sp.r_max = r_max;
+    sp.m = m;
+    sp.n = n;
+    for (int k = 0; k < n; ++k) sp.cols[k] = (uint8_t)p->photons[k];
+    int ke = slos_launch_select(sp, p->c64 ? 1 : 0, stream);
+    if (ke) return hip_fail((hipError_t)ke, "selected-output kernel");
+    e = hipStreamSynchronize((hipStream_t)stream);  // h must outlive the copy
+    if (e != hipSuccess) return hip_fail(e, "selected-output synchronisation");
     return SLOS_OK;
 }
 

@@ -291,3 +291,23 @@ struct PostselectParams {
 int slos_launch_postselect(const PostselectParams &p, int c64, void *stream);
 int slos_launch_postselect_table(const PostselectParams &p, int c64, const int64_t *ranks, int64_t nranks,
                                  const double *sum, double *table, void *stream);
+
+// selected outputs (select.hip)
+#define SLOS_SELECT_MAX_OCC 32
+struct SelectTarget {
+    uint32_t R;                          // prod over occupied modes of (s_j + 1)
+    uint32_t nocc;                       // occupied modes of the target
+    double fac;                          // sqrt(prod s_j!) / sqrt(prod t_i!)
+    uint8_t mode[SLOS_SELECT_MAX_OCC];   // occupied modes, ascending
+    uint8_t mult[SLOS_SELECT_MAX_OCC];   // their occupations
+};
+struct SelectParams {
+    const void *U;                // m x m, plan dtype
+    const SelectTarget *targets;  // device
+    int64_t count;
+    void *out;                    // count amplitudes, plan dtype
+    uint32_t r_max;               // largest R of the call (LDS sizing)
+    int m, n;
+    uint8_t cols[SLOS_MAX_PHOTONS];  // i_k, k = 1..n
+};
+int slos_launch_select(const SelectParams &p, int c64, void *stream);

@@ -79,6 +79,7 @@ def lib():
     L.slos_probs_many.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp]
     L.slos_backward_many.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp]
     L.slos_cdf.argtypes = [vp, vp, vp]
+    L.slos_select.argtypes = [vp, vp, i32p, ctypes.c_int64, vp, vp]
     L.slos_marginals.argtypes = [vp, vp, vp, vp]
     L.slos_sample.argtypes = [vp, vp, vp, ctypes.c_int64, vp, vp]
     L.slos_postselect.argtypes = [vp, vp, i32p, ctypes.c_int, i32p, i32p, vp, vp, vp, ctypes.c_int64, vp, vp]
@@ -98,7 +99,7 @@ def lib():
     L.slos_last_error.restype = ctypes.c_char_p
     for name in ("slos_fock_count", "slos_fock_rank", "slos_fock_unrank", "slos_plan",
                  "slos_plan_ex", "slos_plan_info", "slos_plan_leaf", "slos_amplitudes",
-                 "slos_probs", "slos_cdf", "slos_marginals", "slos_sample", "slos_postselect", "slos_amplitudes_many",
+                 "slos_probs", "slos_cdf", "slos_marginals", "slos_sample", "slos_postselect", "slos_select", "slos_amplitudes_many",
                  "slos_probs_many", "slos_backward_many", "slos_plan_set_timing", "slos_plan_layer_ms", "slos_backward",
                  "slos_mesh_unitary", "slos_mesh_backward", "slos_batch_plan", "slos_batch_offsets",
                  "slos_batch_amplitudes", "slos_batch_capture", "slos_batch_replay"):
@@ -329,6 +330,20 @@ class Plan:
         _check(self._lib.slos_backward(self._h, U.data_ptr(), grad_a.data_ptr(), grad_U.data_ptr(),
                                        _stream_ptr(stream)))
         return grad_U
+
+    def select(self, U, targets, out=None, stream=None):
+        """a(S) for the given output states only (count x m), via the
+        recurrence restricted to t <= S; returns a device tensor of count."""
+        import torch
+        self._check_U(U)
+        t = np.ascontiguousarray(np.asarray(targets, dtype=np.int32).reshape(-1, self.m))
+        if out is None:
+            out = torch.empty(t.shape[0], dtype=self._complex_dtype(), device=U.device)
+        elif out.dtype != self._complex_dtype() or out.numel() != t.shape[0] or not out.is_contiguous():
+            raise ValueError("out has the wrong dtype, size or layout")
+        _check(self._lib.slos_select(self._h, U.data_ptr(), t.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                     t.shape[0], out.data_ptr(), _stream_ptr(stream)))
+        return out
 
     # ---- weak simulation ----------------------------------------------------
     def _check_probs(self, probs):

@@ -199,3 +199,10 @@ def test_many_calls_validate_arguments():
     assert L.slos_backward_many(None, 1, None, None, None, None) == -1
     p = slos.Plan([1, 1, 0], "c64", host_only=True, options={"max_batch": 4})
     assert L.slos_probs_many(p._h, 2, None, None, None, None) == -1
+
+
+def test_select_validates_arguments():
+    L = slos.lib()
+    assert L.slos_select(None, None, None, 1, None, None) == -1
+    p = slos.Plan([1, 1, 0], "c64", host_only=True)
+    assert L.slos_select(p._h, None, None, 1, None, None) == -1

@@ -1,0 +1,92 @@
+"""GPU parity of amplitudes of selected outputs (the recurrence restricted to
+the states below each target) against the oracle's permanents."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2204_00602_amd import inputs, slos
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def need_gpu():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    slos.lib()
+
+
+def _u(U, dtype):
+    return torch.from_numpy(np.ascontiguousarray(U)).to(
+        torch.complex64 if dtype == "c64" else torch.complex128).cuda()
+
+
+def _check(a, ref, M, dtype):
+    if dtype == "c128":
+        err = np.abs(a - ref) / np.maximum(np.abs(ref), 1.0 / math.sqrt(M))
+        assert err.max() <= 1e-12, err.max()
+    else:
+        P, Pr = np.abs(a) ** 2, np.abs(ref) ** 2
+        err = np.abs(P - Pr) / np.maximum(Pr, 1.0 / M)
+        assert err.max() <= 1e-5, err.max()
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_config2_selected_outputs(dtype):
+    m, n = 12, 6
+    T, U = inputs.first_modes_input(m, n), inputs.haar_unitary(m, 2)
+    S = np.concatenate([inputs.uniform_fock_states(m, n, 500, 11), inputs.bunched_fock_states(m, n, 100)])
+    p = slos.Plan(T, dtype)
+    a = p.select(_u(U, dtype), S).cpu().numpy().astype(np.complex128)
+    _check(a, oracle.amplitudes(U, T, S), slos.fock_count(m, n), dtype)
+    # the full distribution at the same ranks
+    full = p.amplitudes(_u(U, dtype))
+    idx = torch.tensor([slos.fock_rank(s) for s in S], device="cuda")
+    tol = 1e-13 if dtype == "c128" else 3e-6
+    assert np.abs(a - full[idx].cpu().numpy()).max() <= tol
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_config3_selected_outputs(dtype):
+    m, n = 24, 12
+    T, U = inputs.first_modes_input(m, n), inputs.haar_unitary(m, 3)
+    S = np.concatenate([inputs.uniform_fock_states(m, n, 2000, 103), inputs.bunched_fock_states(m, n, 100)])
+    p = slos.Plan(T, dtype)
+    a = p.select(_u(U, dtype), S).cpu().numpy().astype(np.complex128)
+    _check(a, oracle.amplitudes(U, T, S), slos.fock_count(m, n), dtype)
+
+
+def test_cnot_logical_outputs(golden_dir):
+    g = json.load(open(os.path.join(golden_dir, "ralph_cnot.json")))
+    U = np.zeros((6, 6), np.complex128)
+    for j, row in enumerate(g["unitary"]):
+        for i, ((a, r), (b, s)) in enumerate(row):
+            U[j, i] = (a * math.sqrt(r) + 1j * b * math.sqrt(s)) / 3.0
+    names = sorted(g["logical_states"])
+    outs = [g["logical_states"][k] for k in names]
+    for kin in names:
+        p = slos.Plan(g["logical_states"][kin], "c128")
+        P = np.abs(p.select(_u(U, "c128"), outs).cpu().numpy()) ** 2
+        want = np.array([1 / 9 if g["expected_map"][kin] == ko else 0.0 for ko in names])
+        assert np.allclose(P, want, atol=1e-15)
+
+
+def test_select_edge_cases():
+    p = slos.Plan([0, 0, 0], "c128")
+    assert p.select(_u(np.eye(3), "c128"), [[0, 0, 0]]).cpu().tolist() == [1 + 0j]
+    p = slos.Plan([3], "c64")
+    a = p.select(_u(np.array([[0.6 + 0.8j]]), "c64"), [[3]]).cpu().numpy()
+    assert abs(a[0] - (0.6 + 0.8j) ** 3) <= 1e-6
+    p = slos.Plan([1, 1, 0], "c128")
+    with pytest.raises(slos.SlosError):
+        p.select(_u(np.eye(3), "c128"), [[1, 0, 0]])      # one photon, plan has two
+    with pytest.raises(slos.SlosError):
+        p.select(_u(np.eye(3), "c128"), [[3, -1, 0]])
+    assert p.select(_u(np.eye(3), "c128"), np.zeros((0, 3), np.int32)).numel() == 0
+    big = slos.Plan([1] * 14, "c64")
+    with pytest.raises(slos.SlosError):                  # 2^14 states exceed one workgroup's LDS
+        big.select(_u(np.eye(14), "c64"), [[1] * 14])
