@@ -173,6 +173,10 @@ struct slos_plan_s {
     int64_t *d_pk_ends = nullptr;     // C(K+n-1, n) for K = 1..m
     double *d_ps_partials = nullptr;  // post-selection partial sums + reduction stage
     SelectTarget *d_sel = nullptr;    // target descriptors of the last slos_select call
+    PsType *d_ps_types = nullptr;     // inner types of the last layer, table runs
+    uint32_t *d_ps_type_off = nullptr;// first table entry per inner-type index
+    uint8_t *d_ps_low = nullptr;      // group counts of every low state (per call)
+    uint32_t ps_ntypes = 0, ps_entries = 0;
     size_t sel_cap = 0;
     // differentiation (SLOS_KEEP_LAYERS plans)
     std::vector<std::vector<BwdUnit>> units;   // per layer
@@ -397,6 +401,12 @@ struct slos_plan_s {
         d_ps_partials = nullptr;
         f(d_sel);
         d_sel = nullptr;
+        f(d_ps_types);
+        d_ps_types = nullptr;
+        f(d_ps_type_off);
+        d_ps_type_off = nullptr;
+        f(d_ps_low);
+        d_ps_low = nullptr;
         sel_cap = 0;
         f(d_units);
         f(d_succ);
@@ -781,6 +791,33 @@ int slos_plan_ex(int m, int n, const int32_t *input_state, int flags, const slos
             (rc = dev_upload(&p->d_pk_ends, ends.data(), ends.size(), "marginal bounds")) ||
             (rc = alloc_dev((void **)&p->d_ps_partials, (SLOS_PS_MAX_WAVES + SLOS_REDUCE_STAGE) * sizeof(double),
                             "post-selection partial sums"))) {
+            p->free_device();
+            delete p;
+            return rc;
+        }
+    }
+    if (n > 0) {
+        // post-selection tables: the inner types the last layer's leaves use
+        std::vector<uint32_t> off(p->types.size(), 0xFFFFFFFFu);
+        std::vector<PsType> pt;
+        uint64_t entries = 0;
+        for (const LeafRec &L : p->leaves[n]) {
+            if (off[L.tab] != 0xFFFFFFFFu) continue;
+            const InnerType &ty = p->types[L.tab];
+            off[L.tab] = (uint32_t)entries;
+            pt.push_back(PsType{(uint32_t)entries, ty.size, ty.q, ty.K, 0});
+            entries += ty.size;
+        }
+        if (entries >= (1ull << 32)) {
+            p->free_device();
+            delete p;
+            return fail(SLOS_ERR_SIZE_OVERFLOW, "post-selection table exceeds 2^32 entries; lower leaf_max");
+        }
+        p->ps_ntypes = (uint32_t)pt.size();
+        p->ps_entries = (uint32_t)entries;
+        if ((rc = dev_upload(&p->d_ps_types, pt.data(), pt.size(), "post-selection types")) ||
+            (rc = dev_upload(&p->d_ps_type_off, off.data(), off.size(), "post-selection offsets")) ||
+            (rc = alloc_dev((void **)&p->d_ps_low, entries * SLOS_PS_MAX_GROUPS, "post-selection table"))) {
             p->free_device();
             delete p;
             return rc;
@@ -1181,9 +1218,18 @@ int slos_postselect(slos_plan_t p, const void *probs, const int32_t *group_of_mo
     const uint64_t threads = std::min<uint64_t>((M + 63) / 64, (uint64_t)SLOS_PS_MAX_WAVES * 64);
     ps.run = (M + threads - 1) / threads;
     ps.partials = p->d_ps_partials;
+    if (p->n > 0) {
+        ps.leaves = p->d_leaves + p->leaf_off[p->n];
+        ps.nleaves = p->leaves[p->n].size();
+        ps.type_off = p->d_ps_type_off;
+        ps.types = p->d_ps_types;
+        ps.ntypes = p->ps_ntypes;
+        ps.entries = p->ps_entries;
+        ps.low = p->d_ps_low;
+    }
     int e = slos_launch_postselect(ps, p->c64 ? 1 : 0, stream);
     if (e) return hip_fail((hipError_t)e, "post-selection kernel");
-    const uint64_t waves = (((M + ps.run - 1) / ps.run + 255) / 256) * 4;
+    const uint64_t waves = ps.nleaves > 0 ? (uint64_t)SLOS_PS_MAX_WAVES : (((M + ps.run - 1) / ps.run + 255) / 256) * 4;
     e = slos_launch_reduce(p->d_ps_partials, (int64_t)waves, p->d_ps_partials + SLOS_PS_MAX_WAVES, kept_sum,
                            stream);
     if (e) return hip_fail((hipError_t)e, "post-selection sum");

@@ -122,6 +122,118 @@ __global__ __launch_bounds__(256) void postselect_kernel(PostselectParams p)
     if (lane == 0) p.partials[tid / 64] = acc;
 }
 
+// ---- leaf path --------------------------------------------------------------
+// The last layer's leaves fix the occupations of their high modes and run
+// their K low photons over the q low modes in the colex order of F(q, K).
+// The group counts of an output are those of its leaf's high part (from the
+// leaf record) plus those of its low part, which depend only on the leaf's
+// inner type and the state's rank in it: ps_low_kernel tabulates them once per
+// call for the inner types the last layer uses, and ps_leaf_kernel reads P and
+// the table with the leaf's outputs (contiguous, so all accesses coalesce).
+
+// Occupations of colex rank `rank` of F(q, K) (the same decoding as unrank).
+__device__ void unrank_q(const PostselectParams &p, int q, int K, uint64_t rank, uint8_t *t)
+{
+    for (int j = 0; j < q; ++j) t[j] = 0;
+    int c = q + K - 2;
+    for (int r = K; r >= 1; --r) {
+        while (c >= r && binom_at(p, c, r) > rank) --c;
+        if (c < r - 1) c = r - 1;
+        rank -= (c >= r) ? binom_at(p, c, r) : 0;
+        t[c - (r - 1)] += 1;
+        --c;
+    }
+}
+
+__global__ __launch_bounds__(256) void ps_low_kernel(PostselectParams p)
+{
+    extern __shared__ unsigned char lds[];
+    uint8_t *t = lds + (size_t)threadIdx.x * 256;  // occupations of up to 255 low modes
+    const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= p.entries) return;
+    // inner type of entry e: last type with off <= e
+    uint32_t lo = 0, hi = p.ntypes;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) / 2;
+        if (p.types[mid].off <= e) lo = mid;
+        else hi = mid;
+    }
+    const PsType ty = p.types[lo];
+    unrank_q(p, ty.q, ty.K, e - ty.off, t);
+    uint8_t c[SLOS_PS_MAX_GROUPS] = {};
+    for (int j = 0; j < ty.q; ++j)
+        if (p.group[j] >= 0) c[p.group[j]] += t[j];
+    uint4 w;
+    w.x = c[0] | c[1] << 8 | c[2] << 16 | (uint32_t)c[3] << 24;
+    w.y = c[4] | c[5] << 8 | c[6] << 16 | (uint32_t)c[7] << 24;
+    w.z = c[8] | c[9] << 8 | c[10] << 16 | (uint32_t)c[11] << 24;
+    w.w = c[12] | c[13] << 8 | c[14] << 16 | (uint32_t)c[15] << 24;
+    ((uint4 *)p.low)[e] = w;
+}
+
+__device__ __forceinline__ uint32_t byte_of(const uint4 &w, int g)
+{
+    const uint32_t d = g < 4 ? w.x : g < 8 ? w.y : g < 12 ? w.z : w.w;
+    return (d >> (8 * (g & 3))) & 0xFFu;
+}
+
+// one wave per leaf of the last layer; one FP64 partial per wave
+template <typename T>
+__global__ __launch_bounds__(256) void ps_leaf_kernel(PostselectParams p)
+{
+    __shared__ int8_t grp[256];
+    for (int j = threadIdx.x; j < 256; j += blockDim.x) grp[j] = p.group[j];
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const uint64_t gw = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const uint64_t nw = (uint64_t)gridDim.x * (blockDim.x >> 6);
+    const T *P = (const T *)p.P;
+    T *out = (T *)p.masked;
+    double acc = 0.0;
+    // the 64-byte leaf record: lane i < 16 holds dword i (one coalesced load),
+    // fields are read back with readlane; the next record is fetched early
+    auto fetch = [&](uint64_t li) -> uint32_t {
+        return (li < p.nleaves && lane < 16) ? ((const uint32_t *)(p.leaves + li))[lane] : 0u;
+    };
+    auto rl = [](uint32_t v, int l) { return (uint32_t)__builtin_amdgcn_readlane((int)v, l); };
+    uint32_t rec = fetch(gw);
+    for (uint64_t li = gw; li < p.nleaves; li += nw) {
+        const uint32_t cur = rec;
+        rec = fetch(li + nw);
+        const uint64_t base = (uint64_t)rl(cur, 0) | ((uint64_t)rl(cur, 1) << 32);
+        const uint32_t size = rl(cur, 2), tab = rl(cur, 3);
+        const uint32_t nhp = (rl(cur, 4) >> 16) & 0xFFu;
+        // group counts of the high part (wave-uniform)
+        uint32_t hc[SLOS_PS_MAX_GROUPS];
+#pragma unroll
+        for (int g = 0; g < SLOS_PS_MAX_GROUPS; ++g) hc[g] = 0;
+        for (uint32_t i = 0; i < nhp; ++i) {
+            const uint32_t mode = (rl(cur, 8 + (int)(i >> 2)) >> (8 * (i & 3))) & 0xFFu;
+            const int g = grp[mode];
+#pragma unroll
+            for (int h = 0; h < SLOS_PS_MAX_GROUPS; ++h) hc[h] += (g == h) ? 1u : 0u;
+        }
+        const uint4 *low = (const uint4 *)p.low + p.type_off[tab];
+        for (uint32_t x = lane; x < size; x += 64) {
+            const uint4 w = low[x];
+            const T v = P[base + x];
+            bool ok = true;
+#pragma unroll
+            for (int g = 0; g < SLOS_PS_MAX_GROUPS; ++g) {
+                if (g < p.ngroups) {
+                    const uint32_t c = byte_of(w, g) + hc[g];
+                    ok = ok && c >= p.cmin[g] && c <= p.cmax[g];
+                }
+            }
+            if (ok) acc += (double)v;
+            if (out) out[base + x] = ok ? v : (T)0;
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if (lane == 0) p.partials[gw] = acc;
+}
+
 // table[i] = P[ranks[i]] / sum_kept if output ranks[i] is kept, else 0.
 template <typename T>
 __global__ __launch_bounds__(64) void postselect_table_kernel(PostselectParams p, const int64_t *ranks,
@@ -158,6 +270,21 @@ hipError_t allow_lds(K kernel, size_t bytes)
 int slos_launch_postselect(const PostselectParams &p, int c64, void *stream)
 {
     hipStream_t s = (hipStream_t)stream;
+    if (p.nleaves > 0) {
+        // leaf path: tabulate the low parts, then one wave per leaf
+        const int gl = (int)((p.entries + 255) / 256);
+        hipError_t e = allow_lds(ps_low_kernel, 256 * 256);
+        if (e != hipSuccess) return (int)e;
+        hipLaunchKernelGGL(ps_low_kernel, dim3(gl > 0 ? gl : 1), dim3(256), 256 * 256, s, p);
+        if ((e = hipGetLastError()) != hipSuccess) return (int)e;
+        const int grid = SLOS_PS_MAX_WAVES / 4;
+        if (c64)
+            hipLaunchKernelGGL(ps_leaf_kernel<float>, dim3(grid), dim3(256), 0, s, p);
+        else
+            hipLaunchKernelGGL(ps_leaf_kernel<double>, dim3(grid), dim3(256), 0, s, p);
+        return (int)hipGetLastError();
+    }
+    // no photons: one output, walked by one thread
     const uint64_t threads = (p.M + p.run - 1) / p.run;
     const int grid = (int)((threads + 255) / 256);
     const size_t lds = kPsHead + 256 * (size_t)(p.m + SLOS_PS_MAX_GROUPS);

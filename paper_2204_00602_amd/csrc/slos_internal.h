@@ -276,6 +276,14 @@ int slos_launch_sample(const void *P, int c64, int64_t M, const double *bp, cons
 // post-selection (postselect.hip)
 #define SLOS_PS_MAX_GROUPS 16
 #define SLOS_PS_MAX_WAVES 8192  // partial sums per post-selection launch
+// an inner type used by the last layer: its low states occupy table entries
+// [off, off + size)
+struct PsType {
+    uint32_t off;
+    uint32_t size;
+    uint16_t q, K;
+    uint32_t pad;
+};
 struct PostselectParams {
     const void *P;          // M probabilities (fp32 or fp64), colex order
     void *masked;           // P masked to the kept outputs, or NULL
@@ -287,6 +295,15 @@ struct PostselectParams {
     double *partials;       // one FP64 partial per wave
     int8_t group[256];      // group of each mode, -1: unconstrained
     uint8_t cmin[SLOS_PS_MAX_GROUPS], cmax[SLOS_PS_MAX_GROUPS];
+    // leaf path: the last layer's leaves, and per inner type used by them a
+    // run of the low-state table (SLOS_PS_MAX_GROUPS group counts per state)
+    const LeafRec *leaves;
+    uint64_t nleaves;
+    const uint32_t *type_off;    // per inner-type index: first table entry
+    const PsType *types;         // ntypes entries, ascending off
+    uint32_t ntypes;             // inner types used by the last layer
+    uint32_t entries;            // table entries (low states)
+    uint8_t *low;                // entries x SLOS_PS_MAX_GROUPS group counts
 };
 int slos_launch_postselect(const PostselectParams &p, int c64, void *stream);
 int slos_launch_postselect_table(const PostselectParams &p, int c64, const int64_t *ranks, int64_t nranks,
