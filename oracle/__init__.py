@@ -18,6 +18,12 @@ What each function follows (paper = arXiv 2204.00602):
   * clements_unitary: a rectangular ("square", Section 2) mesh of MZIs; the
     column layout is this project's reading (the paper only cites the mesh).
   * grad_U: d Perm(A)/d A[r][c] is the permanent of the (r, c) minor.
+  * source_emission / source_events / source_distribution /
+    source_performance: the imperfect-source mixture of Section 3.2.4 (emission
+    probability, pair emission through g2, indistinguishability), each event's
+    output law the convolution of its independent groups, summed over every
+    emission event; the readings are stated beside the functions and pinned by
+    the CNOT figures printed in Appendix A.4 (Fig. slos_output2).
 Parity status: every function here is pinned by tests/test_oracle_pins.py
 (closed forms, brute force, the paper's worked examples); none is unpinned.
 """
@@ -375,3 +381,136 @@ __all__ = [
     "clements_unitary", "grad_U", "mesh_loss", "mesh_grad_phases", "mesh_grad_phases_fd", "mesh_vjp",
     "fock_count", "derangements", "fibonacci", "num_threads",
 ]
+
+
+# ---------------------------------------------------------------------------
+# Imperfect sources (Section 3.2.4: the source model tunes emission
+# probability, multi-photon emission and indistinguishability; Appendix A.4
+# prints the performance of the Ralph CNOT under such sources).
+#
+# Readings (the paper names the parameters and prints their effect on one
+# gate, but gives no formulas):
+#   * every photon of the input T comes from a source of its own;
+#   * a source emits nothing, one photon or two, with P(>= 1) = beta (the
+#     emission probability) and g2 = 2 p2 / (p1 + 2 p2)^2 (the second-order
+#     autocorrelation of the emitted light, "multiphoton_component");
+#   * the first photon of an emission shares the common wavepacket with
+#     probability sqrt(V), else it is distinguishable from every other photon,
+#     so two emitted photons interfere with probability V (the HOM visibility);
+#   * the second photon of a two-photon emission is distinguishable from every
+#     other photon.
+# Photons of different wavepackets do not interfere: the output distribution
+# of one emission event is the convolution of the distributions of its groups
+# of indistinguishable photons (each group's by Eq. eqperm).
+# ---------------------------------------------------------------------------
+
+def source_emission(beta: float, g2: float):
+    """(p0, p1, p2) of one source: p1 + p2 = beta and 2 p2 / (p1 + 2 p2)^2 = g2.
+
+    Solving the second for p2 with p1 = beta - p2 gives the quadratic
+    g2 p2^2 - (1 - beta g2) p2 + beta^2 g2 / 2 = 0, whose smaller root is taken
+    (the one that vanishes with g2)."""
+    if g2 == 0.0:
+        p2 = 0.0
+    else:
+        p2 = (1.0 - beta * g2 - math.sqrt(1.0 - 2.0 * beta * g2)) / g2
+    return 1.0 - beta, beta - p2, p2
+
+
+def _states_index(m: int, n: int):
+    S = fock_states(m, n)
+    return S, {tuple(int(v) for v in s): i for i, s in enumerate(S)}
+
+
+def source_events(T, beta: float, g2: float, V: float):
+    """All emission events of the sources behind input T, with their weights.
+
+    Each event is (weight, main, dist): `main` is the occupation vector of the
+    photons in the common wavepacket and `dist` the input modes of the
+    distinguishable photons.  Per source, in this order: nothing; one photon,
+    common; one photon, distinguishable; two photons, the first common; two
+    photons, the first distinguishable (the second is always distinguishable).
+    """
+    T = [int(v) for v in T]
+    m = len(T)
+    modes = [i for i in range(m) for _ in range(T[i])]
+    p0, p1, p2 = source_emission(beta, g2)
+    x = math.sqrt(V)
+    outcomes = [(p0, 0, 0), (p1 * x, 1, 0), (p1 * (1 - x), 0, 1), (p2 * x, 1, 1), (p2 * (1 - x), 0, 2)]
+    events = []
+
+    def rec(s, w, main, dist):
+        if s == len(modes):
+            events.append((w, tuple(main), tuple(dist)))
+            return
+        for ws, in_main, ndist in outcomes:
+            if ws == 0.0:
+                continue
+            main2 = list(main)
+            main2[modes[s]] += in_main
+            rec(s + 1, w * ws, main2, dist + [modes[s]] * ndist)
+
+    rec(0, 1.0, [0] * m, [])
+    return events
+
+
+def source_distribution(U, T, beta: float, g2: float, V: float, nmax: int):
+    """Output distribution of the imperfect-source mixture, photon numbers
+    0..nmax: a list whose entry N is (states, probs) over S_{m,N} (fock_states
+    order).  Sum over the emission events of weight x the convolution of the
+    common group's P (Eq. eqperm, by permanents) with one |U[:, i]|^2 per
+    distinguishable photon; counts above nmax are dropped."""
+    U = np.asarray(U, dtype=np.complex128)
+    m = U.shape[0]
+    Q = np.abs(U) ** 2
+    idx = [_states_index(m, N) for N in range(nmax + 1)]
+    out = [np.zeros(len(idx[N][0])) for N in range(nmax + 1)]
+    main_cache = {}
+    for w, main, dist in source_events(T, beta, g2, V):
+        nm = sum(main)
+        if nm > nmax:
+            continue
+        if main not in main_cache:
+            main_cache[main] = probabilities(U, np.asarray(main), idx[nm][0])
+        cur = {tuple(int(v) for v in s): p for s, p in zip(idx[nm][0], main_cache[main])}
+        for i in dist:
+            if sum(next(iter(cur))) + 1 > nmax:
+                cur = None
+                break
+            nxt = {}
+            for s, p in cur.items():
+                for j in range(m):
+                    if Q[j, i] == 0.0:
+                        continue
+                    t = list(s)
+                    t[j] += 1
+                    t = tuple(t)
+                    nxt[t] = nxt.get(t, 0.0) + p * Q[j, i]
+            cur = nxt
+        if cur is None:
+            continue
+        N = nm + len(dist)
+        for s, p in cur.items():
+            out[N][idx[N][1][s]] += w * p
+    return [(idx[N][0], out[N]) for N in range(nmax + 1)]
+
+
+def source_performance(dist, group_of_mode, count_min, count_max, min_modes: int):
+    """Processor figures over a graded distribution (list of (states, probs)):
+    physical = total probability of the outputs with at least `min_modes`
+    occupied modes; kept = the part of it whose mode groups hold between
+    count_min[g] and count_max[g] photons.  The gate performance is kept /
+    physical."""
+    g = np.asarray(group_of_mode)
+    phys = kept = 0.0
+    for states, probs in dist:
+        if len(states) == 0:
+            continue
+        occ = (states > 0).sum(axis=1) >= min_modes
+        ok = occ.copy()
+        for k in range(len(count_min)):
+            c = states[:, g == k].sum(axis=1)
+            ok &= (c >= count_min[k]) & (c <= count_max[k])
+        phys += float(np.sum(probs[occ]))
+        kept += float(np.sum(probs[ok]))
+    return phys, kept

@@ -442,3 +442,129 @@ def test_postselect_partitions_the_distribution():
     # an empty top-mode group is Eq. eqpk's event
     _, pk = oracle.postselect(P, S, [-1, -1, 0, 0, 0], [0], [0])
     assert pk == pytest.approx(oracle.partial_certificate(P, S, 2), abs=1e-15)
+
+
+# --- imperfect sources (Section 3.2.4; Appendix A.4, Fig. slos_output2) ------
+
+_CNOT_HERALDED = ([2, 0, 0, 1, 1, 3], [1, 1, 0, 0], [1, 1, 0, 0])
+
+
+@pytest.mark.parametrize("beta,g2", [(1.0, 0.0), (0.5, 0.1), (0.9, 0.05), (0.3, 1.0), (1.0, 0.5)])
+def test_source_emission_inverts_g2(beta, g2):
+    p0, p1, p2 = oracle.source_emission(beta, g2)
+    assert min(p0, p1, p2) >= 0.0
+    assert p0 + p1 + p2 == pytest.approx(1.0, abs=1e-15)
+    assert p1 + p2 == pytest.approx(beta, abs=1e-15)
+    assert 2 * p2 / (p1 + 2 * p2) ** 2 == pytest.approx(g2, abs=1e-12)
+
+
+@pytest.mark.parametrize("case", [0, 1, 2])
+def test_source_cnot_matches_printed_performance(golden_dir, case):
+    """Fig. slos_output2: ratio of 2-photon samples and gate performance for a
+    perfect source, a 50% bright one, and one that also emits pairs (g2 = 0.1)
+    with indistinguishability 0.95; the printed counts are consistent with the
+    model's conditional distribution."""
+    g = json.load(open(os.path.join(golden_dir, "cnot_source.json")))
+    U = _cnot_unitary(json.load(open(os.path.join(golden_dir, "ralph_cnot.json"))))
+    c = g["cases"][case]
+    T = g["input"]
+    d = oracle.source_distribution(U, T, c["emission_probability"], c["multiphoton_component"],
+                                   c["indistinguishability"], 2 * sum(T))
+    phys, kept = oracle.source_performance(d, *_CNOT_HERALDED, min_modes=sum(T))
+    if "physical" in c:
+        assert phys == pytest.approx(c["physical"][0] / c["physical"][1], abs=1e-14)
+        assert kept / phys == pytest.approx(c["logical"][0] / c["logical"][1], abs=1e-14)
+    else:
+        assert abs(phys - c["physical_printed"]) < 5e-7
+        assert abs(kept / phys - c["logical_printed"]) < 5e-7
+    # the printed sample counts: each within 4 sigma of the conditional law
+    n = g["samples"]
+    states, probs = d[sum(T)]
+    for key, cnt in c["counts"].items():
+        s = np.array([int(v) for v in key.split(",")])
+        p = probs[np.all(states == s, axis=1)][0] / kept
+        assert abs(cnt - n * p) <= 4 * math.sqrt(n * p * (1 - p)) + 1e-9, (key, cnt, n * p)
+
+
+@pytest.mark.parametrize("V", [0.0, 0.3, 0.95, 1.0])
+def test_source_hom_visibility(V):
+    """Two sources on a 50:50 beam splitter (Eq. eq:bs): the coincidence rate is
+    (1 - V) / 2 and each bunched output (1 + V) / 4, V being the HOM visibility."""
+    U = oracle.beam_splitter_rx(math.pi / 2)
+    d = oracle.source_distribution(U, [1, 1], 1.0, 0.0, V, 2)
+    states, probs = d[2]
+    P = {tuple(s): p for s, p in zip(states.tolist(), probs)}
+    assert P[(1, 1)] == pytest.approx((1 - V) / 2, abs=1e-15)
+    assert P[(2, 0)] == pytest.approx((1 + V) / 4, abs=1e-15)
+    assert d[0][1].sum() == 0.0 and d[1][1].sum() == 0.0
+
+
+def test_source_perfect_reduces_to_eqperm():
+    U = inputs.haar_unitary(5, 21)
+    T = [1, 0, 2, 0, 1]
+    d = oracle.source_distribution(U, T, 1.0, 0.0, 1.0, 8)
+    for N, (states, probs) in enumerate(d):
+        if N == 4:
+            assert np.allclose(probs, oracle.probabilities(U, T, states), atol=1e-15, rtol=0)
+        else:
+            assert probs.sum() == 0.0
+
+
+def test_source_distinguishable_is_independent_photons():
+    """V = 0: each photon picks its output mode j with probability |U[j, i]|^2 on
+    its own; brute force over the m^n joint choices."""
+    import itertools
+    U = inputs.haar_unitary(3, 22)
+    T = [2, 1, 0]
+    modes = [0, 0, 1]
+    want = {}
+    for js in itertools.product(range(3), repeat=3):
+        p = np.prod([abs(U[j, i]) ** 2 for j, i in zip(js, modes)])
+        s = tuple(np.bincount(js, minlength=3))
+        want[s] = want.get(s, 0.0) + p
+    d = oracle.source_distribution(U, T, 1.0, 0.0, 0.0, 3)
+    states, probs = d[3]
+    for s, p in zip(states.tolist(), probs):
+        assert p == pytest.approx(want.get(tuple(s), 0.0), abs=1e-15)
+
+
+@pytest.mark.parametrize("beta,g2,V", [(0.9, 0.05, 0.9), (0.6, 0.3, 0.5), (1.0, 0.2, 0.0)])
+def test_source_count_law_and_mean_occupation(beta, g2, V):
+    """Whatever U and V: the photon-number law is the product of the sources'
+    laws (coefficients of prod (p0 + p1 z + p2 z^2)); the mean occupation of
+    output mode j is sum over sources of (p1 + 2 p2) |U[j, i_s]|^2; the total is 1."""
+    U = inputs.haar_unitary(4, 23)
+    T = [1, 1, 0, 1]
+    n = sum(T)
+    d = oracle.source_distribution(U, T, beta, g2, V, 2 * n)
+    p0, p1, p2 = oracle.source_emission(beta, g2)
+    law = np.array([1.0])
+    for _ in range(n):
+        law = np.convolve(law, [p0, p1, p2])
+    got = np.array([probs.sum() for _, probs in d])
+    assert np.allclose(got, law, atol=1e-14, rtol=0)
+    mean = sum((states * probs[:, None]).sum(axis=0) for states, probs in d if len(states))
+    want = (p1 + 2 * p2) * (np.abs(U) ** 2 @ np.array(T, float))
+    assert np.allclose(mean, want, atol=1e-14, rtol=0)
+
+
+def test_source_truncation_keeps_lower_counts():
+    U = inputs.haar_unitary(4, 24)
+    full = oracle.source_distribution(U, [1, 0, 1, 0], 0.8, 0.2, 0.7, 4)
+    cut = oracle.source_distribution(U, [1, 0, 1, 0], 0.8, 0.2, 0.7, 2)
+    for N in range(3):
+        assert np.array_equal(full[N][1], cut[N][1])
+
+
+def test_source_pair_photon_is_distinguishable():
+    """HOM with pair emission (beta = 1, V = 1): a 3-photon event is a HOM pair
+    ((2,0) or (0,2), 1/2 each) plus an independent photon (1/2 per port), so each
+    of the four 3-photon outputs has probability 2 p1 p2 / 4.  A pair photon that
+    interfered would give (3,0) a weight of 3/8 instead of 1/4."""
+    U = oracle.beam_splitter_rx(math.pi / 2)
+    p0, p1, p2 = oracle.source_emission(1.0, 0.2)
+    d = oracle.source_distribution(U, [1, 1], 1.0, 0.2, 1.0, 4)
+    states, probs = d[3]
+    for s, p in zip(states.tolist(), probs):
+        assert p == pytest.approx(p1 * p2 / 2, abs=1e-15), s
+    assert d[2][1][np.all(d[2][0] == [1, 1], axis=1)][0] == pytest.approx(0.0, abs=1e-16)
