@@ -304,6 +304,77 @@ int slos_batch_amplitudes(slos_batch_t batch, const void *U, void *out, double *
 int slos_batch_capture(slos_batch_t batch, const void *U, void *out, double *sum_p);
 int slos_batch_replay(slos_batch_t batch, void *stream);
 
+/* ---- imperfect sources ------------------------------------------------------- */
+
+/*
+ * Source model (Section 3.2.4: a Processor's source tunes its emission
+ * probability, multi-photon emission and indistinguishability; Appendix A.4,
+ * Fig. slos_output2, prints their effect on the Ralph CNOT).  Every photon of
+ * the input state comes from a source of its own, which emits nothing (p0),
+ * one photon (p1) or two (p2), with p1 + p2 = emission_probability and
+ * multiphoton_component = g2 = 2 p2 / (p1 + 2 p2)^2.  An emitted first photon
+ * shares the common wavepacket with probability sqrt(indistinguishability)
+ * (two such photons interfere with probability V, the HOM visibility), else it
+ * is distinguishable from every other photon; the second photon of a pair is
+ * always distinguishable.  Photons of different wavepackets do not interfere.
+ * Defaults (src = NULL): a perfect source (1, 0, 1).
+ */
+typedef struct {
+    double emission_probability;   /* (0, 1]                              */
+    double multiphoton_component;  /* g2 in [0, 1], with its product by the
+                                      emission probability at most 1/2     */
+    double indistinguishability;   /* V in [0, 1]                          */
+} slos_source_params_t;
+
+typedef struct slos_source_s *slos_source_t;
+
+/*
+ * Plan the output distribution of the source mixture behind input_state (host,
+ * m int32, n = sum <= 12 photons, i.e. sources) over the photon numbers
+ * 0..nmax (nmax < 0: 2n when pairs are possible, else n; nmax <= 16; the
+ * states of photon numbers above nmax are dropped, those below are exact).
+ * Output layout ("graded"): photon number k occupies elements
+ * [offsets[k], offsets[k+1]) in colex order, offsets from slos_source_info;
+ * fewer than 2^32 states in all.  opts: leaf_max (default 1024) only.  The
+ * plan allocates 1.5 x 2^n graded FP64 vectors of device scratch, the leaf
+ * tables of photon numbers 1..nmax and a batch of the 2^n common-wavepacket
+ * groups; it owns them until slos_source_destroy.
+ * Errors: INVALID_ARG (bad sizes or source parameters), SIZE_OVERFLOW, OOM,
+ * NO_DEVICE.
+ */
+int slos_source_plan(int m, const int32_t *input_state, const slos_source_params_t *src, int nmax,
+                     const slos_options_t *opts, slos_source_t *out);
+void slos_source_destroy(slos_source_t source);
+/* Total states over photon numbers 0..nmax (-1 for a NULL plan). */
+int64_t slos_source_num_outputs(slos_source_t source);
+/* offsets (host, nmax + 2 int64, or NULL); emission (host, 3 doubles: p0,
+ * p1, p2 of one source, or NULL). */
+int slos_source_info(slos_source_t source, int64_t *offsets, double *emission);
+
+/*
+ * probs (device, num_outputs FP64, graded layout) = the mixture's output
+ * probabilities for U (device, complex128 m x m, row = output mode).  The
+ * common-wavepacket group of every subset of sources runs through the batch
+ * kernel; a distinguishable photon entering mode i is the real-weight layer
+ * P'[t] = sum_{j: t_j > 0} |U[j, i]|^2 P[t - e_j]; the subsets fold source by
+ * source in 3 (2^n - 1) such passes.  FP64 throughout.  Asynchronous.
+ */
+int slos_source_probs(slos_source_t source, const void *U, double *probs, void *stream);
+
+/*
+ * Per photon number k = 0..nmax, result[3k .. 3k+2] (host) = total
+ * probability, its part over the outputs with at least min_modes occupied
+ * modes ("physical": at least min_modes detectors click), and the part of
+ * that which passes the mode-group bounds of slos_postselect (group_of_mode,
+ * ngroups, count_min, count_max, same conventions).  With min_modes = n and the
+ * gate's heralds and groups, the sums over k give the physical performance and
+ * (kept / physical) the gate performance of Fig. slos_output2.  FP64 in a fixed
+ * order; synchronises the stream.
+ */
+int slos_source_postselect(slos_source_t source, const double *probs, const int32_t *group_of_mode, int ngroups,
+                           const int32_t *count_min, const int32_t *count_max, int min_modes, double *result,
+                           void *stream);
+
 /* ---- timing ----------------------------------------------------------------- */
 
 /*

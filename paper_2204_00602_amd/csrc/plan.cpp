@@ -17,7 +17,7 @@
 #include <string>
 #include <vector>
 
-#include "slos_internal.h"
+#include "slos_ext.h"
 
 namespace {
 
@@ -1398,8 +1398,11 @@ struct slos_batch_s {
 
 extern "C" {
 
-int slos_batch_plan(int count, const int32_t *ms, const int32_t *inputs, int flags, const slos_options_t *opts,
-                    slos_batch_t *out)
+} // extern "C"
+
+// Batch builder; with shared_u every instance reads the same m x m U at offset 0.
+static int batch_build(int count, const int32_t *ms, const int32_t *inputs, int flags, const slos_options_t *opts,
+                       bool shared_u, slos_batch_t *out)
 {
     if (!out) return fail(SLOS_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
@@ -1471,7 +1474,7 @@ int slos_batch_plan(int count, const int32_t *ms, const int32_t *inputs, int fla
             I.n = (uint32_t)n;
             P.norm_t = 1.0 / std::sqrt(tf);
             uint64_t M = P.B(m + n - 1, n);
-            b->u_off[i + 1] = b->u_off[i] + (int64_t)m * m;
+            b->u_off[i + 1] = shared_u ? 0 : b->u_off[i] + (int64_t)m * m;
             b->out_off[i + 1] = b->out_off[i] + (int64_t)M;
             I.U_off = (uint64_t)b->u_off[i];
             I.out_off = (uint64_t)b->out_off[i];
@@ -1571,6 +1574,14 @@ int slos_batch_plan(int count, const int32_t *ms, const int32_t *inputs, int fla
     return SLOS_OK;
 }
 
+extern "C" {
+
+int slos_batch_plan(int count, const int32_t *ms, const int32_t *inputs, int flags, const slos_options_t *opts,
+                    slos_batch_t *out)
+{
+    return batch_build(count, ms, inputs, flags, opts, false, out);
+}
+
 void slos_batch_destroy(slos_batch_t b)
 {
     if (!b) return;
@@ -1634,6 +1645,329 @@ int slos_batch_replay(slos_batch_t b, void *stream)
     if (!b->exec) return fail(SLOS_ERR_INVALID_ARG, "no captured graph: call slos_batch_capture first");
     hipError_t e = hipGraphLaunch(b->exec, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "graph launch");
+    return SLOS_OK;
+}
+
+} // extern "C"
+
+// ---- imperfect-source mixtures ------------------------------------------------------
+
+struct slos_source_s {
+    int m = 0, n = 0, nmax = 0;
+    double p0 = 0.0, p1 = 1.0, p2 = 0.0, x = 1.0;
+    std::vector<int> modes;         // input mode of source b (ascending)
+    std::vector<uint64_t> off;      // first state of photon number k, k = 0..nmax+1
+    uint64_t G = 0;
+    uint64_t nleaves = 0;
+    slos_batch_t batch = nullptr;   // common-wavepacket groups, one instance per subset
+    std::vector<int64_t> amp_off;   // per subset: first amplitude in d_amp, or -1
+    int64_t namp = 0;
+    slos_plan_s builder;            // binomials, leaves and inner tables of photon numbers 1..nmax
+    // device
+    LeafDescNarrow *d_desc = nullptr;
+    uint32_t *d_pred = nullptr;
+    uint64_t *d_off = nullptr;
+    int64_t *d_amp_off = nullptr;
+    uint64_t *d_binom = nullptr;
+    void *d_amp = nullptr;
+    double *d_slots = nullptr;      // 2^n graded vectors
+    double *d_temp = nullptr;       // 2^(n-1) graded vectors (at least one)
+    double *d_part = nullptr;
+    double *d_res = nullptr;
+
+    void free_device()
+    {
+        auto f = [](void *q) {
+            if (q) (void)hipFree(q);
+        };
+        f(d_desc);
+        f(d_pred);
+        f(d_off);
+        f(d_amp_off);
+        f(d_binom);
+        f(d_amp);
+        f(d_slots);
+        f(d_temp);
+        f(d_part);
+        f(d_res);
+        d_desc = nullptr;
+        d_pred = nullptr;
+        d_off = nullptr;
+        d_amp_off = nullptr;
+        d_binom = nullptr;
+        d_amp = nullptr;
+        d_slots = d_temp = d_part = d_res = nullptr;
+    }
+};
+
+extern "C" {
+
+int slos_source_plan(int m, const int32_t *input_state, const slos_source_params_t *src, int nmax,
+                     const slos_options_t *opts, slos_source_t *out)
+{
+    if (!out) return fail(SLOS_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (m < 1 || m > SLOS_MAX_MODES) return fail(SLOS_ERR_INVALID_ARG, "m = %d outside [1, %d]", m, SLOS_MAX_MODES);
+    if (!input_state) return fail(SLOS_ERR_INVALID_ARG, "input_state is NULL");
+    long n = 0;
+    for (int j = 0; j < m; ++j) {
+        if (input_state[j] < 0) return fail(SLOS_ERR_INVALID_ARG, "input_state[%d] = %d is negative", j, input_state[j]);
+        n += input_state[j];
+    }
+    if (n > SLOS_SRC_MAX_SOURCES)
+        return fail(SLOS_ERR_INVALID_ARG, "%ld photons: at most %d sources", n, SLOS_SRC_MAX_SOURCES);
+    slos_source_params_t sp{1.0, 0.0, 1.0};
+    if (src) sp = *src;
+    const double beta = sp.emission_probability, g2 = sp.multiphoton_component, V = sp.indistinguishability;
+    if (!(beta > 0.0 && beta <= 1.0)) return fail(SLOS_ERR_INVALID_ARG, "emission_probability %g outside (0, 1]", beta);
+    if (!(g2 >= 0.0 && g2 <= 1.0)) return fail(SLOS_ERR_INVALID_ARG, "multiphoton_component %g outside [0, 1]", g2);
+    if (beta * g2 > 0.5)
+        return fail(SLOS_ERR_INVALID_ARG, "emission_probability x multiphoton_component = %g exceeds 1/2",
+                    beta * g2);
+    if (!(V >= 0.0 && V <= 1.0)) return fail(SLOS_ERR_INVALID_ARG, "indistinguishability %g outside [0, 1]", V);
+    // p1 + p2 = beta, g2 = 2 p2 / (p1 + 2 p2)^2: the root of
+    // g2 p2^2 - (1 - beta g2) p2 + beta^2 g2 / 2 = 0 that vanishes with g2,
+    // written without the cancellation of 1 - beta g2 - sqrt(1 - 2 beta g2)
+    const double disc = std::sqrt(1.0 - 2.0 * beta * g2);
+    const double p2 = g2 > 0.0 ? beta * beta * g2 / ((1.0 - beta * g2) + disc) : 0.0;
+    if (nmax < 0) nmax = (int)(p2 > 0.0 ? 2 * n : n);
+    if (nmax > SLOS_SRC_MAX_NMAX)
+        return fail(SLOS_ERR_INVALID_ARG, "nmax = %d above %d photons", nmax, SLOS_SRC_MAX_NMAX);
+
+    slos_source_s *s = new (std::nothrow) slos_source_s;
+    if (!s) return fail(SLOS_ERR_OOM, "host allocation of the source plan failed");
+    s->m = m;
+    s->n = (int)n;
+    s->nmax = nmax;
+    s->p2 = p2;
+    s->p1 = beta - p2;
+    s->p0 = 1.0 - beta;
+    s->x = std::sqrt(V);
+    std::vector<LeafDescNarrow> desc;
+    std::vector<int32_t> ms, inputs;
+    int rc = SLOS_OK;
+    try {
+        for (int j = 0; j < m; ++j)
+            for (int c = 0; c < input_state[j]; ++c) s->modes.push_back(j);
+        slos_plan_s &P = s->builder;
+        P.m = m;
+        P.norm_t = 1.0;
+        P.B.build(m + nmax, nmax);
+        s->off.assign(nmax + 2, 0);
+        for (int k = 0; k <= nmax; ++k) {
+            const uint64_t Nk = P.B(m + k - 1, k);
+            if (Nk == kSat || s->off[k] + Nk < s->off[k])
+                throw std::pair<int, std::string>(SLOS_ERR_SIZE_OVERFLOW, "state count overflows");
+            s->off[k + 1] = s->off[k] + Nk;
+        }
+        s->G = s->off[nmax + 1];
+        if (s->G >= (uint64_t(1) << 32))
+            throw std::pair<int, std::string>(SLOS_ERR_SIZE_OVERFLOW, "more than 2^32 states up to nmax photons");
+        const uint64_t cap = (opts && opts->leaf_max > 0) ? (uint64_t)opts->leaf_max : 1024u;
+        std::vector<uint64_t> deltas;
+        std::vector<uint8_t> md;
+        for (int k = 1; k <= nmax; ++k) {
+            std::vector<LeafRec> lv;
+            std::vector<uint8_t> hm;
+            P.gen_leaves(k, m - 1, k, cap, hm, lv);
+            for (const LeafRec &L : lv) {
+                LeafDescHead h;
+                P.describe(k, L, h, deltas, md);
+                if (h.nh > SLOS_NARROW_GROUPS)
+                    throw std::pair<int, std::string>(SLOS_ERR_INVALID_ARG, "too many occupied high modes");
+                LeafDescNarrow w{};
+                w.h = h;
+                w.h.out_base += s->off[k];
+                w.h.low_base += s->off[k - 1];
+                for (size_t g = 0; g < deltas.size(); ++g) {
+                    w.delta[g] = (uint32_t)deltas[g];
+                    w.mode[g] = md[g];
+                }
+                desc.push_back(w);
+            }
+        }
+        s->nleaves = desc.size();
+        if (P.pred.size() >= (size_t(1) << 32))
+            throw std::pair<int, std::string>(SLOS_ERR_SIZE_OVERFLOW, "inner tables exceed 2^32 entries");
+        // one batch instance per subset whose common group fits in nmax photons
+        const uint32_t nsub = 1u << n;
+        s->amp_off.assign(nsub, -1);
+        int64_t pos = 0;
+        for (uint32_t a = 0; a < nsub; ++a) {
+            const int k = __builtin_popcount(a);
+            if (k > nmax) continue;
+            s->amp_off[a] = pos;
+            pos += (int64_t)(s->off[k + 1] - s->off[k]);
+            ms.push_back(m);
+            const size_t at = inputs.size();
+            inputs.resize(at + m, 0);
+            for (int b = 0; b < n; ++b)
+                if (a >> b & 1u) inputs[at + s->modes[b]] += 1;
+        }
+        s->namp = pos;
+    } catch (std::bad_alloc &) {
+        delete s;
+        return fail(SLOS_ERR_OOM, "host allocation failed while building the source plan");
+    } catch (std::pair<int, std::string> &e) {
+        delete s;
+        return fail(e.first, "%s", e.second.c_str());
+    }
+    if ((rc = batch_build((int)ms.size(), ms.data(), inputs.data(), SLOS_C128, nullptr, true, &s->batch))) {
+        delete s;
+        return rc;
+    }
+    const size_t G = (size_t)s->G;
+    const size_t nslots = (size_t)1 << s->n, ntemp = std::max<size_t>(1, nslots / 2);
+    if (desc.empty()) desc.resize(1);  // nmax = 0: no leaves, keep the uploads non-empty
+    if (s->builder.pred.empty()) s->builder.pred.resize(1, 0);
+    if ((rc = dev_upload(&s->d_desc, desc.data(), desc.size(), "source leaf descriptors")) ||
+        (rc = dev_upload(&s->d_pred, s->builder.pred.data(), s->builder.pred.size(), "source inner tables")) ||
+        (rc = dev_upload(&s->d_off, s->off.data(), s->off.size(), "source offsets")) ||
+        (rc = dev_upload(&s->d_amp_off, s->amp_off.data(), s->amp_off.size(), "source amplitude offsets")) ||
+        (rc = dev_upload(&s->d_binom, s->builder.B.t.data(), s->builder.B.t.size(), "binomial table")) ||
+        (rc = alloc_dev(&s->d_amp, (size_t)s->namp * 16, "common-group amplitudes")) ||
+        (rc = alloc_dev((void **)&s->d_slots, nslots * G * 8, "source subset vectors")) ||
+        (rc = alloc_dev((void **)&s->d_temp, ntemp * G * 8, "source butterfly scratch")) ||
+        (rc = alloc_dev((void **)&s->d_part, (size_t)(nmax + 1) * SLOS_SRC_STATS_BLOCKS * 3 * 8,
+                        "source statistics partials")) ||
+        (rc = alloc_dev((void **)&s->d_res, (size_t)(nmax + 1) * 3 * 8, "source statistics"))) {
+        slos_batch_destroy(s->batch);
+        s->free_device();
+        delete s;
+        return rc;
+    }
+    *out = s;
+    return SLOS_OK;
+}
+
+void slos_source_destroy(slos_source_t s)
+{
+    if (!s) return;
+    slos_batch_destroy(s->batch);
+    s->free_device();
+    delete s;
+}
+
+int64_t slos_source_num_outputs(slos_source_t s) { return s ? (int64_t)s->G : -1; }
+
+int slos_source_info(slos_source_t s, int64_t *offsets, double *emission)
+{
+    if (!s) return fail(SLOS_ERR_INVALID_ARG, "source plan is NULL");
+    if (offsets)
+        for (int k = 0; k <= s->nmax + 1; ++k) offsets[k] = (int64_t)s->off[k];
+    if (emission) {
+        emission[0] = s->p0;
+        emission[1] = s->p1;
+        emission[2] = s->p2;
+    }
+    return SLOS_OK;
+}
+
+int slos_source_probs(slos_source_t s, const void *U, double *probs, void *stream)
+{
+    if (!s) return fail(SLOS_ERR_INVALID_ARG, "source plan is NULL");
+    if (!U || !probs) return fail(SLOS_ERR_INVALID_ARG, "U and probs must be device pointers");
+    const uint64_t G = s->G;
+    int e = slos_batch_amplitudes(s->batch, U, s->d_amp, nullptr, stream);
+    if (e) return e;
+    SrcFillParams fp{};
+    fp.slots = s->d_slots;
+    fp.G = G;
+    fp.amp = (const double *)s->d_amp;
+    fp.amp_off = s->d_amp_off;
+    fp.off = s->d_off;
+    fp.nmax = s->nmax;
+    if ((e = slos_launch_src_fill(fp, 1 << s->n, stream))) return hip_fail((hipError_t)e, "source fill kernel");
+    SrcPassParams pp{};
+    pp.desc = s->d_desc;
+    pp.nleaves = s->nleaves;
+    pp.pred = s->d_pred;
+    pp.off = s->d_off;
+    pp.U = U;
+    pp.m = s->m;
+    pp.nmax = s->nmax;
+    for (int b = 0; b < s->n; ++b) {
+        // pairs r: P0 = slot (2r) << b (source b not common), P1 = slot (2r+1) << b
+        const int npairs = 1 << (s->n - b - 1);
+        const uint64_t st = (uint64_t(2) << b) * G;
+        double *P0 = s->d_slots, *P1 = s->d_slots + (uint64_t(1) << b) * G, *Z = s->d_temp;
+        pp.col = s->modes[b];
+        // Z = (1-x) p2 L P0 + x p2 P1 + (1-x) p1 P0
+        pp.in = P0;
+        pp.s_in = st;
+        pp.a = P1;
+        pp.s_a = st;
+        pp.b = P0;
+        pp.s_b = st;
+        pp.y = Z;
+        pp.s_y = G;
+        pp.gamma = (1.0 - s->x) * s->p2;
+        pp.alpha = s->x * s->p2;
+        pp.beta = (1.0 - s->x) * s->p1;
+        pp.span = 2 * b + 1;
+        if ((e = slos_launch_src_pass(pp, npairs, stream))) return hip_fail((hipError_t)e, "source pass kernel");
+        // P0 <- L Z + p0 P0 + x p1 P1
+        pp.in = Z;
+        pp.s_in = G;
+        pp.a = P0;
+        pp.s_a = st;
+        pp.b = P1;
+        pp.s_b = st;
+        pp.y = P0;
+        pp.s_y = st;
+        pp.gamma = 1.0;
+        pp.alpha = s->p0;
+        pp.beta = s->x * s->p1;
+        pp.span = 2 * b + 2;
+        if ((e = slos_launch_src_pass(pp, npairs, stream))) return hip_fail((hipError_t)e, "source pass kernel");
+    }
+    hipError_t he = hipMemcpyAsync(probs, s->d_slots, G * 8, hipMemcpyDeviceToDevice, (hipStream_t)stream);
+    if (he != hipSuccess) return hip_fail(he, "source result copy");
+    return SLOS_OK;
+}
+
+int slos_source_postselect(slos_source_t s, const double *probs, const int32_t *group_of_mode, int ngroups,
+                           const int32_t *count_min, const int32_t *count_max, int min_modes, double *result,
+                           void *stream)
+{
+    if (!s) return fail(SLOS_ERR_INVALID_ARG, "source plan is NULL");
+    if (!probs || !result) return fail(SLOS_ERR_INVALID_ARG, "probs (device) and result (host) are required");
+    if (ngroups < 0 || ngroups > SLOS_PS_MAX_GROUPS)
+        return fail(SLOS_ERR_INVALID_ARG, "ngroups = %d outside [0, %d]", ngroups, SLOS_PS_MAX_GROUPS);
+    if (ngroups > 0 && (!count_min || !count_max))
+        return fail(SLOS_ERR_INVALID_ARG, "count_min and count_max are required");
+    if (min_modes < 0) return fail(SLOS_ERR_INVALID_ARG, "min_modes = %d is negative", min_modes);
+    SrcStatsParams sp{};
+    for (int j = 0; j < 256; ++j) sp.group[j] = -1;
+    if (group_of_mode)
+        for (int j = 0; j < s->m; ++j) {
+            const int g = group_of_mode[j];
+            if (g < -1 || g >= ngroups)
+                return fail(SLOS_ERR_INVALID_ARG, "group_of_mode[%d] = %d outside [-1, %d)", j, g, ngroups);
+            sp.group[j] = (int8_t)g;
+        }
+    for (int g = 0; g < ngroups; ++g) {
+        if (count_min[g] < 0 || count_max[g] < count_min[g] || count_max[g] > 255)
+            return fail(SLOS_ERR_INVALID_ARG, "group %d: bounds [%d, %d] invalid", g, count_min[g], count_max[g]);
+        sp.cmin[g] = (uint8_t)count_min[g];
+        sp.cmax[g] = (uint8_t)count_max[g];
+    }
+    sp.P = probs;
+    sp.off = s->d_off;
+    sp.binom = s->d_binom;
+    sp.bstride = s->builder.B.stride;
+    sp.m = s->m;
+    sp.nmax = s->nmax;
+    sp.ngroups = ngroups;
+    sp.min_modes = min_modes;
+    sp.partials = s->d_part;
+    sp.result = s->d_res;
+    int e = slos_launch_src_stats(sp, stream);
+    if (e) return hip_fail((hipError_t)e, "source statistics kernel");
+    hipError_t he = hipMemcpyAsync(result, s->d_res, (size_t)(s->nmax + 1) * 3 * 8, hipMemcpyDeviceToHost,
+                                   (hipStream_t)stream);
+    if (he == hipSuccess) he = hipStreamSynchronize((hipStream_t)stream);
+    if (he != hipSuccess) return hip_fail(he, "source statistics copy");
     return SLOS_OK;
 }
 

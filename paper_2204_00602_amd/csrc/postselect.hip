@@ -18,7 +18,7 @@
 
 #include <algorithm>
 
-#include "slos_internal.h"
+#include "slos_ext.h"
 
 namespace {
 

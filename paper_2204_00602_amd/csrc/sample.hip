@@ -20,7 +20,7 @@
 
 #include <algorithm>
 
-#include "slos_internal.h"
+#include "slos_ext.h"
 
 namespace {
 

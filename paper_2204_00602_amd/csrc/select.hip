@@ -16,7 +16,7 @@
 // summed in a fixed order (digits ascending), so results are reproducible.
 #include <hip/hip_runtime.h>
 
-#include "slos_internal.h"
+#include "slos_ext.h"
 
 namespace {
 

@@ -1,0 +1,123 @@
+// Internal structures of the kernels beside the layer recurrence: weak
+// simulation, post-selection, selected outputs and imperfect-source mixtures
+// (sample.hip, postselect.hip, select.hip, source.hip) and the host code that
+// launches them (plan.cpp).  Not part of the public ABI.
+#pragma once
+
+#include "slos_internal.h"
+
+// states per block of the cumulative-probability table (multiple of 64)
+#define SLOS_CDF_BLOCK 1024
+
+// weak simulation (sample.hip)
+int slos_launch_cdf(const void *P, int c64, int64_t M, double *bp, void *stream);
+int slos_launch_marginals(const void *P, int c64, const double *bp, const int64_t *ends, int m, double *pk,
+                          void *stream);
+int slos_launch_sample(const void *P, int c64, int64_t M, const double *bp, const double *r, int64_t count,
+                       int64_t *ranks, void *stream);
+
+// post-selection (postselect.hip)
+#define SLOS_PS_MAX_GROUPS 16
+#define SLOS_PS_MAX_WAVES 8192  // partial sums per post-selection launch
+// an inner type used by the last layer: its low states occupy table entries
+// [off, off + size)
+struct PsType {
+    uint32_t off;
+    uint32_t size;
+    uint16_t q, K;
+    uint32_t pad;
+};
+struct PostselectParams {
+    const void *P;          // M probabilities (fp32 or fp64), colex order
+    void *masked;           // P masked to the kept outputs, or NULL
+    int64_t M;
+    const uint64_t *binom;  // binom[a * bstride + b] = C(a, b)
+    int bstride;
+    int m, n, ngroups;
+    uint64_t run;           // consecutive ranks per thread
+    double *partials;       // one FP64 partial per wave
+    int8_t group[256];      // group of each mode, -1: unconstrained
+    uint8_t cmin[SLOS_PS_MAX_GROUPS], cmax[SLOS_PS_MAX_GROUPS];
+    // leaf path: the last layer's leaves, and per inner type used by them a
+    // run of the low-state table (SLOS_PS_MAX_GROUPS group counts per state)
+    const LeafRec *leaves;
+    uint64_t nleaves;
+    const uint32_t *type_off;    // per inner-type index: first table entry
+    const PsType *types;         // ntypes entries, ascending off
+    uint32_t ntypes;             // inner types used by the last layer
+    uint32_t entries;            // table entries (low states)
+    uint8_t *low;                // entries x SLOS_PS_MAX_GROUPS group counts
+};
+int slos_launch_postselect(const PostselectParams &p, int c64, void *stream);
+int slos_launch_postselect_table(const PostselectParams &p, int c64, const int64_t *ranks, int64_t nranks,
+                                 const double *sum, double *table, void *stream);
+
+// selected outputs (select.hip)
+#define SLOS_SELECT_MAX_OCC 32
+struct SelectTarget {
+    uint32_t R;                          // prod over occupied modes of (s_j + 1)
+    uint32_t nocc;                       // occupied modes of the target
+    double fac;                          // sqrt(prod s_j!) / sqrt(prod t_i!)
+    uint8_t mode[SLOS_SELECT_MAX_OCC];   // occupied modes, ascending
+    uint8_t mult[SLOS_SELECT_MAX_OCC];   // their occupations
+};
+struct SelectParams {
+    const void *U;                // m x m, plan dtype
+    const SelectTarget *targets;  // device
+    int64_t count;
+    void *out;                    // count amplitudes, plan dtype
+    uint32_t r_max;               // largest R of the call (LDS sizing)
+    int m, n;
+    uint8_t cols[SLOS_MAX_PHOTONS];  // i_k, k = 1..n
+};
+int slos_launch_select(const SelectParams &p, int c64, void *stream);
+
+// imperfect-source mixtures (source.hip)
+#define SLOS_SRC_MAX_SOURCES 12   // 2^12 emission subsets
+#define SLOS_SRC_MAX_NMAX 16      // photon numbers kept: 0..nmax
+#define SLOS_SRC_STATS_BLOCKS 256 // partial sums per photon number
+// Main-group probabilities into the slots: slot s (one per subset of sources,
+// bit b = source b in the common wavepacket) is |a|^2 of its instance on the
+// states with popcount(s) photons and 0 elsewhere.
+struct SrcFillParams {
+    double *slots;          // nslots x G
+    uint64_t G;             // states of photon numbers 0..nmax
+    const double *amp;      // batch output, complex128 amplitudes
+    const int64_t *amp_off; // per slot: first amplitude, or -1 (main group above nmax)
+    const uint64_t *off;    // off[k] = first state of photon number k, k = 0..nmax+1
+    int nmax;
+};
+// y = gamma * L(in) + alpha * a + beta * b on graded vectors, one launch for
+// all pairs r = blockIdx.y of a butterfly step.  (L in)[t] = sum over the
+// occupied modes j of t of |U[j, col]|^2 in[t - e_j]: one distinguishable
+// photon entering mode col.  y may alias a or b (same element only), never in.
+// Outputs of photon number outside [popcount(r), popcount(r) + span] are
+// known to be 0 and are written as 0 without reading.
+struct SrcPassParams {
+    const double *in;
+    const double *a;
+    const double *b;
+    double *y;
+    uint64_t s_in, s_a, s_b, s_y;   // elements between consecutive pairs
+    double gamma, alpha, beta;
+    const LeafDescNarrow *desc;     // leaves of photon numbers 1..nmax, graded ranks
+    uint64_t nleaves;
+    const uint32_t *pred;
+    const uint64_t *off;
+    const void *U;                  // complex128 m x m
+    int m, col, nmax, span;
+};
+struct SrcStatsParams {
+    const double *P;
+    const uint64_t *off;
+    const uint64_t *binom;          // binom[a * bstride + b] = C(a, b)
+    int bstride;
+    int m, nmax, ngroups, min_modes;
+    int8_t group[256];
+    uint8_t cmin[SLOS_PS_MAX_GROUPS], cmax[SLOS_PS_MAX_GROUPS];
+    double *partials;               // [nmax + 1][SLOS_SRC_STATS_BLOCKS][3]
+    double *result;                 // [nmax + 1][3]: mass, physical, kept
+};
+int slos_launch_src_fill(const SrcFillParams &p, int nslots, void *stream);
+int slos_launch_src_pass(const SrcPassParams &p, int npairs, void *stream);
+int slos_launch_src_stats(const SrcStatsParams &p, void *stream);

@@ -67,8 +67,6 @@ static_assert(sizeof(LeafDescWide) == 336, "LeafDescWide must stay 336 bytes");
 // Bytes of readable slack after every layer buffer: the low-block staging
 // copies whole 16-byte chunks in 1 KiB wave-wide steps.
 #define SLOS_BUFFER_SLACK 2048
-// states per block of the cumulative-probability table (multiple of 64)
-#define SLOS_CDF_BLOCK 1024
 // accumulation modes of the c64 layer kernel
 #define SLOS_COMP_NONE 0
 #define SLOS_COMP_BIASED 1
@@ -265,66 +263,3 @@ struct BatchParams {
 
 int slos_launch_batch(const BatchParams &p, int c64, int rr, int threads, int grid, void *stream);
 int slos_prepare_batch_kernels(void);
-
-// weak simulation (sample.hip)
-int slos_launch_cdf(const void *P, int c64, int64_t M, double *bp, void *stream);
-int slos_launch_marginals(const void *P, int c64, const double *bp, const int64_t *ends, int m, double *pk,
-                          void *stream);
-int slos_launch_sample(const void *P, int c64, int64_t M, const double *bp, const double *r, int64_t count,
-                       int64_t *ranks, void *stream);
-
-// post-selection (postselect.hip)
-#define SLOS_PS_MAX_GROUPS 16
-#define SLOS_PS_MAX_WAVES 8192  // partial sums per post-selection launch
-// an inner type used by the last layer: its low states occupy table entries
-// [off, off + size)
-struct PsType {
-    uint32_t off;
-    uint32_t size;
-    uint16_t q, K;
-    uint32_t pad;
-};
-struct PostselectParams {
-    const void *P;          // M probabilities (fp32 or fp64), colex order
-    void *masked;           // P masked to the kept outputs, or NULL
-    int64_t M;
-    const uint64_t *binom;  // binom[a * bstride + b] = C(a, b)
-    int bstride;
-    int m, n, ngroups;
-    uint64_t run;           // consecutive ranks per thread
-    double *partials;       // one FP64 partial per wave
-    int8_t group[256];      // group of each mode, -1: unconstrained
-    uint8_t cmin[SLOS_PS_MAX_GROUPS], cmax[SLOS_PS_MAX_GROUPS];
-    // leaf path: the last layer's leaves, and per inner type used by them a
-    // run of the low-state table (SLOS_PS_MAX_GROUPS group counts per state)
-    const LeafRec *leaves;
-    uint64_t nleaves;
-    const uint32_t *type_off;    // per inner-type index: first table entry
-    const PsType *types;         // ntypes entries, ascending off
-    uint32_t ntypes;             // inner types used by the last layer
-    uint32_t entries;            // table entries (low states)
-    uint8_t *low;                // entries x SLOS_PS_MAX_GROUPS group counts
-};
-int slos_launch_postselect(const PostselectParams &p, int c64, void *stream);
-int slos_launch_postselect_table(const PostselectParams &p, int c64, const int64_t *ranks, int64_t nranks,
-                                 const double *sum, double *table, void *stream);
-
-// selected outputs (select.hip)
-#define SLOS_SELECT_MAX_OCC 32
-struct SelectTarget {
-    uint32_t R;                          // prod over occupied modes of (s_j + 1)
-    uint32_t nocc;                       // occupied modes of the target
-    double fac;                          // sqrt(prod s_j!) / sqrt(prod t_i!)
-    uint8_t mode[SLOS_SELECT_MAX_OCC];   // occupied modes, ascending
-    uint8_t mult[SLOS_SELECT_MAX_OCC];   // their occupations
-};
-struct SelectParams {
-    const void *U;                // m x m, plan dtype
-    const SelectTarget *targets;  // device
-    int64_t count;
-    void *out;                    // count amplitudes, plan dtype
-    uint32_t r_max;               // largest R of the call (LDS sizing)
-    int m, n;
-    uint8_t cols[SLOS_MAX_PHOTONS];  // i_k, k = 1..n
-};
-int slos_launch_select(const SelectParams &p, int c64, void *stream);

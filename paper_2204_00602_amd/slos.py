@@ -48,6 +48,12 @@ class Options(ctypes.Structure):
 _lib = None
 
 
+class SourceParams(ctypes.Structure):
+    _fields_ = [("emission_probability", ctypes.c_double),
+                ("multiphoton_component", ctypes.c_double),
+                ("indistinguishability", ctypes.c_double)]
+
+
 def lib():
     """The loaded libslos.so (raises if it was not built)."""
     global _lib
@@ -93,6 +99,16 @@ def lib():
     L.slos_batch_amplitudes.argtypes = [vp, vp, vp, vp, vp]
     L.slos_batch_capture.argtypes = [vp, vp, vp, vp]
     L.slos_batch_replay.argtypes = [vp, vp]
+    L.slos_source_plan.argtypes = [ctypes.c_int, i32p, ctypes.POINTER(SourceParams), ctypes.c_int,
+                                   ctypes.POINTER(Options), ctypes.POINTER(vp)]
+    L.slos_source_destroy.argtypes = [vp]
+    L.slos_source_destroy.restype = None
+    L.slos_source_num_outputs.argtypes = [vp]
+    L.slos_source_num_outputs.restype = ctypes.c_int64
+    L.slos_source_info.argtypes = [vp, i64p, ctypes.POINTER(ctypes.c_double)]
+    L.slos_source_probs.argtypes = [vp, vp, vp, vp]
+    L.slos_source_postselect.argtypes = [vp, vp, i32p, ctypes.c_int, i32p, i32p, ctypes.c_int,
+                                         ctypes.POINTER(ctypes.c_double), vp]
     L.slos_plan_set_timing.argtypes = [vp, ctypes.c_int]
     L.slos_plan_layer_ms.argtypes = [vp, ctypes.POINTER(ctypes.c_float), ctypes.c_int]
     L.slos_last_error.argtypes = []
@@ -102,7 +118,8 @@ def lib():
                  "slos_probs", "slos_cdf", "slos_marginals", "slos_sample", "slos_postselect", "slos_select", "slos_amplitudes_many",
                  "slos_probs_many", "slos_backward_many", "slos_plan_set_timing", "slos_plan_layer_ms", "slos_backward",
                  "slos_mesh_unitary", "slos_mesh_backward", "slos_batch_plan", "slos_batch_offsets",
-                 "slos_batch_amplitudes", "slos_batch_capture", "slos_batch_replay"):
+                 "slos_batch_amplitudes", "slos_batch_capture", "slos_batch_replay", "slos_source_plan",
+                 "slos_source_info", "slos_source_probs", "slos_source_postselect"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -499,6 +516,90 @@ class Batch:
 
     def output(self, out, i):
         return out[int(self.out_offsets[i]):int(self.out_offsets[i + 1])]
+
+
+class Source:
+    """Output distribution of an imperfect single-photon source behind an input
+    state (slos_source_plan): photon numbers 0..nmax, each in colex order, one
+    after the other (`offsets[k]` .. `offsets[k+1]`), FP64."""
+
+    def __init__(self, input_state: Sequence[int], emission_probability: float = 1.0,
+                 multiphoton_component: float = 0.0, indistinguishability: float = 1.0,
+                 nmax: int = -1, options: Optional[dict] = None):
+        self.input_state = _state_arr(input_state)
+        self.m = int(self.input_state.size)
+        self.n = int(self.input_state.sum())
+        sp = SourceParams(float(emission_probability), float(multiphoton_component), float(indistinguishability))
+        opts = Options()
+        for k, v in (options or {}).items():
+            setattr(opts, k, int(v))
+        self._lib = lib()
+        h = ctypes.c_void_p()
+        _check(self._lib.slos_source_plan(self.m, self.input_state.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                          ctypes.byref(sp), int(nmax), ctypes.byref(opts), ctypes.byref(h)))
+        self._h = h
+        self.num_outputs = int(self._lib.slos_source_num_outputs(h))
+        off = np.zeros(2 * self.n + 18, dtype=np.int64)
+        em = np.zeros(3, dtype=np.float64)
+        _check(self._lib.slos_source_info(h, off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                          em.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        self.nmax = int(np.flatnonzero(off[1:] == self.num_outputs)[0])
+        self.offsets = off[: self.nmax + 2].copy()
+        self.emission = tuple(float(v) for v in em)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.slos_source_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def probs(self, U, out=None, stream=None):
+        """Mixture probabilities for U (complex128 m x m on the device)."""
+        import torch
+        if not (isinstance(U, torch.Tensor) and U.is_cuda and U.dtype == torch.complex128
+                and tuple(U.shape) == (self.m, self.m) and U.is_contiguous()):
+            raise ValueError(f"U must be a contiguous complex128 CUDA tensor of shape ({self.m}, {self.m})")
+        if out is None:
+            out = torch.empty(self.num_outputs, dtype=torch.float64, device=U.device)
+        elif not (out.is_cuda and out.dtype == torch.float64 and out.numel() == self.num_outputs
+                  and out.is_contiguous()):
+            raise ValueError("out must be a contiguous float64 CUDA tensor of num_outputs elements")
+        _check(self._lib.slos_source_probs(self._h, U.data_ptr(), out.data_ptr(), _stream_ptr(stream)))
+        return out
+
+    def split(self, probs):
+        """Views of `probs` per photon number k = 0..nmax."""
+        return [probs[self.offsets[k]:self.offsets[k + 1]] for k in range(self.nmax + 1)]
+
+    def postselect(self, probs, group_of_mode=None, count_min=(), count_max=(), min_modes: int = 0, stream=None):
+        """Per photon number: (total, physical, kept), a (nmax + 1) x 3 array
+        (see slos_source_postselect)."""
+        import torch
+        if not (isinstance(probs, torch.Tensor) and probs.is_cuda and probs.dtype == torch.float64
+                and probs.numel() == self.num_outputs):
+            raise ValueError("probs must be the float64 CUDA output of probs()")
+        i32p = ctypes.POINTER(ctypes.c_int32)
+        lo = np.ascontiguousarray(np.asarray(count_min, dtype=np.int32).reshape(-1))
+        hi = np.ascontiguousarray(np.asarray(count_max, dtype=np.int32).reshape(-1))
+        if lo.size != hi.size:
+            raise ValueError("count_min and count_max need one entry per group")
+        gm = None
+        if group_of_mode is not None:
+            gm = np.ascontiguousarray(np.asarray(group_of_mode, dtype=np.int32).reshape(-1))
+            if gm.size != self.m:
+                raise ValueError("group_of_mode needs m entries")
+        res = np.zeros(3 * (self.nmax + 1), dtype=np.float64)
+        _check(self._lib.slos_source_postselect(self._h, probs.data_ptr(),
+                                                None if gm is None else gm.ctypes.data_as(i32p), int(lo.size),
+                                                lo.ctypes.data_as(i32p), hi.ctypes.data_as(i32p), int(min_modes),
+                                                res.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                                _stream_ptr(stream)))
+        return res.reshape(self.nmax + 1, 3)
 
 
 def mesh_mzi_count(m: int) -> int:

@@ -206,3 +206,37 @@ def test_select_validates_arguments():
     assert L.slos_select(None, None, None, 1, None, None) == -1
     p = slos.Plan([1, 1, 0], "c64", host_only=True)
     assert L.slos_select(p._h, None, None, 1, None, None) == -1
+
+
+@pytest.mark.parametrize("beta,g2,V,nmax,state", [
+    (0.0, 0.0, 1.0, -1, [1, 1, 0]),        # no emission
+    (1.2, 0.0, 1.0, -1, [1, 1, 0]),
+    (1.0, -0.1, 1.0, -1, [1, 1, 0]),
+    (1.0, 0.6, 1.0, -1, [1, 1, 0]),        # beta * g2 above 1/2
+    (1.0, 0.0, 1.5, -1, [1, 1, 0]),
+    (1.0, 0.1, 1.0, 17, [1, 1, 0]),        # nmax above 16
+    (1.0, 0.1, 1.0, -1, [9, 0, 0]),        # 2n = 18 photons by default
+    (1.0, 0.0, 1.0, -1, [13, 0, 0]),       # more than 12 sources
+    (1.0, 0.0, 1.0, -1, [1, -1, 0]),
+])
+def test_source_plan_validates_arguments(beta, g2, V, nmax, state):
+    import ctypes
+    L = slos.lib()
+    st = np.ascontiguousarray(np.asarray(state, np.int32))
+    sp = slos.SourceParams(beta, g2, V)
+    h = ctypes.c_void_p()
+    rc = L.slos_source_plan(len(state), st.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), ctypes.byref(sp),
+                            nmax, None, ctypes.byref(h))
+    assert rc == -1 and not h.value
+    assert b"outside" in L.slos_last_error() or b"exceeds" in L.slos_last_error() or \
+        b"sources" in L.slos_last_error() or b"above" in L.slos_last_error() or b"negative" in L.slos_last_error()
+
+
+def test_source_calls_validate_arguments():
+    L = slos.lib()
+    assert L.slos_source_plan(3, None, None, -1, None, None) == -1
+    assert L.slos_source_probs(None, None, None, None) == -1
+    assert L.slos_source_postselect(None, None, None, 0, None, None, 0, None, None) == -1
+    assert L.slos_source_info(None, None, None) == -1
+    assert L.slos_source_num_outputs(None) == -1
+    L.slos_source_destroy(None)

@@ -1,0 +1,141 @@
+"""GPU parity of the imperfect-source mixture (slos_source_*) against the oracle.
+
+Element by element (graded distribution over photon numbers 0..nmax, matched
+by occupation tuple) at sizes the oracle finishes in seconds, including a
+doubly occupied input mode, truncation below 2n, tiny leaves (many leaves and
+ragged tails) and the vacuum; the Ralph CNOT figures printed in Appendix A.4;
+and, at m = 12 with 6 sources, properties that hold at any size: the
+photon-number law is the product of the sources' laws and the mean occupation
+of output mode j is sum_s (p1 + 2 p2) |U[j, i_s]|^2, whatever U and V.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2204_00602_amd import inputs, slos
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.fixture(scope="module", autouse=True)
+def need_gpu():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    slos.lib()
+
+
+def _cnot():
+    g = json.load(open(os.path.join(HERE, "golden", "ralph_cnot.json")))
+    U = np.zeros((6, 6), np.complex128)
+    for j, row in enumerate(g["unitary"]):
+        for i, ((a, r), (b, s)) in enumerate(row):
+            U[j, i] = (a * math.sqrt(r) + 1j * b * math.sqrt(s)) / 3.0
+    return U
+
+
+def _gpu(T, U, beta, g2, V, nmax=-1, options=None):
+    src = slos.Source(T, beta, g2, V, nmax=nmax, options=options)
+    Ud = torch.from_numpy(np.asarray(U, np.complex128)).cuda().contiguous()
+    P = src.probs(Ud)
+    torch.cuda.synchronize()
+    return src, P
+
+
+def _compare(src, P, ref, atol=1e-14, rtol=1e-11):
+    parts = src.split(P)
+    assert len(parts) == len(ref)
+    for k, (states, probs) in enumerate(ref):
+        got = parts[k].cpu().numpy()
+        assert got.size == len(states)
+        idx = np.array([slos.fock_rank(s) for s in states], dtype=np.int64) if len(states) else np.zeros(0, int)
+        err = np.abs(got[idx] - probs)
+        assert np.all(err <= atol + rtol * np.abs(probs)), (k, float(err.max()))
+        assert np.unique(idx).size == idx.size
+
+
+@pytest.mark.parametrize("case", [0, 1, 2])
+def test_source_cnot_printed_figures(case):
+    g = json.load(open(os.path.join(HERE, "golden", "cnot_source.json")))
+    c = g["cases"][case]
+    U = _cnot()
+    T = g["input"]
+    prm = (c["emission_probability"], c["multiphoton_component"], c["indistinguishability"])
+    print(f"[source] CNOT case {case} {prm}", flush=True)
+    src, P = _gpu(T, U, *prm, nmax=4)
+    _compare(src, P, oracle.source_distribution(U, T, *prm, 4))
+    res = src.postselect(P, [2, 0, 0, 1, 1, 3], [1, 1, 0, 0], [1, 1, 0, 0], min_modes=2)
+    phys, kept = res[:, 1].sum(), res[:, 2].sum()
+    assert res[:, 0].sum() == pytest.approx(1.0, abs=1e-13)
+    if "physical" in c:
+        assert phys == pytest.approx(c["physical"][0] / c["physical"][1], abs=1e-13)
+        assert kept / phys == pytest.approx(c["logical"][0] / c["logical"][1], abs=1e-13)
+    else:
+        assert abs(phys - c["physical_printed"]) < 5e-7
+        assert abs(kept / phys - c["logical_printed"]) < 5e-7
+
+
+@pytest.mark.parametrize("m,T,prm,nmax,opts", [
+    (6, [1, 1, 1, 0, 0, 0], (0.9, 0.05, 0.9), 6, None),
+    (6, [1, 1, 1, 0, 0, 0], (0.7, 0.3, 0.4), 6, {"leaf_max": 4}),     # many leaves, ragged tails
+    (6, [2, 1, 0, 1, 0, 0], (0.8, 0.2, 0.6), 8, {"leaf_max": 16}),    # two sources in one mode
+    (8, [1, 0, 1, 0, 1, 0, 1, 0], (0.9, 0.05, 0.9), 8, None),
+    (6, [1, 1, 1, 0, 0, 0], (0.8, 0.2, 0.6), 4, None),                # truncated below 2n
+    (5, [1, 1, 0, 1, 0], (1.0, 0.0, 0.0), -1, None),                  # fully distinguishable
+    (4, [0, 0, 0, 0], (0.5, 0.1, 0.5), -1, None),                     # vacuum input
+])
+def test_source_matches_oracle(m, T, prm, nmax, opts):
+    print(f"[source] m={m} T={T} {prm} nmax={nmax} opts={opts}", flush=True)
+    U = inputs.haar_unitary(m, 40 + m)
+    src, P = _gpu(T, U, *prm, nmax=nmax, options=opts)
+    ref = oracle.source_distribution(U, T, *prm, src.nmax)
+    _compare(src, P, ref)
+
+
+def test_source_perfect_equals_plain_distribution():
+    m, T = 8, [1, 1, 0, 0, 1, 1, 0, 0]
+    U = inputs.haar_unitary(m, 50)
+    src, P = _gpu(T, U, 1.0, 0.0, 1.0)
+    assert src.nmax == 4
+    parts = src.split(P)
+    for k in range(4):
+        assert float(parts[k].abs().max()) == 0.0
+    states = oracle.fock_states(m, 4)
+    idx = np.array([slos.fock_rank(s) for s in states])
+    ref = oracle.probabilities(U, T, states)
+    got = parts[4].cpu().numpy()[idx]
+    assert np.allclose(got, ref, atol=1e-15, rtol=1e-12)
+
+
+def test_source_properties_m12_six_sources():
+    """The benchmark workload: m = 12, 6 sources, photon numbers 0..12 (2.7M states)."""
+    m, T = 12, [1] * 6 + [0] * 6
+    beta, g2, V = 0.9, 0.05, 0.92
+    U = inputs.haar_unitary(m, 2)
+    print("[source] m=12 six sources", flush=True)
+    src, P = _gpu(T, U, beta, g2, V)
+    assert src.nmax == 12 and src.num_outputs == math.comb(24, 12)
+    p0, p1, p2 = oracle.source_emission(beta, g2)
+    law = np.array([1.0])
+    for _ in range(6):
+        law = np.convolve(law, [p0, p1, p2])
+    res = src.postselect(P)
+    assert np.allclose(res[:, 0], law, atol=1e-13, rtol=0)
+    assert float(P.min()) >= -1e-18
+    # mean occupation of each output mode from its photon-number law (groups = {j})
+    Q = np.abs(U) ** 2
+    want = (p1 + 2 * p2) * (Q @ np.array(T, float))
+    for j in range(m):
+        gm = [-1] * m
+        gm[j] = 0
+        mean = 0.0
+        for c in range(1, 13):
+            mean += c * src.postselect(P, gm, [c], [c])[:, 2].sum()
+        assert mean == pytest.approx(want[j], abs=1e-12), j
+    # the emission probabilities the library derived from (beta, g2)
+    assert np.allclose(src.emission, (p0, p1, p2), atol=1e-15, rtol=1e-12)
