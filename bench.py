@@ -256,6 +256,79 @@ def time_select(torch, slos, T, U_np, steps, warmup, count=10_000):
     return res
 
 
+def source_algorithmic_bytes(m, n, nmax):
+    """Bytes the mixture must move at least, per evaluation: the common-group
+    ladder (read the parent vector, write the child, complex128), the fill
+    (read each group, write its probabilities), every butterfly pass (write the
+    output's support, read a and b where they meet it, read the input where it
+    feeds an output) and the final copy of the result (FP64)."""
+    N = [math.comb(m + k - 1, k) for k in range(nmax + 1)]
+
+    def span(lo, hi):
+        return sum(N[k] for k in range(max(lo, 0), min(hi, nmax) + 1))
+
+    total = 0
+    for a in range(1, min(n, nmax) + 1):
+        total += math.comb(n, a) * 16 * (N[a - 1] + N[a])
+    for a in range(0, min(n, nmax) + 1):
+        total += math.comb(n, a) * (16 + 8) * N[a]
+    for b in range(n):
+        for r in range(1 << (n - b - 1)):
+            c = bin(r).count("1")
+            # (in_lo, in_len), (a_lo, a_len), (b_lo, b_len), y_len of the two passes
+            for (il, iln), (al, aln), (bl, bln), yl in (((0, 2 * b), (1, 2 * b), (0, 2 * b), 2 * b + 1),
+                                                        ((0, 2 * b + 1), (0, 2 * b), (1, 2 * b), 2 * b + 2)):
+                ylo, yhi = c, min(nmax, c + yl)
+                total += 8 * span(ylo, yhi)
+                total += 8 * span(max(ylo, c + al), min(yhi, c + al + aln))
+                total += 8 * span(max(ylo, c + bl), min(yhi, c + bl + bln))
+                total += 8 * span(max(ylo - 1, c + il), min(yhi - 1, c + il + iln))
+    G = sum(N)
+    return total + 16 * G
+
+
+def time_source(torch, slos, steps, warmup, m=12, nsrc=6, beta=0.9, g2=0.05, V=0.92):
+    """Imperfect-source mixture (FP64): m=12, one source per photon of
+    |1^6 0^6>, every photon number 0..12 (2,704,156 states), Haar U seed 2.
+    Timed with HIP events around the whole call on its stream; the processor
+    figures (per-number mass, physical, kept) timed separately."""
+    from paper_2204_00602_amd import inputs
+    T = [1] * nsrc + [0] * (m - nsrc)
+    src = slos.Source(T, beta, g2, V)
+    Ud = torch.from_numpy(inputs.haar_unitary(m, 2)).cuda()
+    P = torch.empty(src.num_outputs, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    t_mix = t_stats = 0.0
+    gm = [0, 0, 1, 1] + [-1] * (m - 4)
+    for it in range(warmup + steps):
+        ev[0].record(stream)
+        src.probs(Ud, out=P, stream=stream)
+        ev[1].record(stream)
+        res = src.postselect(P, gm, [1, 1], [1, 1], min_modes=nsrc, stream=stream)
+        ev[2].record(stream)
+        torch.cuda.synchronize()
+        if it >= warmup:
+            t_mix += ev[0].elapsed_time(ev[1])
+            t_stats += ev[1].elapsed_time(ev[2])
+    t_mix, t_stats = t_mix / steps, t_stats / steps
+    out = {
+        "workload": f"m={m}, {nsrc} sources (emission {beta}, g2 {g2}, indistinguishability {V}), "
+                    f"photon numbers 0..{src.nmax} ({src.num_outputs} states), complex128 common groups, FP64 mixture",
+        "ms": t_mix, "states_per_s": src.num_outputs / (t_mix * 1e-3),
+        "algorithmic_bytes": source_algorithmic_bytes(m, nsrc, src.nmax),
+        "algorithmic_GBps": source_algorithmic_bytes(m, nsrc, src.nmax) / (t_mix * 1e-3) / 1e9,
+        "roofline_frac": source_algorithmic_bytes(m, nsrc, src.nmax) / (t_mix * 1e-3) / 1e9 / HBM_PEAK_GBPS,
+        "subsets": 1 << nsrc, "layer_passes": 2 * ((1 << nsrc) - 1),
+        "stats_ms": t_stats, "total_mass": float(res[:, 0].sum()),
+        "physical": float(res[:, 1].sum()), "kept": float(res[:, 2].sum()),
+    }
+    src.close()
+    del P
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(U_np, T, target_s=20.0):
     """The oracle, untuned, on a bounded sample of the workload's outputs."""
     import oracle
@@ -406,6 +479,11 @@ def main():
         line["selected"] = time_select(torch, slos, T, U, max(3, args.steps // 4), 1)
         print(f"[bench] selected: c64 {line['selected']['c64']['ms']:.3f} ms, "
               f"c128 {line['selected']['c128']['ms']:.3f} ms", file=sys.stderr, flush=True)
+    if not args.no_extras and not args.only:
+        print("[bench] imperfect source: m=12, 6 sources, photon numbers 0..12", file=sys.stderr, flush=True)
+        line["source"] = time_source(torch, slos, args.steps, args.warmup)
+        print(f"[bench] source: {line['source']['ms']:.3f} ms per mixture, "
+              f"figures {line['source']['stats_ms']:.3f} ms", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(U, T)

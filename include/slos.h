@@ -331,11 +331,11 @@ typedef struct slos_source_s *slos_source_t;
 /*
  * Plan the output distribution of the source mixture behind input_state (host,
  * m int32, n = sum <= 12 photons, i.e. sources) over the photon numbers
- * 0..nmax (nmax < 0: 2n when pairs are possible, else n; nmax <= 16; the
+ * 0..nmax (nmax < 0: 2n when pairs are possible, else n; nmax <= min(2n, 16); the
  * states of photon numbers above nmax are dropped, those below are exact).
  * Output layout ("graded"): photon number k occupies elements
  * [offsets[k], offsets[k+1]) in colex order, offsets from slos_source_info;
- * fewer than 2^32 states in all.  opts: leaf_max (default 1024) only.  The
+ * fewer than 2^32 states in all.  opts: leaf_max (default 256) only.  The
  * plan allocates 1.5 x 2^n graded FP64 vectors of device scratch, the leaf
  * tables of photon numbers 1..nmax and a batch of the 2^n common-wavepacket
  * groups; it owns them until slos_source_destroy.

@@ -1398,11 +1398,8 @@ struct slos_batch_s {
 
 extern "C" {
 
-} // extern "C"
-
-// Batch builder; with shared_u every instance reads the same m x m U at offset 0.
-static int batch_build(int count, const int32_t *ms, const int32_t *inputs, int flags, const slos_options_t *opts,
-                       bool shared_u, slos_batch_t *out)
+int slos_batch_plan(int count, const int32_t *ms, const int32_t *inputs, int flags, const slos_options_t *opts,
+                    slos_batch_t *out)
 {
     if (!out) return fail(SLOS_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
@@ -1474,7 +1471,7 @@ static int batch_build(int count, const int32_t *ms, const int32_t *inputs, int 
             I.n = (uint32_t)n;
             P.norm_t = 1.0 / std::sqrt(tf);
             uint64_t M = P.B(m + n - 1, n);
-            b->u_off[i + 1] = shared_u ? 0 : b->u_off[i] + (int64_t)m * m;
+            b->u_off[i + 1] = b->u_off[i] + (int64_t)m * m;
             b->out_off[i + 1] = b->out_off[i] + (int64_t)M;
             I.U_off = (uint64_t)b->u_off[i];
             I.out_off = (uint64_t)b->out_off[i];
@@ -1574,14 +1571,6 @@ static int batch_build(int count, const int32_t *ms, const int32_t *inputs, int 
     return SLOS_OK;
 }
 
-extern "C" {
-
-int slos_batch_plan(int count, const int32_t *ms, const int32_t *inputs, int flags, const slos_options_t *opts,
-                    slos_batch_t *out)
-{
-    return batch_build(count, ms, inputs, flags, opts, false, out);
-}
-
 void slos_batch_destroy(slos_batch_t b)
 {
     if (!b) return;
@@ -1659,8 +1648,11 @@ struct slos_source_s {
     std::vector<uint64_t> off;      // first state of photon number k, k = 0..nmax+1
     uint64_t G = 0;
     uint64_t nleaves = 0;
-    slos_batch_t batch = nullptr;   // common-wavepacket groups, one instance per subset
-    std::vector<int64_t> amp_off;   // per subset: first amplitude in d_amp, or -1
+    std::vector<uint64_t> leaves_upto;  // leaves of photon numbers 1..k, k = 0..nmax
+    std::vector<int64_t> amp_off;   // per subset: its common group's vector in d_amp, or -1
+    std::vector<uint32_t> sub_off;  // subsets of size a: sub_masks[sub_off[a] .. sub_off[a+1])
+    std::vector<uint32_t> sub_masks;
+    std::vector<double> inv_tfac;   // per subset: 1 / prod_i t_i! of its common group
     int64_t namp = 0;
     slos_plan_s builder;            // binomials, leaves and inner tables of photon numbers 1..nmax
     // device
@@ -1668,6 +1660,9 @@ struct slos_source_s {
     uint32_t *d_pred = nullptr;
     uint64_t *d_off = nullptr;
     int64_t *d_amp_off = nullptr;
+    uint32_t *d_sub = nullptr;
+    double *d_inv_tfac = nullptr;
+    double *d_lowfac = nullptr;
     uint64_t *d_binom = nullptr;
     void *d_amp = nullptr;
     double *d_slots = nullptr;      // 2^n graded vectors
@@ -1684,6 +1679,9 @@ struct slos_source_s {
         f(d_pred);
         f(d_off);
         f(d_amp_off);
+        f(d_sub);
+        f(d_inv_tfac);
+        f(d_lowfac);
         f(d_binom);
         f(d_amp);
         f(d_slots);
@@ -1694,6 +1692,9 @@ struct slos_source_s {
         d_pred = nullptr;
         d_off = nullptr;
         d_amp_off = nullptr;
+        d_sub = nullptr;
+        d_inv_tfac = nullptr;
+        d_lowfac = nullptr;
         d_binom = nullptr;
         d_amp = nullptr;
         d_slots = d_temp = d_part = d_res = nullptr;
@@ -1733,6 +1734,7 @@ int slos_source_plan(int m, const int32_t *input_state, const slos_source_params
     if (nmax < 0) nmax = (int)(p2 > 0.0 ? 2 * n : n);
     if (nmax > SLOS_SRC_MAX_NMAX)
         return fail(SLOS_ERR_INVALID_ARG, "nmax = %d above %d photons", nmax, SLOS_SRC_MAX_NMAX);
+    if (nmax > 2 * n) return fail(SLOS_ERR_INVALID_ARG, "nmax = %d above 2n = %ld photons", nmax, 2 * n);
 
     slos_source_s *s = new (std::nothrow) slos_source_s;
     if (!s) return fail(SLOS_ERR_OOM, "host allocation of the source plan failed");
@@ -1763,9 +1765,10 @@ int slos_source_plan(int m, const int32_t *input_state, const slos_source_params
         s->G = s->off[nmax + 1];
         if (s->G >= (uint64_t(1) << 32))
             throw std::pair<int, std::string>(SLOS_ERR_SIZE_OVERFLOW, "more than 2^32 states up to nmax photons");
-        const uint64_t cap = (opts && opts->leaf_max > 0) ? (uint64_t)opts->leaf_max : 1024u;
+        const uint64_t cap = (opts && opts->leaf_max > 0) ? (uint64_t)opts->leaf_max : 256u;
         std::vector<uint64_t> deltas;
         std::vector<uint8_t> md;
+        s->leaves_upto.assign(nmax + 1, 0);
         for (int k = 1; k <= nmax; ++k) {
             std::vector<LeafRec> lv;
             std::vector<uint8_t> hm;
@@ -1779,31 +1782,40 @@ int slos_source_plan(int m, const int32_t *input_state, const slos_source_params
                 w.h = h;
                 w.h.out_base += s->off[k];
                 w.h.low_base += s->off[k - 1];
+                w.h.pad = (uint32_t)k;
                 for (size_t g = 0; g < deltas.size(); ++g) {
                     w.delta[g] = (uint32_t)deltas[g];
                     w.mode[g] = md[g];
                 }
                 desc.push_back(w);
             }
+            s->leaves_upto[k] = desc.size();
         }
         s->nleaves = desc.size();
         if (P.pred.size() >= (size_t(1) << 32))
             throw std::pair<int, std::string>(SLOS_ERR_SIZE_OVERFLOW, "inner tables exceed 2^32 entries");
-        // one batch instance per subset whose common group fits in nmax photons
+        // common groups: a compact vector per subset whose group fits in nmax photons
         const uint32_t nsub = 1u << n;
         s->amp_off.assign(nsub, -1);
+        s->inv_tfac.assign(nsub, 1.0);
+        s->sub_off.assign(n + 2, 0);
         int64_t pos = 0;
-        for (uint32_t a = 0; a < nsub; ++a) {
-            const int k = __builtin_popcount(a);
-            if (k > nmax) continue;
-            s->amp_off[a] = pos;
-            pos += (int64_t)(s->off[k + 1] - s->off[k]);
-            ms.push_back(m);
-            const size_t at = inputs.size();
-            inputs.resize(at + m, 0);
-            for (int b = 0; b < n; ++b)
-                if (a >> b & 1u) inputs[at + s->modes[b]] += 1;
+        for (int a = 0; a <= n; ++a) {
+            s->sub_off[a] = (uint32_t)s->sub_masks.size();
+            for (uint32_t A = 0; A < nsub; ++A) {
+                if (__builtin_popcount(A) != a) continue;
+                s->sub_masks.push_back(A);
+                if (a > nmax) continue;
+                s->amp_off[A] = pos;
+                pos += (int64_t)(s->off[a + 1] - s->off[a]);
+                std::vector<int> occ(m, 0);
+                double tf = 1.0;
+                for (int b = 0; b < n; ++b)
+                    if (A >> b & 1u) tf *= (double)(++occ[s->modes[b]]);
+                s->inv_tfac[A] = 1.0 / tf;
+            }
         }
+        s->sub_off[n + 1] = (uint32_t)s->sub_masks.size();
         s->namp = pos;
     } catch (std::bad_alloc &) {
         delete s;
@@ -1812,15 +1824,17 @@ int slos_source_plan(int m, const int32_t *input_state, const slos_source_params
         delete s;
         return fail(e.first, "%s", e.second.c_str());
     }
-    if ((rc = batch_build((int)ms.size(), ms.data(), inputs.data(), SLOS_C128, nullptr, true, &s->batch))) {
-        delete s;
-        return rc;
-    }
     const size_t G = (size_t)s->G;
     const size_t nslots = (size_t)1 << s->n, ntemp = std::max<size_t>(1, nslots / 2);
-    if (desc.empty()) desc.resize(1);  // nmax = 0: no leaves, keep the uploads non-empty
-    if (s->builder.pred.empty()) s->builder.pred.resize(1, 0);
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+        delete s;
+        return fail(SLOS_ERR_NO_DEVICE, "no HIP device");
+    }
     if ((rc = dev_upload(&s->d_desc, desc.data(), desc.size(), "source leaf descriptors")) ||
+        (rc = dev_upload(&s->d_lowfac, s->builder.lowfac.data(), s->builder.lowfac.size(), "source factorials")) ||
+        (rc = dev_upload(&s->d_sub, s->sub_masks.data(), s->sub_masks.size(), "source subsets")) ||
+        (rc = dev_upload(&s->d_inv_tfac, s->inv_tfac.data(), s->inv_tfac.size(), "source group factors")) ||
         (rc = dev_upload(&s->d_pred, s->builder.pred.data(), s->builder.pred.size(), "source inner tables")) ||
         (rc = dev_upload(&s->d_off, s->off.data(), s->off.size(), "source offsets")) ||
         (rc = dev_upload(&s->d_amp_off, s->amp_off.data(), s->amp_off.size(), "source amplitude offsets")) ||
@@ -1828,10 +1842,17 @@ int slos_source_plan(int m, const int32_t *input_state, const slos_source_params
         (rc = alloc_dev(&s->d_amp, (size_t)s->namp * 16, "common-group amplitudes")) ||
         (rc = alloc_dev((void **)&s->d_slots, nslots * G * 8, "source subset vectors")) ||
         (rc = alloc_dev((void **)&s->d_temp, ntemp * G * 8, "source butterfly scratch")) ||
-        (rc = alloc_dev((void **)&s->d_part, (size_t)(nmax + 1) * SLOS_SRC_STATS_BLOCKS * 3 * 8,
+        (rc = alloc_dev((void **)&s->d_part, (size_t)(SLOS_SRC_STATS_MAX_BLOCKS + nmax + 1) * 3 * 8,
                         "source statistics partials")) ||
         (rc = alloc_dev((void **)&s->d_res, (size_t)(nmax + 1) * 3 * 8, "source statistics"))) {
-        slos_batch_destroy(s->batch);
+        s->free_device();
+        delete s;
+        return rc;
+    }
+    const double one[2] = {1.0, 0.0};  // the empty group: the vacuum's coefficient
+    hipError_t he = hipMemcpy(s->d_amp, one, sizeof one, hipMemcpyHostToDevice);
+    if (he != hipSuccess) {
+        rc = hip_fail(he, "source set-up");
         s->free_device();
         delete s;
         return rc;
@@ -1843,7 +1864,6 @@ int slos_source_plan(int m, const int32_t *input_state, const slos_source_params
 void slos_source_destroy(slos_source_t s)
 {
     if (!s) return;
-    slos_batch_destroy(s->batch);
     s->free_device();
     delete s;
 }
@@ -1868,57 +1888,92 @@ int slos_source_probs(slos_source_t s, const void *U, double *probs, void *strea
     if (!s) return fail(SLOS_ERR_INVALID_ARG, "source plan is NULL");
     if (!U || !probs) return fail(SLOS_ERR_INVALID_ARG, "U and probs must be device pointers");
     const uint64_t G = s->G;
-    int e = slos_batch_amplitudes(s->batch, U, s->d_amp, nullptr, stream);
-    if (e) return e;
+    int e;
+    SrcGroupParams gp{};
+    gp.amp = (double2 *)s->d_amp;
+    gp.amp_off = s->d_amp_off;
+    gp.desc = s->d_desc;
+    gp.pred = s->d_pred;
+    gp.U = U;
+    gp.m = s->m;
+    for (int b = 0; b < s->n; ++b) gp.modes[b] = (uint8_t)s->modes[b];
+    for (int a = 1; a <= std::min(s->n, s->nmax); ++a) {
+        gp.subsets = s->d_sub + s->sub_off[a];
+        gp.leaf_lo = s->leaves_upto[a - 1];
+        gp.leaf_hi = s->leaves_upto[a];
+        gp.off_out = s->off[a];
+        gp.off_in = s->off[a - 1];
+        if ((e = slos_launch_src_group(gp, (int)(s->sub_off[a + 1] - s->sub_off[a]), stream)))
+            return hip_fail((hipError_t)e, "source group kernel");
+    }
     SrcFillParams fp{};
     fp.slots = s->d_slots;
     fp.G = G;
-    fp.amp = (const double *)s->d_amp;
+    fp.amp = (const double2 *)s->d_amp;
     fp.amp_off = s->d_amp_off;
-    fp.off = s->d_off;
+    fp.inv_tfac = s->d_inv_tfac;
+    fp.desc = s->d_desc;
+    fp.lowfac = s->d_lowfac;
+    for (int k = 0; k <= s->nmax; ++k) fp.leaves_upto[k] = s->leaves_upto[k];
+    for (int k = 0; k <= s->nmax + 1; ++k) fp.off[k] = s->off[k];
     fp.nmax = s->nmax;
     if ((e = slos_launch_src_fill(fp, 1 << s->n, stream))) return hip_fail((hipError_t)e, "source fill kernel");
     SrcPassParams pp{};
     pp.desc = s->d_desc;
     pp.nleaves = s->nleaves;
     pp.pred = s->d_pred;
-    pp.off = s->d_off;
     pp.U = U;
     pp.m = s->m;
     pp.nmax = s->nmax;
     for (int b = 0; b < s->n; ++b) {
-        // pairs r: P0 = slot (2r) << b (source b not common), P1 = slot (2r+1) << b
+        // pairs r: P0 = slot (2r) << b (source b not common), P1 = slot (2r+1) << b.
+        // With c = popcount(r): P0 holds photon numbers [c, c + 2b], P1 [c + 1, c + 1 + 2b].
         const int npairs = 1 << (s->n - b - 1);
         const uint64_t st = (uint64_t(2) << b) * G;
         double *P0 = s->d_slots, *P1 = s->d_slots + (uint64_t(1) << b) * G, *Z = s->d_temp;
+        const int cmax = s->n - b - 1;  // largest c of the step
         pp.col = s->modes[b];
-        // Z = (1-x) p2 L P0 + x p2 P1 + (1-x) p1 P0
+        // Z = (1-x) p2 L P0 + x p2 P1 + (1-x) p1 P0, photon numbers [c, c + 2b + 1]
         pp.in = P0;
         pp.s_in = st;
+        pp.in_lo = 0;
+        pp.in_len = 2 * b;
         pp.a = P1;
         pp.s_a = st;
+        pp.a_lo = 1;
+        pp.a_len = 2 * b;
         pp.b = P0;
         pp.s_b = st;
+        pp.b_lo = 0;
+        pp.b_len = 2 * b;
         pp.y = Z;
         pp.s_y = G;
+        pp.y_len = 2 * b + 1;
         pp.gamma = (1.0 - s->x) * s->p2;
         pp.alpha = s->x * s->p2;
         pp.beta = (1.0 - s->x) * s->p1;
-        pp.span = 2 * b + 1;
+        pp.nleaves = s->leaves_upto[std::min(s->nmax, cmax + pp.y_len)];
         if ((e = slos_launch_src_pass(pp, npairs, stream))) return hip_fail((hipError_t)e, "source pass kernel");
-        // P0 <- L Z + p0 P0 + x p1 P1
+        // P0 <- L Z + p0 P0 + x p1 P1, photon numbers [c, c + 2b + 2]
         pp.in = Z;
         pp.s_in = G;
+        pp.in_lo = 0;
+        pp.in_len = 2 * b + 1;
         pp.a = P0;
         pp.s_a = st;
+        pp.a_lo = 0;
+        pp.a_len = 2 * b;
         pp.b = P1;
         pp.s_b = st;
+        pp.b_lo = 1;
+        pp.b_len = 2 * b;
         pp.y = P0;
         pp.s_y = st;
+        pp.y_len = 2 * b + 2;
         pp.gamma = 1.0;
         pp.alpha = s->p0;
         pp.beta = s->x * s->p1;
-        pp.span = 2 * b + 2;
+        pp.nleaves = s->leaves_upto[std::min(s->nmax, cmax + pp.y_len)];
         if ((e = slos_launch_src_pass(pp, npairs, stream))) return hip_fail((hipError_t)e, "source pass kernel");
     }
     hipError_t he = hipMemcpyAsync(probs, s->d_slots, G * 8, hipMemcpyDeviceToDevice, (hipStream_t)stream);
@@ -1962,6 +2017,13 @@ int slos_source_postselect(slos_source_t s, const double *probs, const int32_t *
     sp.min_modes = min_modes;
     sp.partials = s->d_part;
     sp.result = s->d_res;
+    // fixed chunks of >= 1024 states (a multiple of 256), whole chunks per photon number
+    uint64_t chunk = std::max<uint64_t>(1024, (s->G + SLOS_SRC_STATS_MAX_BLOCKS - 1) / SLOS_SRC_STATS_MAX_BLOCKS);
+    chunk = (chunk + 255) / 256 * 256;
+    sp.chunk = chunk;
+    sp.blk_off[0] = 0;
+    for (int k = 0; k <= s->nmax; ++k)
+        sp.blk_off[k + 1] = sp.blk_off[k] + (uint32_t)((s->off[k + 1] - s->off[k] + chunk - 1) / chunk);
     int e = slos_launch_src_stats(sp, stream);
     if (e) return hip_fail((hipError_t)e, "source statistics kernel");
     hipError_t he = hipMemcpyAsync(result, s->d_res, (size_t)(s->nmax + 1) * 3 * 8, hipMemcpyDeviceToHost,

@@ -75,24 +75,50 @@ int slos_launch_select(const SelectParams &p, int c64, void *stream);
 // imperfect-source mixtures (source.hip)
 #define SLOS_SRC_MAX_SOURCES 12   // 2^12 emission subsets
 #define SLOS_SRC_MAX_NMAX 16      // photon numbers kept: 0..nmax
-#define SLOS_SRC_STATS_BLOCKS 256 // partial sums per photon number
-// Main-group probabilities into the slots: slot s (one per subset of sources,
-// bit b = source b in the common wavepacket) is |a|^2 of its instance on the
-// states with popcount(s) photons and 0 elsewhere.
+#define SLOS_SRC_STATS_MAX_BLOCKS 16384  // statistics blocks: chunks of at least 1024 states
+// Common-wavepacket groups, all subsets of the sources: the amplitude vector
+// (monomial coefficients of the recurrence, no normalisation) of subset A is
+// that of A minus its highest source advanced by one layer of the recurrence
+// with that source's input mode: one launch per subset size a, blockIdx.y over
+// the subsets of size a.  Vectors are compact (C(m+a-1, a) complex128 each, at
+// amp_off[A]); the empty subset holds [1], written once at plan time.
+struct SrcGroupParams {
+    double2 *amp;
+    const int64_t *amp_off;         // per subset mask
+    const uint32_t *subsets;        // masks of this launch's size
+    const LeafDescNarrow *desc;     // leaves of photon number a: [leaf_lo, leaf_hi)
+    uint64_t leaf_lo, leaf_hi;
+    uint64_t off_out, off_in;       // graded offsets of photon numbers a and a - 1
+    const uint32_t *pred;
+    const void *U;                  // complex128 m x m
+    int m;
+    uint8_t modes[SLOS_SRC_MAX_SOURCES];  // input mode of each source
+};
+// Common-group probabilities into the slots: slot s (bit b = source b in the
+// common wavepacket) receives P = |A_s|^2 prod_j s_j! / prod_i t_i! on the
+// states of popcount(s) photons, its whole support (prod s_j! from the leaf's
+// high-mode factor and the inner table's low factors); the rest of the slot is
+// never read.
 struct SrcFillParams {
     double *slots;          // nslots x G
-    uint64_t G;             // states of photon numbers 0..nmax
-    const double *amp;      // batch output, complex128 amplitudes
-    const int64_t *amp_off; // per slot: first amplitude, or -1 (main group above nmax)
-    const uint64_t *off;    // off[k] = first state of photon number k, k = 0..nmax+1
+    uint64_t G;
+    const double2 *amp;
+    const int64_t *amp_off; // per slot: amplitude vector, or -1 (group above nmax)
+    const double *inv_tfac; // per slot: 1 / prod_i t_i! of its group
+    const LeafDescNarrow *desc;
+    const double *lowfac;
+    uint64_t leaves_upto[SLOS_SRC_MAX_NMAX + 1];  // leaves of photon numbers 1..k
+    uint64_t off[SLOS_SRC_MAX_NMAX + 2];
     int nmax;
 };
 // y = gamma * L(in) + alpha * a + beta * b on graded vectors, one launch for
 // all pairs r = blockIdx.y of a butterfly step.  (L in)[t] = sum over the
 // occupied modes j of t of |U[j, col]|^2 in[t - e_j]: one distinguishable
 // photon entering mode col.  y may alias a or b (same element only), never in.
-// Outputs of photon number outside [popcount(r), popcount(r) + span] are
-// known to be 0 and are written as 0 without reading.
+// Supports: with c = popcount(r), operand X holds photon numbers
+// [c + X_lo, c + X_lo + X_len] and is read only there; y is written on
+// [c, c + y_len] (all clipped to [0, nmax]) and nowhere else.  Leaf records
+// carry their photon number in h.pad.
 struct SrcPassParams {
     const double *in;
     const double *a;
@@ -101,11 +127,11 @@ struct SrcPassParams {
     uint64_t s_in, s_a, s_b, s_y;   // elements between consecutive pairs
     double gamma, alpha, beta;
     const LeafDescNarrow *desc;     // leaves of photon numbers 1..nmax, graded ranks
-    uint64_t nleaves;
+    uint64_t nleaves;               // leaves this launch scans (a prefix: photon numbers 1..kmax)
     const uint32_t *pred;
-    const uint64_t *off;
     const void *U;                  // complex128 m x m
-    int m, col, nmax, span;
+    int m, col, nmax;
+    int in_lo, in_len, a_lo, a_len, b_lo, b_len, y_len;
 };
 struct SrcStatsParams {
     const double *P;
@@ -115,9 +141,12 @@ struct SrcStatsParams {
     int m, nmax, ngroups, min_modes;
     int8_t group[256];
     uint8_t cmin[SLOS_PS_MAX_GROUPS], cmax[SLOS_PS_MAX_GROUPS];
-    double *partials;               // [nmax + 1][SLOS_SRC_STATS_BLOCKS][3]
+    uint64_t chunk;                               // states per block
+    uint32_t blk_off[SLOS_SRC_MAX_NMAX + 2];      // first block of each photon number
+    double *partials;               // blk_off[nmax + 1] x 3
     double *result;                 // [nmax + 1][3]: mass, physical, kept
 };
+int slos_launch_src_group(const SrcGroupParams &p, int nsub, void *stream);
 int slos_launch_src_fill(const SrcFillParams &p, int nslots, void *stream);
 int slos_launch_src_pass(const SrcPassParams &p, int npairs, void *stream);
 int slos_launch_src_stats(const SrcStatsParams &p, void *stream);

@@ -215,6 +215,7 @@ def test_select_validates_arguments():
     (1.0, 0.6, 1.0, -1, [1, 1, 0]),        # beta * g2 above 1/2
     (1.0, 0.0, 1.5, -1, [1, 1, 0]),
     (1.0, 0.1, 1.0, 17, [1, 1, 0]),        # nmax above 16
+    (1.0, 0.1, 1.0, 5, [1, 1, 0]),         # nmax above 2n
     (1.0, 0.1, 1.0, -1, [9, 0, 0]),        # 2n = 18 photons by default
     (1.0, 0.0, 1.0, -1, [13, 0, 0]),       # more than 12 sources
     (1.0, 0.0, 1.0, -1, [1, -1, 0]),
