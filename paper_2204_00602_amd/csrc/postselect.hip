@@ -214,19 +214,33 @@ __global__ __launch_bounds__(256) void ps_leaf_kernel(PostselectParams p)
             for (int h = 0; h < SLOS_PS_MAX_GROUPS; ++h) hc[h] += (g == h) ? 1u : 0u;
         }
         const uint4 *low = (const uint4 *)p.low + p.type_off[tab];
-        for (uint32_t x = lane; x < size; x += 64) {
-            const uint4 w = low[x];
-            const T v = P[base + x];
-            bool ok = true;
+        // four outputs per lane and step (x0 + 64u), loads first: P is read once
+        // (non-temporal, so the shared low-state table stays in L2)
+        for (uint32_t x0 = lane; x0 < size; x0 += 256) {
+            uint4 w[4];
+            T v[4];
 #pragma unroll
-            for (int g = 0; g < SLOS_PS_MAX_GROUPS; ++g) {
-                if (g < p.ngroups) {
-                    const uint32_t c = byte_of(w, g) + hc[g];
-                    ok = ok && c >= p.cmin[g] && c <= p.cmax[g];
-                }
+            for (int u = 0; u < 4; ++u) {
+                const uint32_t x = x0 + 64u * u;
+                const uint32_t xc = x < size ? x : x0;
+                w[u] = low[xc];
+                v[u] = __builtin_nontemporal_load(P + base + xc);
             }
-            if (ok) acc += (double)v;
-            if (out) out[base + x] = ok ? v : (T)0;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const uint32_t x = x0 + 64u * u;
+                if (x >= size) break;
+                bool ok = true;
+#pragma unroll
+                for (int g = 0; g < SLOS_PS_MAX_GROUPS; ++g) {
+                    if (g < p.ngroups) {
+                        const uint32_t c = byte_of(w[u], g) + hc[g];
+                        ok = ok && c >= p.cmin[g] && c <= p.cmax[g];
+                    }
+                }
+                if (ok) acc += (double)v[u];
+                if (out) out[base + x] = ok ? v[u] : (T)0;
+            }
         }
     }
 #pragma unroll

@@ -13,9 +13,12 @@
 // block sums are summed again, those few run sums are scanned in one
 // workgroup, and cdf_fix_kernel turns the block sums into the exclusive prefix
 // bp[0..nb] (bp[nb] = sum P), every step in a fixed order, so the table is
-// reproducible.  A sample finds
-// its block with a 64-way search over bp and then its state with wave scans of
-// the block in 64-state chunks.
+// reproducible; the run prefixes stay after the table (sp = bp + nb + 1), and
+// the block kernel also keeps the sums of each block's 16 chunks of 64 states
+// (cs = sp + nsup + 1).  A sample finds its run with a 64-way search over sp,
+// its block with a 64-way search over that run's part of bp, its chunk from the
+// block's 16 chunk sums (one cache line), and then its state with a wave scan
+// of that chunk: about 400 bytes per sample instead of half a 4 KB block.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -31,7 +34,7 @@ typedef double cdf_d2 __attribute__((ext_vector_type(2)));
 
 template <typename T>
 __global__ __launch_bounds__(256) void cdf_block_kernel(const T *__restrict__ P, int64_t M, int64_t nb,
-                                                        double *__restrict__ bp)
+                                                        double *__restrict__ bp, double *__restrict__ cs)
 {
     const int lane = threadIdx.x & 63;
     const int64_t gw = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
@@ -63,6 +66,10 @@ __global__ __launch_bounds__(256) void cdf_block_kernel(const T *__restrict__ P,
                 if (x < M) s += (double)P[x];
             }
         }
+        // chunk c (states 64c .. 64c + 63) is held by lanes 4c .. 4c + 3
+        double cc = s + __shfl_xor(s, 1, 64);
+        cc += __shfl_xor(cc, 2, 64);
+        if ((lane & 3) == 0) cs[b * kChunks + (lane >> 2)] = cc;
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
         if (lane == 0) bp[b] = s;
@@ -168,15 +175,31 @@ __global__ __launch_bounds__(256) void sample_kernel(const T *__restrict__ P, in
                                                      int64_t nb, const double *__restrict__ r, int64_t count,
                                                      int64_t *__restrict__ ranks)
 {
+    const int64_t nsup = (nb + SLOS_CDF_BLOCK - 1) / SLOS_CDF_BLOCK;
+    const double *__restrict__ sp = bp + nb + 1;  // run prefixes, nsup + 1 entries
+    const double *__restrict__ cs = sp + nsup + 1;  // chunk sums, kChunks per block
     const int lane = threadIdx.x & 63;
     const int64_t gw = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
     const double total = bp[nb];
     for (int64_t sidx = gw; sidx < count; sidx += nw) {
         const double t = r[sidx] * total;
-        // largest block b in [0, nb) with bp[b] <= t: 64-way search (bp is
-        // non-decreasing and bp[0] = 0 <= t, so the predicate holds on a prefix)
-        int64_t lo = 0, hi = nb;
+        // the run of SLOS_CDF_BLOCK blocks first: largest s with sp[s] <= t over
+        // the small run-prefix table (cache resident), then the largest block b
+        // of that run with bp[b] <= t; both 64-way searches (the tables are
+        // non-decreasing and start at 0 <= t, so the predicate holds on a prefix)
+        int64_t lo = 0, hi = nsup;
+        while (hi - lo > 1) {
+            const int64_t step = (hi - lo + 63) / 64;
+            const int64_t pos = lo + (int64_t)lane * step;
+            const bool ok = pos < hi && sp[pos] <= t;
+            const uint64_t bal = __ballot(ok);
+            const int last = bal ? 63 - __builtin_clzll(bal) : 0;
+            lo = lo + (int64_t)last * step;
+            hi = min(lo + step, hi);
+        }
+        lo = lo * SLOS_CDF_BLOCK;
+        hi = min(lo + SLOS_CDF_BLOCK, nb);
         while (hi - lo > 1) {
             const int64_t step = (hi - lo + 63) / 64;
             const int64_t pos = lo + (int64_t)lane * step;
@@ -186,11 +209,24 @@ __global__ __launch_bounds__(256) void sample_kernel(const T *__restrict__ P, in
             lo = lo + (int64_t)last * step;
             hi = min(lo + step, hi);
         }
-        // first state of block lo whose running sum exceeds t
+        // the block's chunk sums (one line): the first chunk whose running sum
+        // exceeds t, else the last chunk of non-zero probability
         const int64_t base = lo * SLOS_CDF_BLOCK;
-        double run = bp[lo];
+        const double c_own = lane < kChunks ? cs[lo * kChunks + lane] : 0.0;
+        double c_inc = c_own;
+#pragma unroll
+        for (int o = 1; o < kChunks; o <<= 1) {
+            const double u = __shfl_up(c_inc, o, 64);
+            if (lane >= o) c_inc += u;
+        }
+        const uint64_t c_cross = __ballot(lane < kChunks && bp[lo] + c_inc > t && c_own > 0.0);
+        const uint64_t c_pos = __ballot(lane < kChunks && c_own > 0.0);
+        const int i0 = c_cross ? __builtin_ctzll(c_cross) : (c_pos ? 63 - __builtin_clzll(c_pos) : 0);
+        // then the states of the chunks from i0 on (rounding between the chunk
+        // sums and this scan can move the crossing on to a later chunk)
+        double run = bp[lo] + __shfl(c_inc - c_own, i0, 64);
         int64_t found = -1, last_pos = -1;
-        for (int i = 0; i < kChunks && found < 0; ++i) {
+        for (int i = i0; i < kChunks && found < 0; ++i) {
             const int64_t x = base + i * 64 + lane;
             const double v = x < M ? (double)P[x] : 0.0;
             double c = v;
@@ -218,14 +254,15 @@ int slos_launch_cdf(const void *P, int c64, int64_t M, double *bp, void *stream)
 {
     const int64_t nb = (M + SLOS_CDF_BLOCK - 1) / SLOS_CDF_BLOCK;
     const int64_t nsup = (nb + SLOS_CDF_BLOCK - 1) / SLOS_CDF_BLOCK;
-    double *sp = bp + nb + 1;  // nsup + 1 run prefixes after the table
+    double *sp = bp + nb + 1;    // nsup + 1 run prefixes after the table
+    double *cs = sp + nsup + 1;  // then 16 chunk sums per block
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((nb + 3) / 4, 8192));
     const int gsup = (int)std::max<int64_t>(1, std::min<int64_t>((nsup + 3) / 4, 8192));
     hipStream_t s = (hipStream_t)stream;
     if (c64)
-        hipLaunchKernelGGL(cdf_block_kernel<float>, dim3(grid), dim3(256), 0, s, (const float *)P, M, nb, bp);
+        hipLaunchKernelGGL(cdf_block_kernel<float>, dim3(grid), dim3(256), 0, s, (const float *)P, M, nb, bp, cs);
     else
-        hipLaunchKernelGGL(cdf_block_kernel<double>, dim3(grid), dim3(256), 0, s, (const double *)P, M, nb, bp);
+        hipLaunchKernelGGL(cdf_block_kernel<double>, dim3(grid), dim3(256), 0, s, (const double *)P, M, nb, bp, cs);
     hipLaunchKernelGGL(cdf_super_kernel, dim3(gsup), dim3(256), 0, s, (const double *)bp, nb, nsup, sp);
     hipLaunchKernelGGL(cdf_scan_kernel, dim3(1), dim3(1024), 0, s, sp, nsup);
     hipLaunchKernelGGL(cdf_fix_kernel, dim3(gsup), dim3(256), 0, s, bp, nb, (const double *)sp, nsup);
