@@ -168,7 +168,8 @@ __global__ __launch_bounds__(256) void ps_low_kernel(PostselectParams p)
     w.y = c[4] | c[5] << 8 | c[6] << 16 | (uint32_t)c[7] << 24;
     w.z = c[8] | c[9] << 8 | c[10] << 16 | (uint32_t)c[11] << 24;
     w.w = c[12] | c[13] << 8 | c[14] << 16 | (uint32_t)c[15] << 24;
-    ((uint4 *)p.low)[e] = w;
+    if (p.ngroups <= 4) ((uint32_t *)p.low)[e] = w.x;  // narrow table: 4 bytes per state
+    else ((uint4 *)p.low)[e] = w;
 }
 
 __device__ __forceinline__ uint32_t byte_of(const uint4 &w, int g)
@@ -177,10 +178,20 @@ __device__ __forceinline__ uint32_t byte_of(const uint4 &w, int g)
     return (d >> (8 * (g & 3))) & 0xFFu;
 }
 
-// one wave per leaf of the last layer; one FP64 partial per wave
-template <typename T>
+// table entry of a low state: 16 group counts, or 4 in one word (NARROW)
+template <bool NARROW> struct LowEntry;
+template <> struct LowEntry<false> { using type = uint4; };
+template <> struct LowEntry<true> { using type = uint32_t; };
+__device__ __forceinline__ uint32_t count_of(const uint4 &w, int g) { return byte_of(w, g); }
+__device__ __forceinline__ uint32_t count_of(uint32_t w, int g) { return (w >> (8 * (g & 3))) & 0xFFu; }
+
+// one wave per leaf of the last layer; one FP64 partial per wave.  NARROW:
+// at most 4 groups, table entries of 4 bytes
+template <typename T, bool NARROW>
 __global__ __launch_bounds__(256) void ps_leaf_kernel(PostselectParams p)
 {
+    using E = typename LowEntry<NARROW>::type;
+    constexpr int NG = NARROW ? 4 : SLOS_PS_MAX_GROUPS;
     __shared__ int8_t grp[256];
     for (int j = threadIdx.x; j < 256; j += blockDim.x) grp[j] = p.group[j];
     __syncthreads();
@@ -213,11 +224,11 @@ __global__ __launch_bounds__(256) void ps_leaf_kernel(PostselectParams p)
 #pragma unroll
             for (int h = 0; h < SLOS_PS_MAX_GROUPS; ++h) hc[h] += (g == h) ? 1u : 0u;
         }
-        const uint4 *low = (const uint4 *)p.low + p.type_off[tab];
+        const E *low = (const E *)p.low + p.type_off[tab];
         // four outputs per lane and step (x0 + 64u), loads first: P is read once
         // (non-temporal, so the shared low-state table stays in L2)
         for (uint32_t x0 = lane; x0 < size; x0 += 256) {
-            uint4 w[4];
+            E w[4];
             T v[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
@@ -232,9 +243,9 @@ __global__ __launch_bounds__(256) void ps_leaf_kernel(PostselectParams p)
                 if (x >= size) break;
                 bool ok = true;
 #pragma unroll
-                for (int g = 0; g < SLOS_PS_MAX_GROUPS; ++g) {
+                for (int g = 0; g < NG; ++g) {
                     if (g < p.ngroups) {
-                        const uint32_t c = byte_of(w[u], g) + hc[g];
+                        const uint32_t c = count_of(w[u], g) + hc[g];
                         ok = ok && c >= p.cmin[g] && c <= p.cmax[g];
                     }
                 }
@@ -292,10 +303,15 @@ int slos_launch_postselect(const PostselectParams &p, int c64, void *stream)
         hipLaunchKernelGGL(ps_low_kernel, dim3(gl > 0 ? gl : 1), dim3(256), 256 * 256, s, p);
         if ((e = hipGetLastError()) != hipSuccess) return (int)e;
         const int grid = SLOS_PS_MAX_WAVES / 4;
-        if (c64)
-            hipLaunchKernelGGL(ps_leaf_kernel<float>, dim3(grid), dim3(256), 0, s, p);
+        const bool narrow = p.ngroups <= 4;
+        if (c64 && narrow)
+            hipLaunchKernelGGL((ps_leaf_kernel<float, true>), dim3(grid), dim3(256), 0, s, p);
+        else if (c64)
+            hipLaunchKernelGGL((ps_leaf_kernel<float, false>), dim3(grid), dim3(256), 0, s, p);
+        else if (narrow)
+            hipLaunchKernelGGL((ps_leaf_kernel<double, true>), dim3(grid), dim3(256), 0, s, p);
         else
-            hipLaunchKernelGGL(ps_leaf_kernel<double>, dim3(grid), dim3(256), 0, s, p);
+            hipLaunchKernelGGL((ps_leaf_kernel<double, false>), dim3(grid), dim3(256), 0, s, p);
         return (int)hipGetLastError();
     }
     // no photons: one output, walked by one thread

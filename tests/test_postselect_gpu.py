@@ -78,6 +78,10 @@ def test_config2_groups_match_oracle(dtype):
         ([-1] * m, [], []),
         ([0] + [-1] * 11, [7], [9]),   # more photons than exist: nothing kept
         ([i % 4 for i in range(m)], [1, 1, 1, 1], [2, 2, 2, 2]),
+        # more than 4 groups: the 16-count table entries
+        ([i % 5 for i in range(m)], [0, 1, 0, 1, 0], [2, 2, 1, 3, 2]),
+        ([i % 6 for i in range(m)], [1] * 6, [1] * 6),
+        (list(range(m)), [0] * m, [1] * m),                             # no bunching
     ]
     Pn = P.cpu().numpy().astype(np.float64)
     for gm, lo, hi in cases:
