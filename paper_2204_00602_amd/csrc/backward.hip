@@ -184,16 +184,12 @@ __device__ __forceinline__ Cd cmul(Cd a, Cd b) { return Cd{a.x * b.x - a.y * b.y
 __device__ __forceinline__ Cd cadd(Cd a, Cd b) { return Cd{a.x + b.x, a.y + b.y}; }
 __device__ __forceinline__ Cd cconj(Cd a) { return Cd{a.x, -a.y}; }
 
-// 2x2 MZI block B and its derivatives dB/da, dB/db
-__device__ void mzi_block(double a, double b, Cd B[4], Cd dA[4], Cd dBb[4])
+// 2x2 MZI block B and its derivatives dB/da, dB/db, from e^{ia} and e^{ib}
+__device__ void mzi_block_e(Cd ea, Cd eb, Cd B[4], Cd dA[4], Cd dBb[4])
 {
     const double r = 0.70710678118654752440;  // cos(pi/4) = sin(pi/4)
     // BS * BS-like products written out: BS = r [[1, i], [i, 1]]
     // M = BS PS0(a) BS = r^2 [[e^{ia} - 1, i(e^{ia} + 1)], [i(e^{ia} + 1), -e^{ia} + 1]]
-    double sa, ca, sb, cb;
-    sincos(a, &sa, &ca);
-    sincos(b, &sb, &cb);
-    const Cd ea{ca, sa}, eb{cb, sb};
     const double h = r * r;
     const Cd m00{h * (ea.x - 1.0), h * ea.y};
     const Cd m01{-h * ea.y, h * (ea.x + 1.0)};   // i h (e^{ia} + 1)
@@ -220,127 +216,139 @@ __device__ void mzi_block(double a, double b, Cd B[4], Cd dA[4], Cd dBb[4])
     dBb[3] = cmul(ieb, m11);
 }
 
-// one workgroup per phase set; thread c owns column c of the running product
+__device__ __forceinline__ Cd cexp_i(double a)
+{
+    double s, c;
+    sincos(a, &s, &c);
+    return Cd{c, s};
+}
+
+// The phase factors e^{i phi} of one phase set: staged in LDS by all lanes at
+// once when E is given (the sweeps then need no sincos on their critical path),
+// else computed where they are used.
+struct PhaseFactors {
+    const double *ph;
+    Cd *E;  // 2 * nmzi entries, or nullptr
+    __device__ void stage(int nmzi, int lane, int nlanes)
+    {
+        if (!E) return;
+        for (int i = lane; i < 2 * nmzi; i += nlanes) E[i] = cexp_i(ph[i]);
+        __syncthreads();
+    }
+    __device__ void block(int k, Cd B[4], Cd dA[4], Cd dB[4]) const
+    {
+        if (E) mzi_block_e(E[2 * k], E[2 * k + 1], B, dA, dB);
+        else mzi_block_e(cexp_i(ph[2 * k]), cexp_i(ph[2 * k + 1]), B, dA, dB);
+    }
+};
+
+// One wave per phase set (m <= 64); lane c owns column c of the running
+// product, so the sweeps share nothing between lanes and need no barriers.
 template <typename T>
-__global__ void mesh_forward_kernel(int m, int nmzi, const double *__restrict__ phases,
-                                    typename Cb<T>::type *__restrict__ Uout)
+__global__ __launch_bounds__(64) void mesh_forward_kernel(int m, int nmzi, const double *__restrict__ phases,
+                                                          typename Cb<T>::type *__restrict__ Uout, int stage)
 {
     using C = typename Cb<T>::type;
-    extern __shared__ Cd Ush[];  // m x m
+    extern __shared__ Cd Ush[];  // m x m, then 2 nmzi phase factors when staged
     const int b = blockIdx.x;
-    const double *ph = phases + (size_t)b * 2 * nmzi;
+    PhaseFactors pf{phases + (size_t)b * 2 * nmzi, stage ? Ush + m * m : nullptr};
+    pf.stage(nmzi, threadIdx.x, blockDim.x);
     const int c = threadIdx.x;
-    if (c < m)
-        for (int r = 0; r < m; ++r) Ush[r * m + c] = Cd{r == c ? 1.0 : 0.0, 0.0};
-    __syncthreads();
+    if (c >= m) return;
+    for (int r = 0; r < m; ++r) Ush[r * m + c] = Cd{r == c ? 1.0 : 0.0, 0.0};
     int k = 0;
     for (int col = 0; col < m; ++col)
         for (int p0 = col % 2; p0 + 1 < m; p0 += 2, ++k) {
             Cd B[4], dA[4], dB[4];
-            mzi_block(ph[2 * k], ph[2 * k + 1], B, dA, dB);
-            if (c < m) {
-                const Cd x0 = Ush[p0 * m + c], x1 = Ush[(p0 + 1) * m + c];
-                Ush[p0 * m + c] = cadd(cmul(B[0], x0), cmul(B[1], x1));
-                Ush[(p0 + 1) * m + c] = cadd(cmul(B[2], x0), cmul(B[3], x1));
-            }
-            __syncthreads();
+            pf.block(k, B, dA, dB);
+            const Cd x0 = Ush[p0 * m + c], x1 = Ush[(p0 + 1) * m + c];
+            Ush[p0 * m + c] = cadd(cmul(B[0], x0), cmul(B[1], x1));
+            Ush[(p0 + 1) * m + c] = cadd(cmul(B[2], x0), cmul(B[3], x1));
         }
-    if (c < m)
-        for (int r = 0; r < m; ++r) {
-            const Cd v = Ush[r * m + c];
-            Uout[(size_t)b * m * m + (size_t)r * m + c] = C{(T)v.x, (T)v.y};
-        }
+    for (int r = 0; r < m; ++r) {
+        const Cd v = Ush[r * m + c];
+        Uout[(size_t)b * m * m + (size_t)r * m + c] = C{(T)v.x, (T)v.y};
+    }
 }
 
 // Reverse sweep: with U = L_k T_k R_k, P = L_k^H G_U and Q = L_k^H U = T_k R_k,
 //   dL/dphi = Re sum conj(P) o (dT_k T_k^H Q),
-// then P <- T_k^H P and Q <- T_k^H Q move to the previous MZI.
+// then P <- T_k^H P and Q <- T_k^H Q move to the previous MZI.  The sum over
+// columns is a wave reduction.
 template <typename T>
-__global__ void mesh_backward_kernel(int m, int nmzi, const double *__restrict__ phases,
-                                     const typename Cb<T>::type *__restrict__ GU, double *__restrict__ gphases)
+__global__ __launch_bounds__(64) void mesh_backward_kernel(int m, int nmzi, const double *__restrict__ phases,
+                                                           const typename Cb<T>::type *__restrict__ GU,
+                                                           double *__restrict__ gphases, int stage)
 {
-    extern __shared__ Cd sh[];  // P (m x m), Q (m x m), red (2 x blockDim)
+    extern __shared__ Cd sh[];  // P (m x m), Q (m x m), then 2 nmzi phase factors when staged
     Cd *P = sh;
     Cd *Q = sh + m * m;
-    double *red = (double *)(sh + 2 * m * m);
     const int b = blockIdx.x;
-    const double *ph = phases + (size_t)b * 2 * nmzi;
+    PhaseFactors pf{phases + (size_t)b * 2 * nmzi, stage ? sh + 2 * m * m : nullptr};
+    pf.stage(nmzi, threadIdx.x, blockDim.x);
     const int c = threadIdx.x;
+    const bool own = c < m;
     // Q = U (rebuilt here), P = G_U
-    if (c < m)
+    if (own)
         for (int r = 0; r < m; ++r) {
             Q[r * m + c] = Cd{r == c ? 1.0 : 0.0, 0.0};
             const auto g = GU[(size_t)b * m * m + (size_t)r * m + c];
             P[r * m + c] = Cd{(double)g.x, (double)g.y};
         }
-    __syncthreads();
     int k = 0;
     for (int col = 0; col < m; ++col)
         for (int p0 = col % 2; p0 + 1 < m; p0 += 2, ++k) {
+            if (!own) continue;
             Cd B[4], dA[4], dB[4];
-            mzi_block(ph[2 * k], ph[2 * k + 1], B, dA, dB);
-            if (c < m) {
-                const Cd x0 = Q[p0 * m + c], x1 = Q[(p0 + 1) * m + c];
-                Q[p0 * m + c] = cadd(cmul(B[0], x0), cmul(B[1], x1));
-                Q[(p0 + 1) * m + c] = cadd(cmul(B[2], x0), cmul(B[3], x1));
+            pf.block(k, B, dA, dB);
+            const Cd x0 = Q[p0 * m + c], x1 = Q[(p0 + 1) * m + c];
+            Q[p0 * m + c] = cadd(cmul(B[0], x0), cmul(B[1], x1));
+            Q[(p0 + 1) * m + c] = cadd(cmul(B[2], x0), cmul(B[3], x1));
+        }
+    // MZIs in reverse: column by column from the last, top pair last within a column
+    k = nmzi;
+    for (int col = m - 1; col >= 0; --col) {
+        const int cnt = (m - 1 - (col % 2) + 1) / 2;
+        for (int i = cnt - 1; i >= 0; --i) {
+            --k;
+            const int p0 = col % 2 + 2 * i;
+            Cd B[4], dA[4], dB[4];
+            pf.block(k, B, dA, dB);
+            // D = dT T^H restricted to rows p0, p0+1 (2x2): D = dB B^H
+            Cd Da[4], Db[4];
+            for (int r = 0; r < 2; ++r)
+                for (int s = 0; s < 2; ++s) {
+                    Da[2 * r + s] =
+                        cadd(cmul(dA[2 * r], cconj(B[2 * s])), cmul(dA[2 * r + 1], cconj(B[2 * s + 1])));
+                    Db[2 * r + s] =
+                        cadd(cmul(dB[2 * r], cconj(B[2 * s])), cmul(dB[2 * r + 1], cconj(B[2 * s + 1])));
+                }
+            double va = 0.0, vb = 0.0;
+            if (own) {
+                const Cd q0 = Q[p0 * m + c], q1 = Q[(p0 + 1) * m + c];
+                const Cd pp0 = P[p0 * m + c], pp1 = P[(p0 + 1) * m + c];
+                const Cd ya0 = cadd(cmul(Da[0], q0), cmul(Da[1], q1));
+                const Cd ya1 = cadd(cmul(Da[2], q0), cmul(Da[3], q1));
+                const Cd yb0 = cadd(cmul(Db[0], q0), cmul(Db[1], q1));
+                const Cd yb1 = cadd(cmul(Db[2], q0), cmul(Db[3], q1));
+                va = pp0.x * ya0.x + pp0.y * ya0.y + pp1.x * ya1.x + pp1.y * ya1.y;
+                vb = pp0.x * yb0.x + pp0.y * yb0.y + pp1.x * yb1.x + pp1.y * yb1.y;
+                // P <- T^H P, Q <- T^H Q on rows p0, p0+1
+                Q[p0 * m + c] = cadd(cmul(cconj(B[0]), q0), cmul(cconj(B[2]), q1));
+                Q[(p0 + 1) * m + c] = cadd(cmul(cconj(B[1]), q0), cmul(cconj(B[3]), q1));
+                P[p0 * m + c] = cadd(cmul(cconj(B[0]), pp0), cmul(cconj(B[2]), pp1));
+                P[(p0 + 1) * m + c] = cadd(cmul(cconj(B[1]), pp0), cmul(cconj(B[3]), pp1));
             }
-            __syncthreads();
-        }
-    for (k = nmzi - 1; k >= 0; --k) {
-        // position of MZI k
-        int col = 0, p0 = 0, kk = 0;
-        for (col = 0; col < m; ++col) {
-            const int cnt = (m - 1 - (col % 2) + 1) / 2;
-            if (kk + cnt > k) {
-                p0 = col % 2 + 2 * (k - kk);
-                break;
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+                va += __shfl_xor(va, o, 64);
+                vb += __shfl_xor(vb, o, 64);
             }
-            kk += cnt;
-        }
-        Cd B[4], dA[4], dB[4];
-        mzi_block(ph[2 * k], ph[2 * k + 1], B, dA, dB);
-        // D = dT T^H restricted to rows p0, p0+1 (2x2): D = dB B^H
-        Cd Da[4], Db[4];
-        for (int r = 0; r < 2; ++r)
-            for (int s = 0; s < 2; ++s) {
-                Da[2 * r + s] = cadd(cmul(dA[2 * r], cconj(B[2 * s])), cmul(dA[2 * r + 1], cconj(B[2 * s + 1])));
-                Db[2 * r + s] = cadd(cmul(dB[2 * r], cconj(B[2 * s])), cmul(dB[2 * r + 1], cconj(B[2 * s + 1])));
+            if (c == 0) {
+                gphases[(size_t)b * 2 * nmzi + 2 * k] = va;
+                gphases[(size_t)b * 2 * nmzi + 2 * k + 1] = vb;
             }
-        double va = 0.0, vb = 0.0;
-        if (c < m) {
-            const Cd q0 = Q[p0 * m + c], q1 = Q[(p0 + 1) * m + c];
-            const Cd pp0 = P[p0 * m + c], pp1 = P[(p0 + 1) * m + c];
-            const Cd ya0 = cadd(cmul(Da[0], q0), cmul(Da[1], q1));
-            const Cd ya1 = cadd(cmul(Da[2], q0), cmul(Da[3], q1));
-            const Cd yb0 = cadd(cmul(Db[0], q0), cmul(Db[1], q1));
-            const Cd yb1 = cadd(cmul(Db[2], q0), cmul(Db[3], q1));
-            va = pp0.x * ya0.x + pp0.y * ya0.y + pp1.x * ya1.x + pp1.y * ya1.y;
-            vb = pp0.x * yb0.x + pp0.y * yb0.y + pp1.x * yb1.x + pp1.y * yb1.y;
         }
-        red[c] = va;
-        red[blockDim.x + c] = vb;
-        __syncthreads();
-        for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-            if (c < w) {
-                red[c] += red[c + w];
-                red[blockDim.x + c] += red[blockDim.x + c + w];
-            }
-            __syncthreads();
-        }
-        if (c == 0) {
-            gphases[(size_t)b * 2 * nmzi + 2 * k] = red[0];
-            gphases[(size_t)b * 2 * nmzi + 2 * k + 1] = red[blockDim.x];
-        }
-        // P <- T^H P, Q <- T^H Q on rows p0, p0+1
-        if (c < m) {
-            const Cd q0 = Q[p0 * m + c], q1 = Q[(p0 + 1) * m + c];
-            Q[p0 * m + c] = cadd(cmul(cconj(B[0]), q0), cmul(cconj(B[2]), q1));
-            Q[(p0 + 1) * m + c] = cadd(cmul(cconj(B[1]), q0), cmul(cconj(B[3]), q1));
-            const Cd x0 = P[p0 * m + c], x1 = P[(p0 + 1) * m + c];
-            P[p0 * m + c] = cadd(cmul(cconj(B[0]), x0), cmul(cconj(B[2]), x1));
-            P[(p0 + 1) * m + c] = cadd(cmul(cconj(B[1]), x0), cmul(cconj(B[3]), x1));
-        }
-        __syncthreads();
     }
 }
 
@@ -410,17 +418,18 @@ int slos_launch_gradu(const void *colsum, const int32_t *photons, int n, int m, 
 int slos_launch_mesh_forward(int m, int batch, const double *phases, void *U, int c64, void *stream)
 {
     const int nmzi = m * (m - 1) / 2;
-    const int threads = ((m + 63) / 64) * 64;
-    const size_t lds = (size_t)m * m * sizeof(Cd);
+    const size_t mat = (size_t)m * m * sizeof(Cd), fac = 2 * (size_t)nmzi * sizeof(Cd);
+    const int stage = mat + fac <= SLOS_LDS_DYNAMIC_MAX;  // phase factors in LDS when they fit
+    const size_t lds = mat + (stage ? fac : 0);
     static bool a32 = false, a64 = false;
     hipError_t e = c64 ? allow_lds(mesh_forward_kernel<float>, a32) : allow_lds(mesh_forward_kernel<double>, a64);
     if (e != hipSuccess) return (int)e;
     if (c64)
-        hipLaunchKernelGGL(mesh_forward_kernel<float>, dim3(batch), dim3(threads), lds, (hipStream_t)stream, m, nmzi,
-                           phases, (float2 *)U);
+        hipLaunchKernelGGL(mesh_forward_kernel<float>, dim3(batch), dim3(64), lds, (hipStream_t)stream, m, nmzi,
+                           phases, (float2 *)U, stage);
     else
-        hipLaunchKernelGGL(mesh_forward_kernel<double>, dim3(batch), dim3(threads), lds, (hipStream_t)stream, m,
-                           nmzi, phases, (double2 *)U);
+        hipLaunchKernelGGL(mesh_forward_kernel<double>, dim3(batch), dim3(64), lds, (hipStream_t)stream, m, nmzi,
+                           phases, (double2 *)U, stage);
     return (int)hipGetLastError();
 }
 
@@ -428,16 +437,17 @@ int slos_launch_mesh_backward(int m, int batch, const double *phases, const void
                               void *stream)
 {
     const int nmzi = m * (m - 1) / 2;
-    const int threads = ((m + 63) / 64) * 64;
-    const size_t lds = 2 * (size_t)m * m * sizeof(Cd) + 2 * (size_t)threads * sizeof(double);
+    const size_t mat = 2 * (size_t)m * m * sizeof(Cd), fac = 2 * (size_t)nmzi * sizeof(Cd);
+    const int stage = mat + fac <= SLOS_LDS_DYNAMIC_MAX;
+    const size_t lds = mat + (stage ? fac : 0);
     static bool a32 = false, a64 = false;
     hipError_t e = c64 ? allow_lds(mesh_backward_kernel<float>, a32) : allow_lds(mesh_backward_kernel<double>, a64);
     if (e != hipSuccess) return (int)e;
     if (c64)
-        hipLaunchKernelGGL(mesh_backward_kernel<float>, dim3(batch), dim3(threads), lds, (hipStream_t)stream, m,
-                           nmzi, phases, (const float2 *)GU, gphases);
+        hipLaunchKernelGGL(mesh_backward_kernel<float>, dim3(batch), dim3(64), lds, (hipStream_t)stream, m, nmzi,
+                           phases, (const float2 *)GU, gphases, stage);
     else
-        hipLaunchKernelGGL(mesh_backward_kernel<double>, dim3(batch), dim3(threads), lds, (hipStream_t)stream, m,
-                           nmzi, phases, (const double2 *)GU, gphases);
+        hipLaunchKernelGGL(mesh_backward_kernel<double>, dim3(batch), dim3(64), lds, (hipStream_t)stream, m, nmzi,
+                           phases, (const double2 *)GU, gphases, stage);
     return (int)hipGetLastError();
 }

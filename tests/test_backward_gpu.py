@@ -88,7 +88,7 @@ def test_backward_requires_kept_layers():
         p.backward(U, torch.zeros(6, dtype=torch.complex128, device="cuda"))
 
 
-@pytest.mark.parametrize("m", [2, 5, 12])
+@pytest.mark.parametrize("m", [2, 5, 12, 64])  # 64: the largest mesh, phase factors staged
 def test_mesh_forward_matches_oracle(m):
     k = slos.mesh_mzi_count(m)
     ph = inputs.mesh_phases(3, k, 220 + m)
@@ -97,7 +97,7 @@ def test_mesh_forward_matches_oracle(m):
         assert np.abs(U[b] - oracle.clements_unitary(m, ph[b])).max() < 1e-13
 
 
-@pytest.mark.parametrize("m", [3, 6, 12])
+@pytest.mark.parametrize("m", [3, 6, 12, 50, 64])  # 50, 64: phase factors computed in the sweep
 def test_mesh_backward_matches_oracle_vjp(m):
     k = slos.mesh_mzi_count(m)
     ph = inputs.mesh_phases(2, k, 230 + m)
