@@ -89,23 +89,35 @@ __global__ __launch_bounds__(64) void bwd_layer_kernel(BwdParams p)
             const bool ok = y < U.low_size;
             const uint32_t yc = ok ? y : U.low_size - 1u;
             const C a = A[U.low_base + yc];
+            const double ar = (double)a.x, ai = (double)a.y;
             double accr = 0.0, acci = 0.0;
-            for (int j = 0; j < p.m; ++j) {
-                // successor t' + e_j: inside the forward leaf for a low mode,
-                // the aligned block of the high part + e_j otherwise
-                const uint64_t pos = j < (int)U.q ? U.out_base + succ[(size_t)j * U.low_size + yc]
-                                                  : hb[j - (int)U.q] + yc;
-                const C s = gk[pos];
-                const double sr = (double)s.x, si = (double)s.y;
-                const double ur = (double)uc[j].x, ui = (double)uc[j].y;
-                accr += ur * sr - ui * si;
-                acci += ur * si + ui * sr;
-                if (ok) {
-                    // s * conj(a)
-                    const double ar = (double)a.x, ai = (double)a.y;
-                    double2 &pj = part[j * 64 + lane];
-                    pj.x += sr * ar + si * ai;
-                    pj.y += si * ar - sr * ai;
+            // four successor modes per step, their loads issued first (modes in
+            // ascending order within and across steps, so the sums keep one order)
+            for (int j0 = 0; j0 < p.m; j0 += 4) {
+                C sv[4];
+#pragma unroll
+                for (int d = 0; d < 4; ++d) {
+                    const int j = j0 + d < p.m ? j0 + d : j0;
+                    // successor t' + e_j: inside the forward leaf for a low mode,
+                    // the aligned block of the high part + e_j otherwise
+                    const uint64_t pos = j < (int)U.q ? U.out_base + succ[(size_t)j * U.low_size + yc]
+                                                      : hb[j - (int)U.q] + yc;
+                    sv[d] = gk[pos];
+                }
+#pragma unroll
+                for (int d = 0; d < 4; ++d) {
+                    const int j = j0 + d;
+                    if (j >= p.m) break;
+                    const double sr = (double)sv[d].x, si = (double)sv[d].y;
+                    const double ur = (double)uc[j].x, ui = (double)uc[j].y;
+                    accr += ur * sr - ui * si;
+                    acci += ur * si + ui * sr;
+                    if (ok) {
+                        // s * conj(a)
+                        double2 &pj = part[j * 64 + lane];
+                        pj.x += sr * ar + si * ai;
+                        pj.y += si * ar - sr * ai;
+                    }
                 }
             }
             if (ok) gkm1[U.low_base + y] = C{(T)accr, (T)acci};

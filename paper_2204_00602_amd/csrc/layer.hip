@@ -824,7 +824,8 @@ int slos_launch_vacuum(void *out, int c64, int mode, double *sum_p, void *stream
 
 int slos_launch_zero_u32(uint32_t *buf, int count, void *stream)
 {
-    hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(256), 0, (hipStream_t)stream, buf, count);
+    const int grid = std::max(1, std::min((count + 255) / 256, 1024));
+    hipLaunchKernelGGL(zero_u32_kernel, dim3(grid), dim3(256), 0, (hipStream_t)stream, buf, count);
     return (int)hipGetLastError();
 }
 
