@@ -65,7 +65,9 @@ def load_traffic(variant):
 
 
 def time_variant(torch, slos, T, U_np, dtype, compensated, steps, warmup):
+    t0 = time.perf_counter()
     plan = slos.Plan(T, dtype, compensated=compensated)
+    build_s = time.perf_counter() - t0
     tdt = torch.complex64 if dtype == "c64" else torch.complex128
     Ud = torch.from_numpy(U_np).to(tdt).cuda().contiguous()
     out = torch.empty(plan.num_outputs, dtype=tdt, device="cuda")
@@ -90,8 +92,10 @@ def time_variant(torch, slos, T, U_np, dtype, compensated, steps, warmup):
     lm = np.asarray(layer_ms)
     res = {
         "ms_per_step": total_ms / steps,
+        "step_ms_median": float(np.median(lm.sum(axis=1))),  # layers + sum reduction, per step
         "layer_ms_mean": lm.mean(axis=0).tolist(),
         "sum_p": float(sum_p.item()),
+        "plan_build_s": build_s,
     }
     del out, Ud
     plan.close()
@@ -454,6 +458,8 @@ def main():
                          "achieved_GBps_step": slos.algorithmic_bytes(m, n, 16 if k == "c128" else 8)
                          / (v["ms_per_step"] * 1e-3) / 1e9,
                          "last_layer_ms": v["layer_ms_mean"][n - 1],
+                         "step_ms_median": v["step_ms_median"],
+                         "plan_build_s": v["plan_build_s"],
                          "sum_p": v["sum_p"]} for k, v in results.items()},
     }
     if "c128" in results:
