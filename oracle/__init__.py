@@ -514,3 +514,53 @@ def source_performance(dist, group_of_mode, count_min, count_max, min_modes: int
         phys += float(np.sum(probs[occ]))
         kept += float(np.sum(probs[ok]))
     return phys, kept
+
+
+def source_probability(U, T, beta: float, g2: float, V: float, S) -> float:
+    """P(S) of the imperfect-source mixture for one output S, by the event sum:
+    sum over emission events of weight x sum over the splits S = S' + R of the
+    common group's P(S') (Eq. eqperm) times the law of the distinguishable
+    photons, Perm(|U|^2 restricted to rows R and their input columns) / prod R!
+    (independent particles).  Independent of source_distribution's convolutions."""
+    U = np.asarray(U, dtype=np.complex128)
+    m = U.shape[0]
+    Q = (np.abs(U) ** 2).astype(np.complex128)
+    S = [int(v) for v in S]
+    N = sum(S)
+    pm_cache, qd_cache = {}, {}
+
+    def subs(k):
+        out = []
+
+        def rec(j, left, cur):
+            if j == m:
+                if left == 0:
+                    out.append(tuple(cur))
+                return
+            for v in range(min(S[j], left) + 1):
+                rec(j + 1, left - v, cur + [v])
+
+        rec(0, k, [])
+        return out
+
+    total = 0.0
+    for w, main, dist in source_events(T, beta, g2, V):
+        nm = sum(main)
+        if nm + len(dist) != N:
+            continue
+        for Sp in subs(nm):
+            key = (main, Sp)
+            if key not in pm_cache:
+                pm_cache[key] = float(probabilities(U, np.asarray(main), np.asarray([Sp]))[0])
+            pm = pm_cache[key]
+            if pm == 0.0:
+                continue
+            R = tuple(s - sp for s, sp in zip(S, Sp))
+            dkey = (tuple(sorted(dist)), R)
+            if dkey not in qd_cache:
+                rows = [j for j in range(m) for _ in range(R[j])]
+                sub = Q[np.ix_(rows, list(dkey[0]))] if rows else np.zeros((0, 0), np.complex128)
+                fac = float(np.prod([math.factorial(r) for r in R]))
+                qd_cache[dkey] = perm(sub).real / fac
+            total += w * pm * qd_cache[dkey]
+    return total

@@ -568,3 +568,17 @@ def test_source_pair_photon_is_distinguishable():
     for s, p in zip(states.tolist(), probs):
         assert p == pytest.approx(p1 * p2 / 2, abs=1e-15), s
     assert d[2][1][np.all(d[2][0] == [1, 1], axis=1)][0] == pytest.approx(0.0, abs=1e-16)
+
+
+@pytest.mark.parametrize("m,T,prm", [(4, [1, 1, 0, 1], (0.8, 0.2, 0.6)), (3, [2, 1, 0], (0.7, 0.1, 0.3)),
+                                     (5, [1, 0, 1, 0, 0], (1.0, 0.5, 1.0))])
+def test_source_probability_matches_convolution(m, T, prm):
+    """Two independent routes to the mixture: per-event convolutions of the
+    groups' laws, and the per-output event sum with the distinguishable
+    photons' law as a permanent of |U|^2."""
+    U = inputs.haar_unitary(m, 25 + m)
+    n = sum(T)
+    d = oracle.source_distribution(U, T, *prm, 2 * n)
+    for states, probs in d:
+        for s, p in zip(states, probs):
+            assert oracle.source_probability(U, T, *prm, s) == pytest.approx(p, abs=1e-14, rel=1e-12)

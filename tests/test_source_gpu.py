@@ -139,3 +139,22 @@ def test_source_properties_m12_six_sources():
         assert mean == pytest.approx(want[j], abs=1e-12), j
     # the emission probabilities the library derived from (beta, g2)
     assert np.allclose(src.emission, (p0, p1, p2), atol=1e-15, rtol=1e-12)
+
+
+def test_source_sampled_outputs_m12_six_sources():
+    """The benchmark workload against the oracle's per-output event sum on
+    sampled outputs of every photon number class (vacuum, 3..9, 12)."""
+    m, T = 12, [1] * 6 + [0] * 6
+    prm = (0.9, 0.05, 0.92)
+    U = inputs.haar_unitary(m, 2)
+    src, P = _gpu(T, U, *prm)
+    parts = src.split(P)
+    picks = [np.zeros(m, np.int32)]
+    for N, cnt in ((3, 2), (5, 2), (6, 3), (7, 2), (9, 1), (12, 1)):
+        picks += list(inputs.uniform_fock_states(m, N, cnt, 60 + N))
+    print(f"[source] m=12 sampled outputs: {len(picks)}", flush=True)
+    for s in picks:
+        N = int(s.sum())
+        got = float(parts[N][slos.fock_rank(s)].item())
+        want = oracle.source_probability(U, T, *prm, s)
+        assert got == pytest.approx(want, abs=1e-16, rel=1e-11), (s.tolist(), got, want)
