@@ -4,9 +4,11 @@ Element by element (graded distribution over photon numbers 0..nmax, matched
 by occupation tuple) at sizes the oracle finishes in seconds, including a
 doubly occupied input mode, truncation below 2n, tiny leaves (many leaves and
 ragged tails) and the vacuum; the Ralph CNOT figures printed in Appendix A.4;
-and, at m = 12 with 6 sources, properties that hold at any size: the
-photon-number law is the product of the sources' laws and the mean occupation
-of output mode j is sum_s (p1 + 2 p2) |U[j, i_s]|^2, whatever U and V.
+and, at m = 12 with 6 sources (the benchmark workload), sampled outputs of
+every photon-number class against the oracle's per-output event sum, plus
+properties that hold at any size: the photon-number law is the product of the
+sources' laws and the mean occupation of output mode j is
+sum_s (p1 + 2 p2) |U[j, i_s]|^2, whatever U and V.
 """
 import json
 import math
