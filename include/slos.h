@@ -204,7 +204,7 @@ int slos_sample(slos_plan_t plan, const void *probs, const double *r, int64_t co
  * each target the recurrence of Section 3.2.3 runs over the states t <= S
  * alone, prod_j (s_j + 1) of them (2^n without bunching).  One workgroup per
  * target holds that sub-lattice in LDS, so prod_j (s_j + 1) must stay below
- * about 12K states (c64) or 7K (c128); larger targets are rejected.  U: device
+ * about 10K states (c64) or 6.7K (c128); larger targets are rejected.  U: device
  * m x m (plan dtype); out: device, count amplitudes (plan dtype), out[i] =
  * a(target i).  Synchronises the stream before returning (the target
  * descriptors are uploaded from host memory).

@@ -1250,7 +1250,7 @@ int slos_select(slos_plan_t p, const void *U, const int32_t *targets, int64_t co
     const int m = p->m, n = p->n;
     const size_t es = p->elem();
     // largest sub-lattice whose amplitudes, layers and masks fit a workgroup's LDS
-    const uint64_t r_cap = SLOS_LDS_DYNAMIC_MAX / (es + 5);
+    const uint64_t r_cap = SLOS_LDS_DYNAMIC_MAX / (es + 7);  // A, mask, sorted index, layer
     std::vector<SelectTarget> h;
     uint32_t r_max = 1;
     try {
