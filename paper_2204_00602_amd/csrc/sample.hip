@@ -32,47 +32,85 @@ constexpr int kChunks = SLOS_CDF_BLOCK / 64;
 typedef float cdf_f4 __attribute__((ext_vector_type(4)));
 typedef double cdf_d2 __attribute__((ext_vector_type(2)));
 
+// Block b is read in SLOS_CDF_BLOCK / 256 steps of 256 consecutive states: in
+// step i lane l holds states 256 i + 4 l .. 256 i + 4 l + 3 (one 16-byte load
+// for fp32, two for fp64), so each load of the wave covers one contiguous KiB
+// (fp32).  part[i] = the lane's sum of its four states of step i.
+constexpr int kSteps = SLOS_CDF_BLOCK / 256;
+
+template <typename T>
+__device__ __forceinline__ void lane_parts(const T *__restrict__ P, int64_t M, int64_t b, int lane, bool full,
+                                           double *part)
+{
+    const int64_t base = b * SLOS_CDF_BLOCK + 4 * (int64_t)lane;
+    if (full) {
+        if constexpr (sizeof(T) == 4) {
+            cdf_f4 v[kSteps];
+#pragma unroll
+            for (int i = 0; i < kSteps; ++i) v[i] = __builtin_nontemporal_load((const cdf_f4 *)(P + base + 256 * i));
+#pragma unroll
+            for (int i = 0; i < kSteps; ++i)
+                part[i] = ((double)v[i].x + (double)v[i].y) + ((double)v[i].z + (double)v[i].w);
+        } else {
+            cdf_d2 v[2 * kSteps];
+#pragma unroll
+            for (int i = 0; i < kSteps; ++i) {
+                v[2 * i] = __builtin_nontemporal_load((const cdf_d2 *)(P + base + 256 * i));
+                v[2 * i + 1] = __builtin_nontemporal_load((const cdf_d2 *)(P + base + 256 * i) + 1);
+            }
+#pragma unroll
+            for (int i = 0; i < kSteps; ++i)
+                part[i] = (v[2 * i].x + v[2 * i].y) + (v[2 * i + 1].x + v[2 * i + 1].y);
+        }
+    } else {
+        for (int i = 0; i < kSteps; ++i) {
+            double s = 0.0;
+            for (int e = 0; e < 4; ++e) {
+                const int64_t x = base + 256 * i + e;
+                if (x < M) s += (double)P[x];
+            }
+            part[i] = s;
+        }
+    }
+}
+
+// block sum bp[b] and the block's 16 chunk sums from the lanes' parts: chunk
+// 4 i + g (64 states) is step i of lanes 16 g .. 16 g + 15
+__device__ __forceinline__ void block_finish(const double *part, int64_t b, int lane, double *__restrict__ bp,
+                                             double *__restrict__ cs)
+{
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < kSteps; ++i) {
+        double c = part[i];
+#pragma unroll
+        for (int o = 1; o < 16; o <<= 1) c += __shfl_xor(c, o, 64);
+        if ((lane & 15) == 0) cs[b * kChunks + 4 * i + (lane >> 4)] = c;
+        s += part[i];
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if (lane == 0) bp[b] = s;
+}
+
+// One wave per pair of blocks (b, b + nw) per step: both blocks' loads are in
+// flight together.
 template <typename T>
 __global__ __launch_bounds__(256) void cdf_block_kernel(const T *__restrict__ P, int64_t M, int64_t nb,
                                                         double *__restrict__ bp, double *__restrict__ cs)
 {
+    static_assert(SLOS_CDF_BLOCK == 1024, "16 chunks of 64 states in 4 steps of 256");
     const int lane = threadIdx.x & 63;
     const int64_t gw = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
-    constexpr int per = SLOS_CDF_BLOCK / 64;  // states per lane, contiguous
-    for (int64_t b = gw; b < nb; b += nw) {
-        const int64_t base = b * SLOS_CDF_BLOCK;
-        double s = 0.0;
-        if (base + SLOS_CDF_BLOCK <= M) {
-            // whole block: 16-byte loads, all in flight, then a fixed-order sum
-            const T *q = P + base + (int64_t)lane * per;
-            if constexpr (sizeof(T) == 4) {
-                cdf_f4 v[per / 4];
-#pragma unroll
-                for (int i = 0; i < per / 4; ++i) v[i] = __builtin_nontemporal_load((const cdf_f4 *)q + i);
-#pragma unroll
-                for (int i = 0; i < per / 4; ++i)
-                    s += ((double)v[i].x + (double)v[i].y) + ((double)v[i].z + (double)v[i].w);
-            } else {
-                cdf_d2 v[per / 2];
-#pragma unroll
-                for (int i = 0; i < per / 2; ++i) v[i] = __builtin_nontemporal_load((const cdf_d2 *)q + i);
-#pragma unroll
-                for (int i = 0; i < per / 2; ++i) s += v[i].x + v[i].y;
-            }
-        } else {
-            for (int i = 0; i < per; ++i) {
-                const int64_t x = base + (int64_t)lane * per + i;
-                if (x < M) s += (double)P[x];
-            }
-        }
-        // chunk c (states 64c .. 64c + 63) is held by lanes 4c .. 4c + 3
-        double cc = s + __shfl_xor(s, 1, 64);
-        cc += __shfl_xor(cc, 2, 64);
-        if ((lane & 3) == 0) cs[b * kChunks + (lane >> 2)] = cc;
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-        if (lane == 0) bp[b] = s;
+    const int64_t nfull = M / SLOS_CDF_BLOCK;  // blocks without a tail
+    for (int64_t b0 = gw; b0 < nb; b0 += 2 * nw) {
+        const int64_t b1 = b0 + nw;
+        double p0[kSteps], p1[kSteps];
+        lane_parts(P, M, b0, lane, b0 < nfull, p0);
+        if (b1 < nb) lane_parts(P, M, b1, lane, b1 < nfull, p1);
+        block_finish(p0, b0, lane, bp, cs);
+        if (b1 < nb) block_finish(p1, b1, lane, bp, cs);
     }
 }
 
