@@ -472,7 +472,7 @@ def main():
         line["batched"] = time_batched(torch, slos, args.steps, args.warmup)
         print(f"[bench] batched: {line['batched']['ms_per_batch']:.3f} ms/batch", file=sys.stderr, flush=True)
         print("[bench] gradient workload: mesh m=12 n=6, 64 phase sets", file=sys.stderr, flush=True)
-        line["gradient"] = time_gradient(torch, slos, max(3, args.steps // 4), 1)
+        line["gradient"] = time_gradient(torch, slos, max(10, args.steps // 2), 2)
         print(f"[bench] gradient: {line['gradient']['ms_per_batch']:.3f} ms/batch", file=sys.stderr, flush=True)
         print("[bench] weak simulation: cumulative table, P(K), 2^20 samples", file=sys.stderr, flush=True)
         line["sampling"] = time_sampling(torch, slos, T, U, args.steps, args.warmup)
