@@ -280,11 +280,14 @@ typedef struct slos_batch_s *slos_batch_t;
  * B.6 evaluates many unitaries per loss).  Instance i has ms[i] modes and its
  * input occupations follow those of instance i-1 in `inputs` (sum of ms[i]
  * int32 in total), with at most 16 photons.  flags: SLOS_C64 or SLOS_C128.
- * opts: leaf_max (default 1024), block_threads, grid_blocks (workgroups,
- * default 1024), outputs_per_lane (default 2); other fields are ignored.
- * The whole batch runs in one kernel launch: each workgroup computes whole
- * instances, all layers, assigned on the host largest-first to the least
- * loaded workgroup, so no workgroup waits on another.
+ * opts: leaf_max (default 1024), block_threads (64 to 1024; the larger give
+ * the big instances more waves), grid_blocks (workgroups, default 1024),
+ * outputs_per_lane (default 2); other fields are ignored.
+ * The whole batch runs in one kernel launch.  An instance whose last layer has
+ * at least two tiles per wave runs on a whole workgroup (its waves share each
+ * layer, a barrier between layers); every other instance runs on a single
+ * wave.  The host assigns both kinds largest-first to the least loaded
+ * workgroup or wave, so no workgroup waits on another.
  */
 int slos_batch_plan(int count, const int32_t *ms, const int32_t *inputs, int flags, const slos_options_t *opts,
                     slos_batch_t *out);

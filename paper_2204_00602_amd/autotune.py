@@ -37,7 +37,7 @@ PLAN_SPACE: Dict[str, List[int]] = {
 BATCH_SPACE: Dict[str, List[int]] = {
     "leaf_max": [64, 128, 256, 512, 1024, 4096],
     "outputs_per_lane": [1, 2, 4],
-    "block_threads": [64, 128, 256],
+    "block_threads": [64, 128, 256, 512, 1024],
     "grid_blocks": [256, 512, 1024, 2048, 4096],
 }
 

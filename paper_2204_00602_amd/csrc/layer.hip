@@ -599,91 +599,139 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 3 : (RR <= 2 ? 4 : 1)) void l
 }
 
 // ---- batches ----------------------------------------------------------------------
-// One workgroup runs whole instances, layer after layer; its waves take the
-// layer's leaves in turn (each wave stages its leaf's low block in its own LDS
-// slice) and a barrier separates layers.  Layers live in two per-workgroup
-// scratch buffers; the last one goes straight to the packed output.  The host
-// assigns instances to workgroups (largest first, to the least loaded), so no
+// Phase 1: the workgroup runs its cooperative instances whole, layer after
+// layer; its waves take the layer's leaves in turn (each wave stages its leaf's
+// low block in its own LDS slice) and a barrier separates layers.  Phase 2:
+// each wave runs its own small instances alone, layer after layer, with its
+// own U column and scratch pair, ordering its layers with a fence instead of a
+// barrier.  Last layers go straight to the packed output.  The host assigns the
+// instances (largest first, to the least loaded workgroup or wave), so no
 // workgroup waits on another and the schedule is fixed.
 template <typename T, int RR>
-__global__ __launch_bounds__(256) void batch_kernel(BatchParams bp)
+__device__ __forceinline__ void batch_layer_leaves(const BatchParams &bp, const BatchInst &I, int k, const void *Xv,
+                                                   void *Yv, const typename Cx<T>::type *u, unsigned char *slice,
+                                                   uint32_t first, uint32_t step, int lane, double &psum)
+{
+    using C = typename Cx<T>::type;
+    const C *X = (const C *)Xv;
+    const int n = (int)I.n;
+    float bmax = 0.f;  // unused: batches are not compensated
+    LayerParams lp{};
+    lp.Y = Yv;
+    lp.pred = bp.pred;
+    lp.lowfac = bp.lowfac;
+    const uint32_t nl = I.nleaves[k - 1];
+    for (uint32_t li = first; li < nl; li += step) {
+        const DescRegs<false> d = load_desc<false>(bp.desc, (uint64_t)I.desc_off[k - 1] + li, lane);
+        const Leaf L = decode_head<false>(d);
+        const C *lowbuf = stage_low<C>(X, L, slice, lane);
+        __builtin_amdgcn_s_waitcnt(0);
+        __builtin_amdgcn_wave_barrier();
+        const uint32_t full = L.size / (64u * RR);
+        if (k == n) {
+            for (uint32_t t = 0; t < full; ++t)
+                tile<T, SLOS_MODE_AMPL, SLOS_COMP_NONE, RR, false>(lp, d, L, X, u, lowbuf, 0.f, t * 64u * RR, lane,
+                                                                  psum, bmax);
+            for (uint32_t t0 = full * 64u * RR; t0 < L.size; t0 += 64u)
+                tile<T, SLOS_MODE_AMPL, SLOS_COMP_NONE, 1, false>(lp, d, L, X, u, lowbuf, 0.f, t0, lane, psum, bmax);
+        } else {
+            for (uint32_t t = 0; t < full; ++t)
+                tile<T, SLOS_MODE_MID, SLOS_COMP_NONE, RR, false>(lp, d, L, X, u, lowbuf, 0.f, t * 64u * RR, lane,
+                                                                 psum, bmax);
+            for (uint32_t t0 = full * 64u * RR; t0 < L.size; t0 += 64u)
+                tile<T, SLOS_MODE_MID, SLOS_COMP_NONE, 1, false>(lp, d, L, X, u, lowbuf, 0.f, t0, lane, psum, bmax);
+        }
+        __builtin_amdgcn_s_waitcnt(0);
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+template <typename T, int RR, int MAXT>
+__global__ __launch_bounds__(MAXT) void batch_kernel(BatchParams bp)
 {
     using C = typename Cx<T>::type;
     __shared__ C u_lds[256];
-    __shared__ double wsum[4];
+    __shared__ double wsum[MAXT / 64];
     extern __shared__ unsigned char dyn_lds[];
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int W = blockDim.x >> 6;
     unsigned char *slice = dyn_lds + (size_t)wv * bp.lds_wave_bytes;
-    C *scr[2];
-    scr[0] = (C *)bp.scratch + (size_t)blockIdx.x * 2 * bp.scratch_stride;
-    scr[1] = scr[0] + bp.scratch_stride;
+    C *u_own = (C *)(dyn_lds + (size_t)W * bp.lds_wave_bytes) + (size_t)wv * 256;
     const C *Ub = (const C *)bp.U;
 
-    for (uint32_t e = bp.wg_start[blockIdx.x]; e < bp.wg_start[blockIdx.x + 1]; ++e) {
-        const uint32_t ii = bp.wg_list[e];
+    // phase 1: cooperative instances
+    {
+        C *scr[2];
+        scr[0] = (C *)bp.scratch + bp.wg_scr[blockIdx.x];
+        scr[1] = scr[0] + bp.scratch_stride;
+        for (uint32_t e = bp.wg_start[blockIdx.x]; e < bp.wg_start[blockIdx.x + 1]; ++e) {
+            const uint32_t ii = bp.wg_list[e];
+            const BatchInst &I = bp.inst[ii];
+            const int m = (int)I.m, n = (int)I.n;
+            double psum = 0.0;
+            for (int k = 1; k <= n; ++k) {
+                __syncthreads();  // layer k-1 is complete and every LDS slice is free
+                const int col = I.col[k - 1];
+                for (int j = threadIdx.x; j < 256; j += blockDim.x) {
+                    C v{0, 0};
+                    if (j < m) v = Ub[I.U_off + (size_t)j * m + col];
+                    u_lds[j] = v;
+                }
+                __syncthreads();
+                const void *X = k == 1 ? bp.vac : (const void *)scr[(k - 1) & 1];
+                void *Y = k == n ? (void *)((C *)bp.out + I.out_off) : (void *)scr[k & 1];
+                batch_layer_leaves<T, RR>(bp, I, k, X, Y, u_lds, slice, (uint32_t)wv, (uint32_t)W, lane, psum);
+            }
+            // sum P of the instance: per wave, then over waves in order
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) psum += __shfl_xor(psum, off, 64);
+            __syncthreads();
+            if (lane == 0) wsum[wv] = psum;
+            __syncthreads();
+            if (threadIdx.x == 0 && bp.sum_p) {
+                double s = 0.0;
+                for (int w = 0; w < W; ++w) s += wsum[w];
+                bp.sum_p[ii] = s;
+            }
+        }
+    }
+
+    // phase 2: this wave's own instances
+    const uint32_t slot = blockIdx.x * (uint32_t)W + (uint32_t)wv;
+    C *my[2];
+    my[0] = (C *)bp.scratch + bp.small_base + (uint64_t)slot * 2 * bp.small_stride;
+    my[1] = my[0] + bp.small_stride;
+    for (uint32_t e = bp.wv_start[slot]; e < bp.wv_start[slot + 1]; ++e) {
+        const uint32_t ii = bp.wv_list[e];
         const BatchInst &I = bp.inst[ii];
         const int m = (int)I.m, n = (int)I.n;
         double psum = 0.0;
-        float bmax = 0.f;  // unused: batches are not compensated
-        if (n == 0 && threadIdx.x == 0) {
+        if (n == 0 && lane == 0) {
             // no photons: the single output is the vacuum, amplitude 1
             ((C *)bp.out)[I.out_off] = C{(T)1, (T)0};
             psum = 1.0;
         }
         for (int k = 1; k <= n; ++k) {
-            __syncthreads();  // layer k-1 is complete and every LDS slice is free
             const int col = I.col[k - 1];
-            for (int j = threadIdx.x; j < 256; j += blockDim.x) {
+            for (int j = lane; j < 256; j += 64) {
                 C v{0, 0};
                 if (j < m) v = Ub[I.U_off + (size_t)j * m + col];
-                u_lds[j] = v;
+                u_own[j] = v;
             }
-            __syncthreads();
-            const C *X = k == 1 ? (const C *)bp.vac : scr[(k - 1) & 1];
-            LayerParams lp{};
-            lp.Y = k == n ? (void *)((C *)bp.out + I.out_off) : (void *)scr[k & 1];
-            lp.pred = bp.pred;
-            lp.lowfac = bp.lowfac;
-            const uint32_t nl = I.nleaves[k - 1];
-            for (uint32_t li = (uint32_t)wv; li < nl; li += (uint32_t)W) {
-                const DescRegs<false> d = load_desc<false>(bp.desc, (uint64_t)I.desc_off[k - 1] + li, lane);
-                const Leaf L = decode_head<false>(d);
-                const C *lowbuf = stage_low<C>(X, L, slice, lane);
-                __builtin_amdgcn_s_waitcnt(0);
-                __builtin_amdgcn_wave_barrier();
-                const uint32_t full = L.size / (64u * RR);
-                if (k == n) {
-                    for (uint32_t t = 0; t < full; ++t)
-                        tile<T, SLOS_MODE_AMPL, SLOS_COMP_NONE, RR, false>(lp, d, L, X, u_lds, lowbuf, 0.f,
-                                                                          t * 64u * RR, lane, psum, bmax);
-                    for (uint32_t t0 = full * 64u * RR; t0 < L.size; t0 += 64u)
-                        tile<T, SLOS_MODE_AMPL, SLOS_COMP_NONE, 1, false>(lp, d, L, X, u_lds, lowbuf, 0.f, t0,
-                                                                         lane, psum, bmax);
-                } else {
-                    for (uint32_t t = 0; t < full; ++t)
-                        tile<T, SLOS_MODE_MID, SLOS_COMP_NONE, RR, false>(lp, d, L, X, u_lds, lowbuf, 0.f,
-                                                                         t * 64u * RR, lane, psum, bmax);
-                    for (uint32_t t0 = full * 64u * RR; t0 < L.size; t0 += 64u)
-                        tile<T, SLOS_MODE_MID, SLOS_COMP_NONE, 1, false>(lp, d, L, X, u_lds, lowbuf, 0.f, t0,
-                                                                        lane, psum, bmax);
-                }
-                __builtin_amdgcn_s_waitcnt(0);
-                __builtin_amdgcn_wave_barrier();
-            }
+            __builtin_amdgcn_s_waitcnt(0);
+            __builtin_amdgcn_wave_barrier();
+            const void *X = k == 1 ? bp.vac : (const void *)my[(k - 1) & 1];
+            void *Y = k == n ? (void *)((C *)bp.out + I.out_off) : (void *)my[k & 1];
+            batch_layer_leaves<T, RR>(bp, I, k, X, Y, u_own, slice, 0u, 1u, lane, psum);
+            // layer k's stores (all lanes) are seen by every lane's loads of layer k + 1
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
         }
-        // sum P of the instance: per wave, then over waves in order
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) psum += __shfl_xor(psum, off, 64);
-        __syncthreads();
-        if (lane == 0) wsum[wv] = psum;
-        __syncthreads();
-        if (threadIdx.x == 0 && bp.sum_p) {
-            double s = 0.0;
-            for (int w = 0; w < W; ++w) s += wsum[w];
-            bp.sum_p[ii] = s;
-        }
+        if (lane == 0 && bp.sum_p) bp.sum_p[ii] = psum;
     }
 }
 
@@ -829,36 +877,53 @@ int slos_launch_zero_u32(uint32_t *buf, int count, void *stream)
     return (int)hipGetLastError();
 }
 
-template <typename T, int RR>
+template <typename T, int RR, int MAXT>
 static hipError_t batch_attr()
 {
-    return hipFuncSetAttribute((const void *)batch_kernel<T, RR>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)SLOS_LDS_DYNAMIC_MAX);
+    return hipFuncSetAttribute((const void *)batch_kernel<T, RR, MAXT>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)SLOS_LDS_DYNAMIC_MAX);
+}
+
+template <int MAXT>
+static hipError_t batch_attrs()
+{
+    hipError_t e;
+    if ((e = batch_attr<float, 1, MAXT>()) || (e = batch_attr<float, 2, MAXT>()) ||
+        (e = batch_attr<float, 4, MAXT>()) || (e = batch_attr<double, 1, MAXT>()) ||
+        (e = batch_attr<double, 2, MAXT>()) || (e = batch_attr<double, 4, MAXT>()))
+        return e;
+    return hipSuccess;
 }
 
 int slos_prepare_batch_kernels(void)
 {
     hipError_t e;
-    if ((e = batch_attr<float, 1>()) || (e = batch_attr<float, 2>()) || (e = batch_attr<float, 4>()) ||
-        (e = batch_attr<double, 1>()) || (e = batch_attr<double, 2>()) || (e = batch_attr<double, 4>()))
-        return (int)e;
+    if ((e = batch_attrs<256>()) || (e = batch_attrs<1024>())) return (int)e;
     return 0;
 }
 
+template <int MAXT>
+static void launch_batch(const BatchParams &p, int c64, int rr, dim3 g, dim3 b, size_t lds, hipStream_t s)
+{
+    if (c64) {
+        if (rr == 1) hipLaunchKernelGGL((batch_kernel<float, 1, MAXT>), g, b, lds, s, p);
+        else if (rr == 2) hipLaunchKernelGGL((batch_kernel<float, 2, MAXT>), g, b, lds, s, p);
+        else hipLaunchKernelGGL((batch_kernel<float, 4, MAXT>), g, b, lds, s, p);
+    } else {
+        if (rr == 1) hipLaunchKernelGGL((batch_kernel<double, 1, MAXT>), g, b, lds, s, p);
+        else if (rr == 2) hipLaunchKernelGGL((batch_kernel<double, 2, MAXT>), g, b, lds, s, p);
+        else hipLaunchKernelGGL((batch_kernel<double, 4, MAXT>), g, b, lds, s, p);
+    }
+}
+
+// Workgroups of up to 256 threads keep the 256-thread register budget; 512 and
+// 1024 (more waves on the cooperative instances) take the 1024-thread one.
 int slos_launch_batch(const BatchParams &p, int c64, int rr, int threads, int grid, void *stream)
 {
-    const size_t lds = (size_t)p.lds_wave_bytes * (size_t)(threads / 64);
-    hipStream_t s = (hipStream_t)stream;
-    dim3 g(grid), b(threads);
-    if (c64) {
-        if (rr == 1) hipLaunchKernelGGL((batch_kernel<float, 1>), g, b, lds, s, p);
-        else if (rr == 2) hipLaunchKernelGGL((batch_kernel<float, 2>), g, b, lds, s, p);
-        else hipLaunchKernelGGL((batch_kernel<float, 4>), g, b, lds, s, p);
-    } else {
-        if (rr == 1) hipLaunchKernelGGL((batch_kernel<double, 1>), g, b, lds, s, p);
-        else if (rr == 2) hipLaunchKernelGGL((batch_kernel<double, 2>), g, b, lds, s, p);
-        else hipLaunchKernelGGL((batch_kernel<double, 4>), g, b, lds, s, p);
-    }
+    const size_t lds = ((size_t)p.lds_wave_bytes + 256 * (c64 ? 8 : 16)) * (size_t)(threads / 64);
+    const hipStream_t s = (hipStream_t)stream;
+    if (threads <= 256) launch_batch<256>(p, c64, rr, dim3(grid), dim3(threads), lds, s);
+    else launch_batch<1024>(p, c64, rr, dim3(grid), dim3(threads), lds, s);
     return (int)hipGetLastError();
 }
 

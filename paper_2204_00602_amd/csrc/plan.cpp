@@ -14,6 +14,7 @@
 #include <cstring>
 #include <map>
 #include <new>
+#include <queue>
 #include <string>
 #include <vector>
 
@@ -1339,13 +1340,19 @@ struct slos_batch_s {
     std::vector<BatchInst> inst;
     std::vector<int64_t> out_off, u_off; // count + 1 each
     std::vector<LeafDescNarrow> desc;
-    std::vector<uint32_t> wg_start, wg_list;
-    uint64_t scratch_stride = 0;         // elements per scratch buffer
+    std::vector<uint32_t> wg_start, wg_list;   // cooperative instances per workgroup
+    std::vector<uint32_t> wv_start, wv_list;   // small instances per wave slot
+    std::vector<uint64_t> wg_scr;              // per workgroup: its cooperative scratch pair
+    uint64_t scratch_stride = 0;         // elements per cooperative scratch buffer
+    uint64_t small_base = 0, small_stride = 0;
+    uint64_t scratch_elems = 0;
     uint32_t lds_wave_bytes = 0;
     int grid = 0;
     // device
     BatchInst *d_inst = nullptr;
     uint32_t *d_wg_start = nullptr, *d_wg_list = nullptr;
+    uint32_t *d_wv_start = nullptr, *d_wv_list = nullptr;
+    uint64_t *d_wg_scr = nullptr;
     LeafDescNarrow *d_desc = nullptr;
     uint32_t *d_pred = nullptr;
     double *d_lowfac = nullptr;
@@ -1361,6 +1368,9 @@ struct slos_batch_s {
         f(d_inst);
         f(d_wg_start);
         f(d_wg_list);
+        f(d_wv_start);
+        f(d_wv_list);
+        f(d_wg_scr);
         f(d_desc);
         f(d_pred);
         f(d_lowfac);
@@ -1369,6 +1379,8 @@ struct slos_batch_s {
         if (exec) (void)hipGraphExecDestroy(exec);
         d_inst = nullptr;
         d_wg_start = d_wg_list = nullptr;
+        d_wv_start = d_wv_list = nullptr;
+        d_wg_scr = nullptr;
         d_desc = nullptr;
         d_pred = nullptr;
         d_lowfac = nullptr;
@@ -1385,6 +1397,11 @@ struct slos_batch_s {
         bp.inst = d_inst;
         bp.wg_start = d_wg_start;
         bp.wg_list = d_wg_list;
+        bp.wv_start = d_wv_start;
+        bp.wv_list = d_wv_list;
+        bp.wg_scr = d_wg_scr;
+        bp.small_base = small_base;
+        bp.small_stride = small_stride;
         bp.desc = d_desc;
         bp.pred = d_pred;
         bp.lowfac = d_lowfac;
@@ -1415,8 +1432,9 @@ int slos_batch_plan(int count, const int32_t *ms, const int32_t *inputs, int fla
     if (o.block_threads == 0) o.block_threads = 256;
     if (o.grid_blocks == 0) o.grid_blocks = 1024;
     if (o.outputs_per_lane == 0) o.outputs_per_lane = 2;
-    if (o.leaf_max < 1 || o.leaf_max > 65536 || (o.block_threads != 64 && o.block_threads != 128 &&
-                                                 o.block_threads != 256) ||
+    if (o.leaf_max < 1 || o.leaf_max > 65536 ||
+        (o.block_threads != 64 && o.block_threads != 128 && o.block_threads != 256 && o.block_threads != 512 &&
+         o.block_threads != 1024) ||
         o.grid_blocks < 1 || o.grid_blocks > (1 << 20) ||
         (o.outputs_per_lane != 1 && o.outputs_per_lane != 2 && o.outputs_per_lane != 4))
         return fail(SLOS_ERR_INVALID_ARG, "invalid batch options");
@@ -1453,8 +1471,8 @@ int slos_batch_plan(int count, const int32_t *ms, const int32_t *inputs, int fla
         b->out_off.assign(count + 1, 0);
         b->u_off.assign(count + 1, 0);
         uint32_t low_max = 0;
-        uint64_t scratch = 1;
         std::vector<double> cost(count);
+        std::vector<uint64_t> inter(count, 0), last(count, 1);  // largest layer below n, layer n
         pos = 0;
         for (int i = 0; i < count; ++i) {
             const int m = ms[i];
@@ -1499,23 +1517,49 @@ int slos_batch_plan(int count, const int32_t *ms, const int32_t *inputs, int fla
                     low_max = std::max(low_max, h.low_size);
                 }
                 const uint64_t Nk = P.B(m + k - 1, k);
-                if (k < n) scratch = std::max(scratch, Nk);
+                if (k < n) inter[i] = std::max(inter[i], Nk);
+                else last[i] = Nk;
                 c += (double)(P.B(m + k - 2, k - 1) + Nk);
             }
             cost[i] = c + 64.0 * n;
             pos += m;
         }
-        // largest instance first, each to the least loaded workgroup
+        // Instances whose last layer has at least two tiles per wave run
+        // cooperatively on a workgroup; the rest run on single waves.  Both
+        // lists are filled largest first, each instance to the least loaded
+        // workgroup (load in wave time: cost / W) or wave slot (whose load
+        // starts at its workgroup's cooperative load).
         const int G = std::min(o.grid_blocks, count);
+        const int W = o.block_threads / 64;
+        const uint64_t coop_min = 2ull * (uint64_t)W * 64u * (uint64_t)o.outputs_per_lane;
         std::vector<int> order(count);
         for (int i = 0; i < count; ++i) order[i] = i;
         std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
         std::vector<double> load(G, 0.0);
-        std::vector<std::vector<uint32_t>> lists(G);
+        std::vector<std::vector<uint32_t>> lists(G), wlists((size_t)G * W);
+        uint64_t coop_inter = 0, small_inter = 0;
+        typedef std::pair<double, uint32_t> Slot;
+        std::vector<int> small;
         for (int i : order) {
-            int g = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-            load[g] += cost[i];
-            lists[g].push_back((uint32_t)i);
+            if (W > 1 && last[i] >= coop_min) {
+                int g = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+                load[g] += cost[i] / W;
+                lists[g].push_back((uint32_t)i);
+                coop_inter = std::max(coop_inter, inter[i]);
+            } else {
+                small.push_back(i);
+                small_inter = std::max(small_inter, inter[i]);
+            }
+        }
+        std::priority_queue<Slot, std::vector<Slot>, std::greater<Slot>> heap;
+        for (int g = 0; g < G; ++g)
+            for (int w = 0; w < W; ++w) heap.push(Slot(load[g], (uint32_t)(g * W + w)));
+        for (int i : small) {
+            Slot sl = heap.top();
+            heap.pop();
+            wlists[sl.second].push_back((uint32_t)i);
+            sl.first += cost[i];
+            heap.push(sl);
         }
         b->grid = G;
         b->wg_start.assign(G + 1, 0);
@@ -1523,9 +1567,27 @@ int slos_batch_plan(int count, const int32_t *ms, const int32_t *inputs, int fla
             b->wg_start[g + 1] = b->wg_start[g] + (uint32_t)lists[g].size();
             b->wg_list.insert(b->wg_list.end(), lists[g].begin(), lists[g].end());
         }
-        b->scratch_stride = scratch + (SLOS_BUFFER_SLACK + es - 1) / es;
+        b->wv_start.assign((size_t)G * W + 1, 0);
+        for (size_t sl = 0; sl < (size_t)G * W; ++sl) {
+            b->wv_start[sl + 1] = b->wv_start[sl] + (uint32_t)wlists[sl].size();
+            b->wv_list.insert(b->wv_list.end(), wlists[sl].begin(), wlists[sl].end());
+        }
+        // scratch: a cooperative pair for each workgroup that has cooperative
+        // instances, then a small pair for every wave slot
+        const uint64_t slack = (SLOS_BUFFER_SLACK + es - 1) / es;
+        b->scratch_stride = std::max<uint64_t>(coop_inter, 1) + slack;
+        b->small_stride = std::max<uint64_t>(small_inter, 1) + slack;
+        b->wg_scr.assign(G, 0);
+        uint64_t pos_scr = 0;
+        for (int g = 0; g < G; ++g)
+            if (!lists[g].empty()) {
+                b->wg_scr[g] = pos_scr;
+                pos_scr += 2 * b->scratch_stride;
+            }
+        b->small_base = pos_scr;
+        b->scratch_elems = pos_scr + (uint64_t)G * W * 2 * b->small_stride;
         b->lds_wave_bytes = slos_lds_wave_bytes(low_max, (uint32_t)es);
-        if (b->lds_wave_bytes * (uint32_t)(o.block_threads / 64) > SLOS_LDS_DYNAMIC_MAX)
+        if ((b->lds_wave_bytes + 256 * es) * (size_t)W > SLOS_LDS_DYNAMIC_MAX)
             throw std::pair<int, std::string>(SLOS_ERR_INVALID_ARG, "leaf_max too large for the LDS of a workgroup");
         if (P.pred.size() >= (size_t(1) << 32) || b->desc.size() >= (size_t(1) << 32))
             throw std::pair<int, std::string>(SLOS_ERR_SIZE_OVERFLOW, "batch tables too large");
@@ -1549,11 +1611,13 @@ int slos_batch_plan(int count, const int32_t *ms, const int32_t *inputs, int fla
     if ((rc = dev_upload(&b->d_inst, b->inst.data(), b->inst.size(), "batch instances")) ||
         (rc = dev_upload(&b->d_wg_start, b->wg_start.data(), b->wg_start.size(), "batch schedule")) ||
         (rc = dev_upload(&b->d_wg_list, b->wg_list.data(), b->wg_list.size(), "batch schedule")) ||
+        (rc = dev_upload(&b->d_wv_start, b->wv_start.data(), b->wv_start.size(), "batch schedule")) ||
+        (rc = dev_upload(&b->d_wv_list, b->wv_list.data(), b->wv_list.size(), "batch schedule")) ||
+        (rc = dev_upload(&b->d_wg_scr, b->wg_scr.data(), b->wg_scr.size(), "batch schedule")) ||
         (rc = dev_upload(&b->d_desc, b->desc.data(), b->desc.size(), "batch descriptors")) ||
         (rc = dev_upload(&b->d_pred, b->builder.pred.data(), b->builder.pred.size(), "batch inner tables")) ||
         (rc = dev_upload(&b->d_lowfac, b->builder.lowfac.data(), b->builder.lowfac.size(), "batch factorials")) ||
-        (rc = alloc_dev(&b->d_scratch, (size_t)b->grid * 2 * b->scratch_stride * es + SLOS_BUFFER_SLACK,
-                        "batch scratch")) ||
+        (rc = alloc_dev(&b->d_scratch, (size_t)b->scratch_elems * es + SLOS_BUFFER_SLACK, "batch scratch")) ||
         (rc = alloc_dev(&b->d_vac, es + SLOS_BUFFER_SLACK, "vacuum layer"))) {
         b->free_device();
         delete b;

@@ -245,20 +245,29 @@ struct BatchInst {
     uint8_t col[SLOS_BATCH_MAX_N];
 };
 
+// Two kinds of work per workgroup: instances large enough to occupy all its
+// waves run cooperatively (all waves, a barrier between layers), first; then
+// each wave runs its own list of small instances alone (wave-level ordering
+// between layers), so no wave idles at a barrier on a one-leaf layer.
 struct BatchParams {
     const void *U;              // packed U matrices
     void *out;                  // packed amplitudes
     double *sum_p;              // per instance, or NULL
     const BatchInst *inst;
-    const uint32_t *wg_start;   // workgroup g runs wg_list[wg_start[g] .. wg_start[g+1])
+    const uint32_t *wg_start;   // workgroup g runs wg_list[wg_start[g] .. wg_start[g+1]) cooperatively
     const uint32_t *wg_list;
+    const uint32_t *wv_start;   // then wave w of g runs wv_list[wv_start[s] .. wv_start[s+1]), s = g W + w
+    const uint32_t *wv_list;
     const LeafDescNarrow *desc;
     const uint32_t *pred;
     const double *lowfac;
-    void *scratch;              // two layer buffers per workgroup
-    uint64_t scratch_stride;    // elements per buffer, slack included
+    void *scratch;              // layer buffers (elements of the plan's type)
+    const uint64_t *wg_scr;     // per workgroup: its cooperative pair of scratch_stride buffers
+    uint64_t scratch_stride;    // elements per cooperative buffer, slack included
+    uint64_t small_base;        // wave slot s: pair of small_stride buffers at small_base + 2 s small_stride
+    uint64_t small_stride;
     const void *vac;            // A_0 = [1]
-    uint32_t lds_wave_bytes;
+    uint32_t lds_wave_bytes;    // low-block slice per wave; a 256-entry U column per wave follows the slices
 };
 
 int slos_launch_batch(const BatchParams &p, int c64, int rr, int threads, int grid, void *stream);

@@ -47,7 +47,9 @@ def check_instance(batch, out, i, T, U, dtype, sample=None):
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 @pytest.mark.parametrize("opts", [None, {"leaf_max": 16, "outputs_per_lane": 1, "block_threads": 64, "grid_blocks": 5},
-                                  {"leaf_max": 300, "outputs_per_lane": 4, "block_threads": 128}])
+                                  {"leaf_max": 300, "outputs_per_lane": 4, "block_threads": 128},
+                                  {"leaf_max": 256, "outputs_per_lane": 2, "block_threads": 1024, "grid_blocks": 37},
+                                  {"leaf_max": 64, "outputs_per_lane": 1, "block_threads": 512, "grid_blocks": 3}])
 def test_batch_matches_oracle(dtype, opts):
     inst = inputs.batch_instances(40, seed=4) + edge_instances()
     b = slos.Batch([t for (_, _, t, _) in inst], dtype, options=opts)
