@@ -42,7 +42,7 @@ def layer_sizes(m, n):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("layer.hip", "slos_internal.h"):
+    for f in ("layer.hip", "slos_internal.h", "plan.cpp"):  # the kernel and the leaf order it is given
         with open(os.path.join(ROOT, "paper_2204_00602_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -87,13 +87,19 @@ typedef struct slos_options {
     int32_t xcd_chunk;       /* consecutive leaves dealt to one XCD at a time
                                 (default 128; fewer when a layer has few leaves)    */
     int32_t ticket_leaves;   /* consecutive leaves a workgroup takes per work ticket
-                                (default 4)                                          */
+                                (default 2)                                          */
     int32_t max_batch;       /* unitaries per *_many call, 1..65535 (default 1): the
                                 plan holds layer buffers for that many instances   */
     int32_t wide_descriptors;/* 1: use the 32-group, 64-bit-delta leaf descriptors on
                                 every layer; 0 (default): only where a leaf needs
                                 them (more than 16 occupied high modes, or a layer
                                 of 2^32 states or more)                             */
+    int32_t leaf_order;      /* order in which a layer's leaves are processed:
+                                d = 1..4 groups the leaves whose high parts agree
+                                once their d highest photons are removed (they
+                                share predecessor blocks, which then stay in cache
+                                while the group runs); 0: d = 1 (default); -1:
+                                colex order                                      */
 } slos_options_t;
 
 /* ---- Fock-space arithmetic (host only; no device needed) ------------------ */

@@ -130,6 +130,26 @@ void colex_unrank(const Binom &B, int m, int k, uint64_t rank, int32_t *occ)
     }
 }
 
+// Process order of a layer's leaves: group the leaves of one inner shape (q, K)
+// whose high parts agree once their d highest photons (hm[0..d), the modes are
+// descending) are removed, so that a group's shared predecessor blocks are read
+// while they are still in cache; colex order puts such leaves far apart (the
+// top photon is the most significant).  Groups in lexicographic order of the
+// remaining photons, leaves within a group by their top photons.
+void order_leaves(std::vector<LeafRec> &lv, int d)
+{
+    std::stable_sort(lv.begin(), lv.end(), [d](const LeafRec &a, const LeafRec &b) {
+        if (a.q != b.q) return a.q < b.q;
+        if (a.K != b.K) return a.K < b.K;
+        const int n = a.nhp;  // equal: the same layer and K
+        for (int i = d; i < n; ++i)
+            if (a.hm[i] != b.hm[i]) return a.hm[i] < b.hm[i];
+        for (int i = 0; i < std::min(d, n); ++i)
+            if (a.hm[i] != b.hm[i]) return a.hm[i] < b.hm[i];
+        return a.out_base < b.out_base;
+    });
+}
+
 } // namespace
 
 struct slos_plan_s {
@@ -549,10 +569,12 @@ int slos_plan_ex(int m, int n, const int32_t *input_state, int flags, const slos
     if (o.grid_blocks == 0) o.grid_blocks = 2048;
     if (o.outputs_per_lane == 0) o.outputs_per_lane = dt == SLOS_C64 ? 4 : 2;
     if (o.xcd_chunk == 0) o.xcd_chunk = 128;
-    if (o.ticket_leaves == 0) o.ticket_leaves = 4;
+    if (o.ticket_leaves == 0) o.ticket_leaves = 2;
     if (o.max_batch == 0) o.max_batch = 1;
     if (o.wide_descriptors < 0 || o.wide_descriptors > 1)
         return fail(SLOS_ERR_INVALID_ARG, "wide_descriptors must be 0 or 1");
+    if (o.leaf_order < -1 || o.leaf_order > 4)
+        return fail(SLOS_ERR_INVALID_ARG, "leaf_order = %d outside [-1, 4]", o.leaf_order);
     if (o.max_batch < 1 || o.max_batch > 65535)
         return fail(SLOS_ERR_INVALID_ARG, "max_batch = %d outside [1, 65535]", o.max_batch);
     if (o.ticket_leaves < 1 || o.ticket_leaves > 4096)
@@ -609,6 +631,9 @@ int slos_plan_ex(int m, int n, const int32_t *input_state, int flags, const slos
             p->gen_leaves(k, m - 1, k, cap, hm, p->leaves[k]);
             for (const LeafRec &L : p->leaves[k])
                 p->low_max[k] = std::max(p->low_max[k], p->types[L.tab].low_size);
+            // grouped order by default (depth 1: leaves that share the block
+            // reached by removing their top photon run together)
+            if (o.leaf_order >= 0) order_leaves(p->leaves[k], o.leaf_order > 0 ? o.leaf_order : 1);
         }
         if (p->keep) {
             p->units.resize(n + 1);

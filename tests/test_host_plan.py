@@ -82,15 +82,15 @@ def test_rank_rejects_bad_states():
     (9, [2, 0, 1, 0, 0, 2, 0, 0, 1], 17), (3, [4, 0, 2], 1), (14, [1, 2, 0, 1, 0, 0, 2, 0, 1, 0, 0, 0, 0, 0], 256),
     (20, [1] * 5 + [0] * 15, 128),
 ])
-def test_leaf_tiling_covers_each_layer_once(m, T, leaf_max):
-    p = slos.Plan(T, "c64", host_only=True, options={"leaf_max": leaf_max})
+@pytest.mark.parametrize("order", [0, 2])
+def test_leaf_tiling_covers_each_layer_once(m, T, leaf_max, order):
+    p = slos.Plan(T, "c64", host_only=True, options={"leaf_max": leaf_max, "leaf_order": order})
     n = int(sum(T))
     for k in range(1, n + 1):
         Nk, nl = p.layer_info(k)
         assert Nk == math.comb(m + k - 1, k)
         nxt = 0
-        for idx in range(nl):
-            base, q, K, hm = p.leaf(k, idx)
+        for base, q, K, hm in sorted(p.leaf(k, idx) for idx in range(nl)):
             size = math.comb(q + K - 1, K)
             assert base == nxt, (k, idx)
             assert size <= leaf_max or K == 0 or q == 1 or (q == m and size == Nk)
