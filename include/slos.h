@@ -75,8 +75,8 @@ typedef struct slos_plan_s *slos_plan_t;
 
 /* Tuning options; a zero field takes its default. */
 typedef struct slos_options {
-    int32_t leaf_max;        /* max states per leaf tile, <= 65536 (default 8192 for
-                                c64, 4096 for c128, 1024 with SLOS_KEEP_LAYERS); a
+    int32_t leaf_max;        /* max states per leaf tile, <= 65536 (default 16384 for
+                                c64, 8192 for c128, 1024 with SLOS_KEEP_LAYERS); a
                                 small layer uses smaller leaves so that it still
                                 spreads over ~2048 workgroups                        */
     int32_t comp_from_layer; /* first compensated layer (default 1: every layer)     */
@@ -100,6 +100,11 @@ typedef struct slos_options {
                                 share predecessor blocks, which then stay in cache
                                 while the group runs); 0: d = 1 (default); -1:
                                 colex order                                      */
+    int32_t low_block_max;   /* largest low block a leaf may stage in LDS (states);
+                                leaves with larger ones are split further, so a
+                                workgroup needs less LDS and more of them fit on
+                                a CU.  0: default (40 KiB: 5120 for c64, 2560 for
+                                c128; no limit with SLOS_KEEP_LAYERS); -1: none */
 } slos_options_t;
 
 /* ---- Fock-space arithmetic (host only; no device needed) ------------------ */

@@ -26,7 +26,8 @@ import numpy as np
 from . import inputs, slos
 
 PLAN_SPACE: Dict[str, List[int]] = {
-    "leaf_max": [1024, 2048, 4096, 8192, 16384],
+    "leaf_max": [2048, 4096, 8192, 16384, 32768],
+    "low_block_max": [2048, 3072, 4096, 5120, 6144],
     "outputs_per_lane": [1, 2, 4],
     "block_threads": [64, 128, 256],
     "grid_blocks": [1024, 2048, 4096, 8192],
@@ -42,7 +43,7 @@ BATCH_SPACE: Dict[str, List[int]] = {
 }
 
 # the library defaults the search starts from (0 = library default)
-PLAN_START = {"leaf_max": 0, "outputs_per_lane": 0, "block_threads": 0, "grid_blocks": 0,
+PLAN_START = {"leaf_max": 0, "low_block_max": 0, "outputs_per_lane": 0, "block_threads": 0, "grid_blocks": 0,
               "ticket_leaves": 0, "xcd_chunk": 0}
 BATCH_START = {"leaf_max": 0, "outputs_per_lane": 0, "block_threads": 0, "grid_blocks": 0}
 

@@ -266,10 +266,13 @@ struct slos_plan_s {
 
     // Leaves of layer k: split F(j+1, K) by the occupation of mode j (blocks
     // t_j = 0, 1, .., K in colex order) until a block holds <= cap states.
+    uint64_t low_cap = ~uint64_t(0);   // largest low block a leaf may have (elements)
+
     void gen_leaves(int k, int j, int K, uint64_t cap, std::vector<uint8_t> &hm, std::vector<LeafRec> &out)
     {
         uint64_t size = B(j + K, K);
-        if (K == 0 || j == 0 || size <= cap) {
+        const uint64_t low = K > 0 ? B(j + K - 1, K - 1) : 0;
+        if (K == 0 || j == 0 || (size <= cap && low <= low_cap)) {
             LeafRec L{};
             L.q = (uint8_t)(j + 1);
             L.K = (uint8_t)K;
@@ -563,7 +566,10 @@ int slos_plan_ex(int m, int n, const int32_t *input_state, int flags, const slos
     // defaults: the fastest settings of a coordinate-descent search at
     // m=24, n=12 on gfx950 (a c128 low block of an 8192-state leaf takes
     // enough LDS to halve the resident workgroups, hence the smaller leaves)
-    if (o.leaf_max == 0) o.leaf_max = (flags & SLOS_KEEP_LAYERS) ? 1024 : (dt == SLOS_C64 ? 8192 : 4096);
+    if (o.leaf_max == 0) o.leaf_max = (flags & SLOS_KEEP_LAYERS) ? 1024 : (dt == SLOS_C64 ? 16384 : 8192);
+    // low blocks of at most 40 KiB: three workgroups' staging fits a CU's LDS,
+    // and the few leaves with larger low blocks are split further
+    if (o.low_block_max == 0) o.low_block_max = (flags & SLOS_KEEP_LAYERS) ? -1 : (dt == SLOS_C64 ? 5120 : 2560);
     if (o.comp_from_layer == 0) o.comp_from_layer = 1;
     if (o.block_threads == 0) o.block_threads = 256;
     if (o.grid_blocks == 0) o.grid_blocks = 2048;
@@ -575,6 +581,8 @@ int slos_plan_ex(int m, int n, const int32_t *input_state, int flags, const slos
         return fail(SLOS_ERR_INVALID_ARG, "wide_descriptors must be 0 or 1");
     if (o.leaf_order < -1 || o.leaf_order > 4)
         return fail(SLOS_ERR_INVALID_ARG, "leaf_order = %d outside [-1, 4]", o.leaf_order);
+    if (o.low_block_max < -1)
+        return fail(SLOS_ERR_INVALID_ARG, "low_block_max = %d is below -1", o.low_block_max);
     if (o.max_batch < 1 || o.max_batch > 65535)
         return fail(SLOS_ERR_INVALID_ARG, "max_batch = %d outside [1, 65535]", o.max_batch);
     if (o.ticket_leaves < 1 || o.ticket_leaves > 4096)
@@ -604,6 +612,7 @@ int slos_plan_ex(int m, int n, const int32_t *input_state, int flags, const slos
     p->opts = o;
     p->batch_cap = o.max_batch;
 
+    if (o.low_block_max > 0) p->low_cap = (uint64_t)o.low_block_max;
     try {
         double tf = 1.0;
         for (int i = 0; i < m; ++i) {

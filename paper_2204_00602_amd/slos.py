@@ -42,7 +42,8 @@ class Options(ctypes.Structure):
                 ("block_threads", ctypes.c_int32), ("grid_blocks", ctypes.c_int32),
                 ("outputs_per_lane", ctypes.c_int32), ("xcd_chunk", ctypes.c_int32),
                 ("ticket_leaves", ctypes.c_int32), ("max_batch", ctypes.c_int32),
-                ("wide_descriptors", ctypes.c_int32), ("leaf_order", ctypes.c_int32)]
+                ("wide_descriptors", ctypes.c_int32), ("leaf_order", ctypes.c_int32),
+                ("low_block_max", ctypes.c_int32)]
 
 
 _lib = None
