@@ -241,3 +241,27 @@ def test_source_calls_validate_arguments():
     assert L.slos_source_info(None, None, None) == -1
     assert L.slos_source_num_outputs(None) == -1
     L.slos_source_destroy(None)
+
+
+@pytest.mark.parametrize("cap", [8, 35, 120])
+def test_low_block_cap_splits_leaves(cap):
+    """Every leaf's low block (same high part, K - 1 low photons) stays within
+    low_block_max, and the leaves still tile each layer exactly."""
+    m, T = 9, [1, 1, 1, 1, 0, 0, 0, 0, 1]
+    p = slos.Plan(T, "c64", host_only=True, options={"leaf_max": 4096, "low_block_max": cap})
+    for k in range(1, 6):
+        Nk, nl = p.layer_info(k)
+        nxt = 0
+        for base, q, K, hm in sorted(p.leaf(k, idx) for idx in range(nl)):
+            low = math.comb(q + K - 2, K - 1) if K > 0 else 0
+            assert low <= cap or q == 1, (k, q, K, low)
+            assert base == nxt
+            nxt = base + math.comb(q + K - 1, K)
+        assert nxt == Nk
+
+
+def test_leaf_order_and_cap_validation():
+    with pytest.raises(slos.SlosError):
+        slos.Plan([1, 1, 0], "c64", host_only=True, options={"leaf_order": 5})
+    with pytest.raises(slos.SlosError):
+        slos.Plan([1, 1, 0], "c64", host_only=True, options={"low_block_max": -2})

@@ -105,6 +105,10 @@ def test_config2_m12_n6_all_outputs(dtype):
     {"leaf_max": 65536},
     {"wide_descriptors": 1},
     {"wide_descriptors": 1, "leaf_max": 5, "outputs_per_lane": 2},
+    {"leaf_order": -1},                                  # colex leaf order
+    {"leaf_order": 3, "leaf_max": 40},
+    {"low_block_max": 6, "leaf_max": 200},               # many leaves split for their low blocks
+    {"low_block_max": -1, "leaf_max": 65536},
 ])
 def test_tilings_and_launch_shapes_agree(opts):
     T, U = haar_case(9, [2, 0, 1, 0, 0, 2, 0, 0, 1], 9)
@@ -285,3 +289,14 @@ def test_config3_m24_n12_c128_sampled():
     check_c128(gather(p, out, S), oracle.amplitudes(U, T, S), p.num_outputs)
     del out
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("dtype,comp", [("c64", True), ("c128", False)])
+def test_leaf_order_leaves_outputs_bit_identical(dtype, comp):
+    """Each output is one thread's fixed-order sum, so the order in which the
+    leaves are processed cannot change a single bit of the amplitudes."""
+    T, U = haar_case(12, [1] * 6 + [0] * 6, 2)
+    _, a, _ = run(T, U, dtype, compensated=comp, options={"leaf_order": -1})
+    _, b, _ = run(T, U, dtype, compensated=comp, options={"leaf_order": 2})
+    _, c, _ = run(T, U, dtype, compensated=comp)
+    assert torch.equal(a, b) and torch.equal(a, c)
