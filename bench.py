@@ -6,8 +6,9 @@ A step is one full-distribution forward pass at m=24 modes, n=12 photons,
 input |1^12 0^12>, on a seeded Haar-random 24x24 unitary: all layers of the
 recurrence, the normalisation and the FP64 sum of P, producing all
 C(35,12) = 834,451,800 amplitudes.  The headline runs in complex64 with
-compensated accumulation on the deep layers; complex64 without compensation
-and complex128 are timed beside it.  Inputs are resident in HBM before the
+compensated accumulation on every layer (the deep layers inherit the error of
+the earlier ones); complex64 without compensation and complex128 are timed
+beside it.  Inputs are resident in HBM before the
 timed region.
 
 Prints one JSON line (see `emit`).  The roofline entry covers the dominant
@@ -436,7 +437,7 @@ def main():
         "data": "synthetic: seeded Haar-random 24x24 unitary (QR of complex Gaussian, seed 3), input |1^12 0^12>",
         "config": {
             "workload": "SLOS full distribution, m=24 modes, n=12 photons, all 834,451,800 amplitudes"
-                        + (", complex64 with compensated accumulation on layers 11-12" if head_name == "c64comp" else ""),
+                        + (", complex64 with compensated accumulation on every layer" if head_name == "c64comp" else ""),
             "m": m, "n": n, "outputs": M, "variant": head_name,
         },
         "achieved_GBps_step": alg_step / (head["ms_per_step"] * 1e-3) / 1e9,

@@ -444,6 +444,12 @@ __device__ __forceinline__ void tile(const LayerParams &p, const DescRegs<WIDE> 
     tile_compute<T, MODE, COMP, RT, WIDE>(in, p, dr, L, X, u_lds, lowbuf, sigma, t0, lane, psum, omax);
 }
 
+// Outputs per 64-byte sector: complex values, or probabilities in MODE_PROB.
+template <typename T, int MODE> constexpr uint32_t kStoreAlign()
+{
+    return 64u / (uint32_t)(MODE == SLOS_MODE_PROB ? sizeof(T) : 2 * sizeof(T));
+}
+
 // Stage the low block with all waves of the workgroup: 1 KiB chunk c of the
 // copy is issued by wave c % W.
 template <typename C>
@@ -560,13 +566,20 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 3 : (RR <= 2 ? 4 : 1)) void l
         if (nli < p.nleaves) nxt = load_desc<WIDE>(p.desc, nli, lane);
 
         double psum = 0.0;
-        const uint32_t full = L.size / (64u * RR);              // full tiles
+        // Tiles start `shift` states before the leaf, so that every row of 64
+        // outputs is stored on whole 64-byte sectors (a row that straddles
+        // sectors writes each partial sector separately: +11% write traffic for
+        // complex64).  Lanes before the leaf wrap to x >= L.size and are masked
+        // like those past its end.
+        const uint32_t shift = (uint32_t)L.out_base & (kStoreAlign<T, MODE>() - 1u);
+        const uint32_t span = L.size + shift;
+        const uint32_t full = span / (64u * RR);              // full tiles
         for (uint32_t t = (uint32_t)wv; t < full; t += (uint32_t)W)
-            tile<T, MODE, COMP, RR, WIDE>(p, cur, L, X, u_lds, lowbuf, sigma, t * 64u * RR, lane, psum, omax);
-        const uint32_t rows = (L.size - full * 64u * RR + 63u) / 64u;  // leftover rows of 64
+            tile<T, MODE, COMP, RR, WIDE>(p, cur, L, X, u_lds, lowbuf, sigma, t * 64u * RR - shift, lane, psum, omax);
+        const uint32_t rows = (span - full * 64u * RR + 63u) / 64u;  // leftover rows of 64
         for (uint32_t r = (uint32_t)wv; r < rows; r += (uint32_t)W)
-            tile<T, MODE, COMP, 1, WIDE>(p, cur, L, X, u_lds, lowbuf, sigma, full * 64u * RR + r * 64u, lane, psum,
-                                         omax);
+            tile<T, MODE, COMP, 1, WIDE>(p, cur, L, X, u_lds, lowbuf, sigma, full * 64u * RR + r * 64u - shift, lane,
+                                         psum, omax);
         if (MODE != SLOS_MODE_MID) {
             // one FP64 partial per (leaf, wave), summed later in a fixed order
 #pragma unroll
