@@ -8,8 +8,7 @@ recurrence, the normalisation and the FP64 sum of P, producing all
 C(35,12) = 834,451,800 amplitudes.  The headline runs in complex64 with
 compensated accumulation on every layer (the deep layers inherit the error of
 the earlier ones); complex64 without compensation and complex128 are timed
-beside it.  Inputs are resident in HBM before the
-timed region.
+beside it.  Inputs are resident in HBM before the timed region.
 
 Prints one JSON line (see `emit`).  The roofline entry covers the dominant
 kernel (the last layer): algorithmic bytes = 8 B x (N_11 read + N_12 written)
@@ -349,6 +348,11 @@ def cpu_baseline(U_np, T, target_s=20.0):
     t0 = time.perf_counter()
     oracle.amplitudes(U_np, T, sample)
     dt = time.perf_counter() - t0
+    # the same oracle on one thread, on the first outputs of the sample (about 3 s)
+    one = sample[: int(min(max(3.0 / max(per * cores, 1e-9), 16), len(sample)))]
+    t0 = time.perf_counter()
+    oracle.amplitudes(U_np, T, one, threads=1)
+    dt1 = time.perf_counter() - t0
     return {
         "value": len(sample) / dt,
         "unit": "amplitudes/s",
@@ -357,6 +361,28 @@ def cpu_baseline(U_np, T, target_s=20.0):
         "sample": (f"{len(sample)} distinct uniformly drawn outputs of the m=24 n=12 workload "
                    f"(seed {SAMPLE_SEED + 1}), FP64 Ryser permanents with extended-precision "
                    f"accumulation, OpenMP over outputs, {dt:.1f} s"),
+        "single_thread": {"value": len(one) / dt1, "unit": "amplitudes/s", "cores": 1,
+                          "sample": f"the first {len(one)} outputs of the same sample, {dt1:.1f} s"},
+    }
+
+
+def cpu_paper_method(U_np, T):
+    """The paper's own method on the host cores: the plain FP64 SLOS recurrence
+    of the oracle package (OpenMP over states) on the whole workload."""
+    import oracle
+    cores = oracle.num_threads()
+    t0 = time.perf_counter()
+    a, sum_p = oracle.slos_recurrence(U_np, T)
+    dt = time.perf_counter() - t0
+    count = a.size
+    del a
+    return {
+        "value": count / dt,
+        "unit": "amplitudes/s",
+        "cores": cores,
+        "kind": "paper's method (SLOS layer recurrence) on CPU, FP64, OpenMP over states",
+        "sample": f"the whole m=24 n=12 workload, all {count:,} amplitudes, {dt:.1f} s",
+        "sum_p": sum_p,
     }
 
 
@@ -494,6 +520,9 @@ def main():
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(U, T)
+        print("[bench] timing the paper's method (SLOS recurrence) on the CPU, whole workload",
+              file=sys.stderr, flush=True)
+        line["cpu_paper_method"] = cpu_paper_method(U, T)
     else:
         line["cpu_baseline"] = None
     print(json.dumps(line), flush=True)

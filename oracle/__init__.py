@@ -18,6 +18,10 @@ What each function follows (paper = arXiv 2204.00602):
   * clements_unitary: a rectangular ("square", Section 2) mesh of MZIs; the
     column layout is this project's reading (the paper only cites the mesh).
   * grad_U: d Perm(A)/d A[r][c] is the permanent of the (r, c) minor.
+  * slos_recurrence: the paper's own method (Section 3.2.3, SLOS back-end),
+    the layered photon-addition recurrence in plain FP64 C with OpenMP: the
+    CPU baseline of the method, and a second route to Eq. eqperm's numbers
+    that the pins compare with the permanent definition.
   * source_emission / source_events / source_distribution /
     source_performance: the imperfect-source mixture of Section 3.2.4 (emission
     probability, pair emission through g2, indistinguishability), each event's
@@ -62,6 +66,8 @@ def _load():
     lib.oracle_grad_U.restype = ctypes.c_int
     lib.oracle_num_threads.argtypes = []
     lib.oracle_num_threads.restype = ctypes.c_int
+    lib.oracle_slos_all.argtypes = [ctypes.c_int, dp, ip, dp, dp, ctypes.c_int]
+    lib.oracle_slos_all.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -130,6 +136,29 @@ def amplitudes(U, T, states, method: str = "ryser", threads: int = 0) -> np.ndar
     if rc != 0:
         raise ValueError(f"oracle_amplitudes failed ({rc})")
     return out.view(np.complex128)
+
+
+def slos_recurrence(U, T, threads: int = 0):
+    """Every amplitude by the paper's own method, written plainly for the CPU
+    (Section 3.2.3, SLOS back-end: photons added one at a time, A_k[t] = sum_j
+    U[j, i_k] A_{k-1}[t - e_j], then the sqrt(prod s! / prod t!) factor), in FP64
+    with OpenMP over states.  Returns (a, sum_P) with a[r] the amplitude of the
+    r-th output in colex order (see colex_sorted).  A baseline and a second
+    route to Eq. eqperm's numbers, not the definition the parity tests use.
+    """
+    U = np.ascontiguousarray(np.asarray(U, dtype=np.complex128))
+    T = np.ascontiguousarray(np.asarray(T, dtype=np.int32))
+    m = T.size
+    if U.shape != (m, m):
+        raise ValueError("U must be m x m")
+    n = int(T.sum())
+    out = np.empty(fock_count(m, n), dtype=np.complex128)
+    s = ctypes.c_double(0.0)
+    rc = _load().oracle_slos_all(m, _dptr(U.view(np.float64)), _iptr(T), _dptr(out.view(np.float64)),
+                                 ctypes.byref(s), int(threads))
+    if rc != 0:
+        raise ValueError(f"oracle_slos_all failed ({rc})")
+    return out, s.value
 
 
 def probabilities(U, T, states, method: str = "ryser", threads: int = 0) -> np.ndarray:

@@ -1,4 +1,4 @@
-"""Compile the oracle's C source into oracle/liboracle.so (gcc, OpenMP, -O2).
+"""Compile the oracle's C sources into oracle/liboracle.so (gcc, OpenMP, -O2).
 
 Test infrastructure only.  No fast-math: the oracle keeps IEEE semantics.
 """
@@ -7,13 +7,13 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = os.path.join(HERE, "permanent.c")
+SRCS = [os.path.join(HERE, "permanent.c"), os.path.join(HERE, "slos_recurrence.c")]
 LIB = os.path.join(HERE, "liboracle.so")
 
 
 def build(verbose: bool = False) -> str:
     cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp",
-           "-Wall", "-Wextra", "-o", LIB + ".tmp", SRC, "-lm"]
+           "-Wall", "-Wextra", "-o", LIB + ".tmp"] + SRCS + ["-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

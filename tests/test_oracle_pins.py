@@ -375,6 +375,58 @@ def test_empty_top_modes_form_a_colex_prefix(m, n):
         assert mask[:c].all() and not mask[c:].any()
 
 
+# ------------------------------------------- the paper's method, plainly on the CPU
+
+@pytest.mark.parametrize("m,T", [(6, [1, 1, 1, 0, 0, 0]), (5, [2, 0, 1, 0, 1]), (3, [0, 3, 0]),
+                                 (8, [1, 0, 1, 0, 1, 0, 1, 0]), (7, [0, 2, 0, 0, 1, 0, 2]), (2, [1, 1])])
+def test_slos_recurrence_matches_permanent_definition(m, T):
+    """The layered recurrence and Eq. eqperm's permanents (brute force over n!
+    permutations, independent of Ryser) give the same amplitudes, state by
+    state in colex order, for single and bunched inputs on a non-symmetric U."""
+    U = inputs.haar_unitary(m, 30 + m)
+    a, sum_p = oracle.slos_recurrence(U, T)
+    S = oracle.colex_sorted(oracle.fock_states(m, sum(T)))
+    ref = oracle.amplitudes(U, T, S, method="brute")
+    assert a.shape == (len(S),)
+    assert np.abs(a - ref).max() < 1e-14
+    assert sum_p == pytest.approx(1.0, abs=1e-13)
+
+
+def test_slos_recurrence_closed_forms():
+    """Identity U: a = delta_{S,T}; all-ones U: a = n!/sqrt(prod s! prod t!);
+    one mode: a = U00^n; the vacuum: a = 1."""
+    T = [2, 0, 1, 1, 0]
+    S = oracle.colex_sorted(oracle.fock_states(5, 4))
+    a, _ = oracle.slos_recurrence(np.eye(5), T)
+    want = np.array([1.0 if list(s) == T else 0.0 for s in S])
+    assert np.array_equal(a, want)
+    a, _ = oracle.slos_recurrence(np.ones((5, 5)), T)
+    tf = math.prod(math.factorial(t) for t in T)
+    want = np.array([math.factorial(4) / math.sqrt(math.prod(math.factorial(x) for x in s) * tf) for s in S])
+    assert np.abs(a - want).max() < 1e-13
+    u = np.array([[0.6 + 0.3j]])
+    a, _ = oracle.slos_recurrence(u, [5])
+    assert a.shape == (1,) and a[0] == pytest.approx(u[0, 0] ** 5, abs=1e-15)
+    a, sum_p = oracle.slos_recurrence(inputs.haar_unitary(3, 1), [0, 0, 0])
+    assert a.tolist() == [1.0] and sum_p == 1.0
+
+
+def test_slos_recurrence_threads_and_sum():
+    """Each amplitude is one state's own sum, so the thread count cannot change
+    it; sum P = 1 for a Haar U at m = 10, n = 5."""
+    U = inputs.haar_unitary(10, 3)
+    T = [1, 1, 0, 1, 0, 1, 0, 1, 0, 0]
+    a1, s1 = oracle.slos_recurrence(U, T, threads=1)
+    a3, s3 = oracle.slos_recurrence(U, T, threads=3)
+    assert np.array_equal(a1, a3)
+    assert s1 == pytest.approx(1.0, abs=1e-13) and s3 == pytest.approx(1.0, abs=1e-13)
+    rng = np.random.default_rng(5)
+    S = oracle.colex_sorted(oracle.fock_states(10, 5))
+    pick = rng.choice(len(S), 40, replace=False)
+    ref = oracle.amplitudes(U, T, S[pick])
+    assert np.abs(a1[pick] - ref).max() < 1e-14
+
+
 def test_inverse_cdf_sample_hand_distribution():
     P = [0.1, 0.0, 0.5, 0.4]
     r = [0.0, 0.05, 0.1, 0.35, 0.65, 0.999999]
