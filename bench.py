@@ -143,6 +143,105 @@ def time_batched(torch, slos, steps, warmup, count=4096, seed=4):
         "max_abs_sum_p_minus_1": dev, "options": opts, "autotune_s": tune_s,
     }
     b.close()
+    del out, sum_p, U
+    torch.cuda.empty_cache()
+
+    # the same instances in complex128: batched (tuned, graph replay), and the
+    # plain path, one plan per instance launched back to back on one stream
+    opts128 = autotune.tune_batch(states, "c128", Us=Us)
+    b = slos.Batch(states, "c128", options=opts128)
+    U = b.pack_u(Us)
+    out = torch.empty(b.total_outputs, dtype=torch.complex128, device="cuda")
+    sp = torch.zeros(b.count, dtype=torch.float64, device="cuda")
+    b.capture(U, out, sp)
+    for _ in range(warmup):
+        b.replay(stream)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(steps):
+        b.replay(stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms128 = e0.elapsed_time(e1) / steps
+    b.close()
+    del out, sp, U
+    t0 = time.perf_counter()
+    plans = [slos.Plan(t, "c128") for t in states]
+    build_s = time.perf_counter() - t0
+    Ud = [torch.from_numpy(np.asarray(u)).to(torch.complex128).cuda() for u in Us]
+    outs = [torch.empty(pl.num_outputs, dtype=torch.complex128, device="cuda") for pl in plans]
+
+    def plain_pass():
+        for pl, u, o in zip(plans, Ud, outs):
+            pl.amplitudes(u, out=o, stream=stream)
+
+    plain_pass()
+    torch.cuda.synchronize()
+    reps = 2
+    e0.record(stream)
+    for _ in range(reps):
+        plain_pass()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_plain = e0.elapsed_time(e1) / reps
+    for pl in plans:
+        pl.close()
+    del plans, Ud, outs
+    torch.cuda.empty_cache()
+    res["c128"] = {
+        "batched_ms": ms128, "batched_options": opts128,
+        "plain_ms": ms_plain, "plain_plan_build_s": build_s,
+        "plain_path": f"one complex128 plan per instance ({count} plans), launched back to back on one stream",
+    }
+    res["speedup_over_batched_c128"] = ms128 / ms
+    res["speedup_over_plain_c128"] = ms_plain / ms
+    return res
+
+
+def time_config2(torch, slos, steps, warmup, m=12, n=6, seed=2):
+    """m=12, n=6, input |1^6 0^6>, Haar U seed 2 (12,376 amplitudes): one
+    instance, small enough to be bound by launch latency.  Each variant through
+    its plan (n layer launches and the sum of P), eagerly and as a captured HIP
+    graph replayed on the stream."""
+    from paper_2204_00602_amd import inputs
+    T = inputs.first_modes_input(m, n)
+    U_np = inputs.haar_unitary(m, seed)
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    reps = max(50, 10 * steps)
+    res = {"workload": f"m={m} n={n}, input |1^{n} 0^{m - n}>, Haar U (seed {seed}), all "
+                       f"{math.comb(m + n - 1, n):,} amplitudes, one instance"}
+    for name, dt, comp in (("c64comp", "c64", True), ("c64", "c64", False), ("c128", "c128", False)):
+        tdt = torch.complex64 if dt == "c64" else torch.complex128
+        plan = slos.Plan(T, dt, compensated=comp)
+        Ud = torch.from_numpy(U_np).to(tdt).cuda()
+        out = torch.empty(plan.num_outputs, dtype=tdt, device="cuda")
+        sp = torch.zeros(1, dtype=torch.float64, device="cuda")
+        for _ in range(warmup + 2):
+            plan.amplitudes(Ud, out=out, sum_p=sp, stream=stream)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(reps):
+            plan.amplitudes(Ud, out=out, sum_p=sp, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        r = {"plan_ms": e0.elapsed_time(e1) / reps, "sum_p": float(sp.item())}
+        # the same pass captured into a HIP graph and replayed: one launch
+        plan.capture(Ud, out, sp)
+        for _ in range(warmup + 2):
+            plan.replay(stream)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(reps):
+            plan.replay(stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        r["graph_ms"] = e0.elapsed_time(e1) / reps
+        r["amplitudes_per_s"] = plan.num_outputs / (min(r["plan_ms"], r["graph_ms"]) * 1e-3)
+        plan.close()
+        res[name] = r
+    res["c64_speedup_over_c128"] = res["c128"]["plan_ms"] / res["c64"]["plan_ms"]
     return res
 
 
@@ -497,7 +596,13 @@ def main():
         print("[bench] batched workload: 4096 uneven instances (tuning, then graph replays)",
               file=sys.stderr, flush=True)
         line["batched"] = time_batched(torch, slos, args.steps, args.warmup)
-        print(f"[bench] batched: {line['batched']['ms_per_batch']:.3f} ms/batch", file=sys.stderr, flush=True)
+        print(f"[bench] batched: {line['batched']['ms_per_batch']:.3f} ms/batch, c128 batched "
+              f"{line['batched']['c128']['batched_ms']:.3f} ms, plain c128 plans "
+              f"{line['batched']['c128']['plain_ms']:.3f} ms", file=sys.stderr, flush=True)
+        print("[bench] config m=12 n=6: plans and one-instance graph replays", file=sys.stderr, flush=True)
+        line["small"] = time_config2(torch, slos, args.steps, args.warmup)
+        print(f"[bench] m=12 n=6: c64 {line['small']['c64']['plan_ms']:.4f} ms, c128 "
+              f"{line['small']['c128']['plan_ms']:.4f} ms per pass", file=sys.stderr, flush=True)
         print("[bench] gradient workload: mesh m=12 n=6, 64 phase sets", file=sys.stderr, flush=True)
         line["gradient"] = time_gradient(torch, slos, max(10, args.steps // 2), 2)
         print(f"[bench] gradient: {line['gradient']['ms_per_batch']:.3f} ms/batch", file=sys.stderr, flush=True)

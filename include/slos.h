@@ -176,6 +176,19 @@ int slos_probs(slos_plan_t plan, const void *U, void *probs, double *sum_p, void
 int slos_amplitudes_many(slos_plan_t plan, int batch, const void *U, void *out, double *sum_p, void *stream);
 int slos_probs_many(slos_plan_t plan, int batch, const void *U, void *probs, double *sum_p, void *stream);
 
+/*
+ * Record one forward pass (slos_amplitudes_many, or slos_probs_many when
+ * `probs` is non-zero, over `batch` instances) for these buffers into a HIP
+ * graph owned by the plan, replacing an earlier one; slos_plan_replay launches
+ * it on a stream.  Nothing runs at capture time.  The buffers stay bound to the
+ * graph and must outlive it (until the next capture or slos_plan_destroy).  The
+ * graph holds kernel nodes only (the ticket counters are cleared by a kernel).
+ * Small plans are bound by launch latency: one graph launch replaces the n
+ * layer launches and the sum.  SLOS_ERR_INVALID_ARG while timing is on.
+ */
+int slos_plan_capture(slos_plan_t plan, int batch, int probs, const void *U, void *out, double *sum_p);
+int slos_plan_replay(slos_plan_t plan, void *stream);
+
 /* ---- weak simulation from the strong one ------------------------------------ */
 
 /*

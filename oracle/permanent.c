@@ -189,12 +189,14 @@ int oracle_amplitudes(int m, int n, const double *U, const int32_t *T, int64_t c
     if (check_state(m, n, T)) return -2;
     for (int64_t q = 0; q < count; ++q)
         if (check_state(m, n, S + q * m)) return -3;
+    int nt = 1;  /* threads of this call only: the process-wide default is left alone */
 #ifdef _OPENMP
-    if (nthreads > 0) omp_set_num_threads(nthreads);
+    nt = nthreads > 0 ? nthreads : omp_get_max_threads();
 #else
     (void)nthreads;
+    (void)nt;
 #endif
-#pragma omp parallel for schedule(dynamic, 16)
+#pragma omp parallel for schedule(dynamic, 16) num_threads(nt)
     for (int64_t q = 0; q < count; ++q) {
         lcplx sub[ORACLE_MAX_N * ORACLE_MAX_N];
         int rows[ORACLE_MAX_N], cols[ORACLE_MAX_N];
@@ -237,16 +239,18 @@ int oracle_grad_U(int m, int n, const double *U, const int32_t *T, int64_t count
     if (check_state(m, n, T)) return -2;
     for (int64_t q = 0; q < count; ++q)
         if (check_state(m, n, S + q * m)) return -3;
+    int nt = 1;  /* threads of this call only: the process-wide default is left alone */
 #ifdef _OPENMP
-    if (nthreads > 0) omp_set_num_threads(nthreads);
+    nt = nthreads > 0 ? nthreads : omp_get_max_threads();
 #else
     (void)nthreads;
+    (void)nt;
 #endif
     size_t mm = (size_t)m * m;
     lcplx *acc = (lcplx *)calloc(mm, sizeof(lcplx));
     if (!acc) return -4;
     int alloc_failed = 0;
-#pragma omp parallel
+#pragma omp parallel num_threads(nt)
     {
         lcplx *loc = (lcplx *)calloc(mm, sizeof(lcplx));
         if (!loc) {

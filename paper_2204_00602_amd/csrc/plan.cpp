@@ -216,6 +216,7 @@ struct slos_plan_s {
     bool timing = false;
     bool timed_reduce = false;
     std::vector<hipEvent_t> events;   // n + 2 when timing is on
+    hipGraphExec_t graph = nullptr;   // slos_plan_capture
 
     size_t elem() const { return c64 ? 8 : 16; }
 
@@ -458,6 +459,8 @@ struct slos_plan_s {
         d_partials = nullptr;
         for (hipEvent_t ev : events) (void)hipEventDestroy(ev);
         events.clear();
+        if (graph) (void)hipGraphExecDestroy(graph);
+        graph = nullptr;
     }
 };
 
@@ -1192,6 +1195,50 @@ int slos_amplitudes_many(slos_plan_t p, int batch, const void *U, void *out, dou
 int slos_probs_many(slos_plan_t p, int batch, const void *U, void *probs, double *sum_p, void *stream)
 {
     return run_forward(p, batch, U, probs, sum_p, stream, SLOS_MODE_PROB);
+}
+
+int slos_plan_capture(slos_plan_t p, int batch, int probs, const void *U, void *out, double *sum_p)
+{
+    int rc = check_plan(p);
+    if (rc) return rc;
+    if (p->timing) return fail(SLOS_ERR_INVALID_ARG, "turn timing off before capturing the pass");
+    if (p->graph) {
+        (void)hipGraphExecDestroy(p->graph);
+        p->graph = nullptr;
+    }
+    hipStream_t s;
+    hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(e, "capture stream");
+    hipGraph_t g = nullptr;
+    e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        (void)hipStreamDestroy(s);
+        return hip_fail(e, "begin capture");
+    }
+    rc = run_forward(p, batch, U, out, sum_p, s, probs ? SLOS_MODE_PROB : SLOS_MODE_AMPL);
+    const hipError_t ee = hipStreamEndCapture(s, &g);
+    if (!rc && ee == hipSuccess) e = hipGraphInstantiate(&p->graph, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipStreamDestroy(s);
+    if (rc) {
+        p->graph = nullptr;
+        return rc;  // run_forward set the message
+    }
+    if (ee != hipSuccess || e != hipSuccess) {
+        p->graph = nullptr;
+        return hip_fail(ee != hipSuccess ? ee : e, "graph capture of the forward pass");
+    }
+    return SLOS_OK;
+}
+
+int slos_plan_replay(slos_plan_t p, void *stream)
+{
+    int rc = check_plan(p);
+    if (rc) return rc;
+    if (!p->graph) return fail(SLOS_ERR_INVALID_ARG, "no captured graph: call slos_plan_capture first");
+    const hipError_t e = hipGraphLaunch(p->graph, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "graph launch");
+    return SLOS_OK;
 }
 
 int slos_cdf(slos_plan_t p, const void *probs, void *stream)

@@ -110,6 +110,8 @@ def lib():
     L.slos_source_probs.argtypes = [vp, vp, vp, vp]
     L.slos_source_postselect.argtypes = [vp, vp, i32p, ctypes.c_int, i32p, i32p, ctypes.c_int,
                                          ctypes.POINTER(ctypes.c_double), vp]
+    L.slos_plan_capture.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, vp, vp]
+    L.slos_plan_replay.argtypes = [vp, vp]
     L.slos_plan_set_timing.argtypes = [vp, ctypes.c_int]
     L.slos_plan_layer_ms.argtypes = [vp, ctypes.POINTER(ctypes.c_float), ctypes.c_int]
     L.slos_last_error.argtypes = []
@@ -120,7 +122,8 @@ def lib():
                  "slos_probs_many", "slos_backward_many", "slos_plan_set_timing", "slos_plan_layer_ms", "slos_backward",
                  "slos_mesh_unitary", "slos_mesh_backward", "slos_batch_plan", "slos_batch_offsets",
                  "slos_batch_amplitudes", "slos_batch_capture", "slos_batch_replay", "slos_source_plan",
-                 "slos_source_info", "slos_source_probs", "slos_source_postselect"):
+                 "slos_source_info", "slos_source_probs", "slos_source_postselect", "slos_plan_capture",
+                 "slos_plan_replay"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -316,6 +319,34 @@ class Plan:
         _check(self._lib.slos_amplitudes_many(self._h, b, U.data_ptr(), out.data_ptr(),
                                               None if sum_p is None else sum_p.data_ptr(), _stream_ptr(stream)))
         return out
+
+    def capture(self, U, out, sum_p=None, probs=False):
+        """Record one forward pass on these buffers into a HIP graph owned by the
+        plan (amplitudes, or P with probs=True; U is m x m or batch x m x m).
+        Nothing runs now; replay() launches the graph."""
+        import torch
+        if U.dim() == 3:
+            b = self._check_many(U)
+        else:
+            self._check_U(U)
+            b = 1
+        if probs:
+            want = torch.float32 if self.dtype == "c64" else torch.float64
+        else:
+            want = self._complex_dtype()
+        if out.dtype != want or out.numel() != b * self.num_outputs or not out.is_contiguous() \
+                or out.device != U.device:
+            raise ValueError("out has the wrong dtype, size, layout or device")
+        if sum_p is not None and (sum_p.dtype != torch.float64 or sum_p.numel() < b or sum_p.device != U.device):
+            raise TypeError("sum_p must be a float64 tensor with one entry per instance")
+        self._bound = (U, out, sum_p)  # the graph keeps raw pointers: keep the tensors alive
+        _check(self._lib.slos_plan_capture(self._h, b, 1 if probs else 0, U.data_ptr(), out.data_ptr(),
+                                           None if sum_p is None else sum_p.data_ptr()))
+
+    def replay(self, stream=None):
+        """Launch the captured forward pass on a stream."""
+        self.forward_count = getattr(self, "forward_count", 0) + 1
+        _check(self._lib.slos_plan_replay(self._h, _stream_ptr(stream)))
 
     def backward_many(self, U, grad_a, grad_U=None, stream=None):
         """Gradients with respect to each U of a batch (see backward)."""
