@@ -225,20 +225,22 @@ __global__ __launch_bounds__(256) void ps_leaf_kernel(PostselectParams p)
             for (int h = 0; h < SLOS_PS_MAX_GROUPS; ++h) hc[h] += (g == h) ? 1u : 0u;
         }
         const E *low = (const E *)p.low + p.type_off[tab];
-        // four outputs per lane and step (x0 + 64u), loads first: P is read once
-        // (non-temporal, so the shared low-state table stays in L2)
-        for (uint32_t x0 = lane; x0 < size; x0 += 256) {
-            E w[4];
-            T v[4];
+        // kSteps outputs per lane and step (x0 + 64u), loads first: P is read
+        // once (non-temporal, so the shared low-state table stays in L2).
+        // Measured at m=24, n=12: 4 per step 1.33 ms, 8 1.24 ms, 16 1.52 ms.
+        constexpr int kSteps = 8;
+        for (uint32_t x0 = lane; x0 < size; x0 += 64u * kSteps) {
+            E w[kSteps];
+            T v[kSteps];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < kSteps; ++u) {
                 const uint32_t x = x0 + 64u * u;
                 const uint32_t xc = x < size ? x : x0;
                 w[u] = low[xc];
                 v[u] = __builtin_nontemporal_load(P + base + xc);
             }
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < kSteps; ++u) {
                 const uint32_t x = x0 + 64u * u;
                 if (x >= size) break;
                 bool ok = true;
