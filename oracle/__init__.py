@@ -66,8 +66,9 @@ def _load():
     lib.oracle_grad_U.restype = ctypes.c_int
     lib.oracle_num_threads.argtypes = []
     lib.oracle_num_threads.restype = ctypes.c_int
-    lib.oracle_slos_all.argtypes = [ctypes.c_int, dp, ip, dp, dp, ctypes.c_int]
-    lib.oracle_slos_all.restype = ctypes.c_int
+    for name in ("oracle_slos_all", "oracle_slos_all_ext"):
+        getattr(lib, name).argtypes = [ctypes.c_int, dp, ip, dp, dp, ctypes.c_int]
+        getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -138,13 +139,14 @@ def amplitudes(U, T, states, method: str = "ryser", threads: int = 0) -> np.ndar
     return out.view(np.complex128)
 
 
-def slos_recurrence(U, T, threads: int = 0):
+def slos_recurrence(U, T, threads: int = 0, extended: bool = False):
     """Every amplitude by the paper's own method, written plainly for the CPU
     (Section 3.2.3, SLOS back-end: photons added one at a time, A_k[t] = sum_j
     U[j, i_k] A_{k-1}[t - e_j], then the sqrt(prod s! / prod t!) factor), in FP64
-    with OpenMP over states.  Returns (a, sum_P) with a[r] the amplitude of the
-    r-th output in colex order (see colex_sorted).  A baseline and a second
-    route to Eq. eqperm's numbers, not the definition the parity tests use.
+    with OpenMP over states (extended=True: the layers and sums in long double).
+    Returns (a, sum_P) with a[r] the amplitude of the r-th output in colex order
+    (see colex_sorted).  A baseline and a second route to Eq. eqperm's numbers;
+    the reference where permanents are out of reach (n = 32).
     """
     U = np.ascontiguousarray(np.asarray(U, dtype=np.complex128))
     T = np.ascontiguousarray(np.asarray(T, dtype=np.int32))
@@ -154,8 +156,8 @@ def slos_recurrence(U, T, threads: int = 0):
     n = int(T.sum())
     out = np.empty(fock_count(m, n), dtype=np.complex128)
     s = ctypes.c_double(0.0)
-    rc = _load().oracle_slos_all(m, _dptr(U.view(np.float64)), _iptr(T), _dptr(out.view(np.float64)),
-                                 ctypes.byref(s), int(threads))
+    fn = _load().oracle_slos_all_ext if extended else _load().oracle_slos_all
+    rc = fn(m, _dptr(U.view(np.float64)), _iptr(T), _dptr(out.view(np.float64)), ctypes.byref(s), int(threads))
     if rc != 0:
         raise ValueError(f"oracle_slos_all failed ({rc})")
     return out, s.value

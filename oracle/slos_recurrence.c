@@ -25,7 +25,9 @@
  *
  * Arithmetic: IEEE binary64 throughout (complex products and sums in double),
  * the normalisation from a table of sqrt(k!), and the sum of P in a fixed order
- * (per-range partials added in range order).
+ * (per-range partials added in range order).  A second entry point runs the
+ * same steps in long double (x87 extended precision) for many-photon cases
+ * whose sums cancel heavily.
  */
 #include <math.h>
 #include <stdint.h>
@@ -88,142 +90,150 @@ static void next_comb(int k, int *c)
  * U[2 (j m + i) + 1] = Im (row = output mode).  T holds the m input
  * occupations.  *sum_p receives sum_S |a(S)|^2.  threads <= 0: OpenMP's
  * default.  Returns 0, or -1 for invalid arguments, -2 when a count overflows,
- * -3 when memory runs out.
+ * -3 when memory runs out.  REAL is the type of the layers and of every sum:
+ * double (oracle_slos_all), or long double (oracle_slos_all_ext: x87 extended
+ * precision, a reference for cases with heavy cancellation over many photons).
  */
-int oracle_slos_all(int m, const double *U, const int32_t *T, double *out, double *sum_p, int threads)
-{
-    if (m < 1 || m > SR_MAX_M || !U || !T || !out) return -1;
-    int n = 0;
-    for (int i = 0; i < m; ++i) {
-        if (T[i] < 0) return -1;
-        n += T[i];
+#define SR_DEFINE(NAME, REAL, SQRT)                                                                          \
+    int NAME(int m, const double *U, const int32_t *T, double *out, double *sum_p, int threads)              \
+    {                                                                                                        \
+        if (m < 1 || m > SR_MAX_M || !U || !T || !out) return -1;                                            \
+        int n = 0;                                                                                           \
+        for (int i = 0; i < m; ++i) {                                                                        \
+            if (T[i] < 0) return -1;                                                                         \
+            n += T[i];                                                                                       \
+        }                                                                                                    \
+        if (n > SR_MAX_N) return -1;                                                                         \
+        uint64_t *C = NULL;                                                                                  \
+        const int W = n + 1;                                                                                 \
+        {                                                                                                    \
+            const int e = binom_table(m + n + 1, W, &C);                                                     \
+            if (e) return e;                                                                                 \
+        }                                                                                                    \
+        if (sum_p) *sum_p = 0.0;                                                                             \
+        /* photon list i_1 <= .. <= i_n and sqrt(k!) */                                                     \
+        int photon[SR_MAX_N + 1];                                                                            \
+        REAL sqrt_fact[SR_MAX_N + 1];                                                                        \
+        REAL tfac = 1;                                                                                       \
+        {                                                                                                    \
+            int k = 0;                                                                                       \
+            for (int i = 0; i < m; ++i)                                                                      \
+                for (int c = 0; c < T[i]; ++c) photon[++k] = i;                                              \
+            REAL f = 1;                                                                                      \
+            sqrt_fact[0] = 1;                                                                                \
+            for (int q = 1; q <= n; ++q) {                                                                   \
+                f *= q;                                                                                      \
+                sqrt_fact[q] = SQRT(f);                                                                      \
+            }                                                                                                \
+            for (int i = 0; i < m; ++i) tfac *= sqrt_fact[T[i]];                                             \
+        }                                                                                                    \
+        if (n == 0) {                                                                                        \
+            out[0] = 1.0;                                                                                    \
+            out[1] = 0.0;                                                                                    \
+            if (sum_p) *sum_p = 1.0;                                                                         \
+            free(C);                                                                                         \
+            return 0;                                                                                        \
+        }                                                                                                    \
+        /* two buffers as large as the largest layer below n */                                             \
+        uint64_t big = 1;                                                                                    \
+        for (int k = 1; k < n; ++k)                                                                          \
+            if (C[(size_t)(m + k - 1) * W + k] > big) big = C[(size_t)(m + k - 1) * W + k];                  \
+        REAL *buf[2] = {NULL, NULL};                                                                         \
+        if (n > 1) {                                                                                         \
+            buf[0] = (REAL *)malloc(2 * sizeof(REAL) * big);                                                 \
+            buf[1] = (REAL *)malloc(2 * sizeof(REAL) * big);                                                 \
+            if (!buf[0] || !buf[1]) {                                                                        \
+                free(buf[0]);                                                                                \
+                free(buf[1]);                                                                                \
+                free(C);                                                                                     \
+                return -3;                                                                                   \
+            }                                                                                                \
+        }                                                                                                    \
+        const REAL one[2] = {1, 0};                                                                          \
+        const REAL *prev = one;                                                                              \
+        int nthr = 1;                                                                                        \
+        SR_THREADS(nthr, threads);                                                                           \
+        const int64_t nparts = (int64_t)nthr * 8;                                                            \
+        REAL *partial = (REAL *)calloc((size_t)nparts, sizeof(REAL));                                        \
+        if (!partial) {                                                                                      \
+            free(buf[0]);                                                                                    \
+            free(buf[1]);                                                                                    \
+            free(C);                                                                                         \
+            return -3;                                                                                       \
+        }                                                                                                    \
+        for (int k = 1; k <= n; ++k) {                                                                       \
+            const uint64_t Nk = C[(size_t)(m + k - 1) * W + k];                                              \
+            const int last = k == n;                                                                         \
+            REAL *cur = last ? NULL : buf[k & 1];                                                            \
+            const int col = photon[k];                                                                       \
+            SR_PARALLEL_FOR(nthr)                                                                            \
+            for (int64_t part = 0; part < nparts; ++part) {                                                  \
+                const uint64_t lo = Nk * (uint64_t)part / (uint64_t)nparts;                                  \
+                const uint64_t hi = Nk * (uint64_t)(part + 1) / (uint64_t)nparts;                            \
+                if (lo >= hi) continue;                                                                      \
+                int c[SR_MAX_N + 2];                                                                         \
+                uint64_t keep[SR_MAX_N + 2], drop[SR_MAX_N + 2];                                             \
+                unrank(C, W, m, k, lo, c);                                                                   \
+                REAL psum = 0;                                                                               \
+                for (uint64_t t = lo; t < hi; ++t) {                                                         \
+                    if (t > lo) next_comb(k, c);                                                             \
+                    /* keep[r] = sum_{q<=r} C(c_q, q); drop[r] = sum_{q>=r} C(c_q - 1, q - 1) */            \
+                    keep[0] = 0;                                                                             \
+                    for (int r = 1; r <= k; ++r) keep[r] = keep[r - 1] + C[(size_t)c[r] * W + r];            \
+                    drop[k + 1] = 0;                                                                         \
+                    for (int r = k; r >= 1; --r)                                                             \
+                        drop[r] = drop[r + 1] + (c[r] >= 1 ? C[(size_t)(c[r] - 1) * W + r - 1] : 0);         \
+                    REAL re = 0, im = 0, sfac = 1;                                                           \
+                    int run = 0;                                                                             \
+                    for (int r = 1; r <= k; ++r) {                                                           \
+                        const int d = c[r] - (r - 1);                                                        \
+                        ++run;                                                                               \
+                        const int d_next = r < k ? c[r + 1] - r : -1;                                        \
+                        if (d_next == d) continue; /* mode d has another photon above r */                   \
+                        const uint64_t pr = keep[r - 1] + drop[r + 1];                                       \
+                        const REAL ur = U[2 * ((size_t)d * m + col)], ui = U[2 * ((size_t)d * m + col) + 1]; \
+                        const REAL xr = prev[2 * pr], xi = prev[2 * pr + 1];                                 \
+                        re += ur * xr - ui * xi;                                                             \
+                        im += ur * xi + ui * xr;                                                             \
+                        if (last) sfac *= sqrt_fact[run];                                                    \
+                        run = 0;                                                                             \
+                    }                                                                                        \
+                    if (last) {                                                                              \
+                        const REAL f = sfac / tfac;                                                          \
+                        re *= f;                                                                             \
+                        im *= f;                                                                             \
+                        psum += re * re + im * im;                                                           \
+                        out[2 * t] = (double)re;                                                             \
+                        out[2 * t + 1] = (double)im;                                                         \
+                    } else {                                                                                 \
+                        cur[2 * t] = re;                                                                     \
+                        cur[2 * t + 1] = im;                                                                 \
+                    }                                                                                        \
+                }                                                                                            \
+                if (last) partial[part] = psum;                                                              \
+            }                                                                                                \
+            prev = cur;                                                                                      \
+        }                                                                                                    \
+        if (sum_p) {                                                                                         \
+            REAL s = 0;                                                                                      \
+            for (int64_t part = 0; part < nparts; ++part) s += partial[part];                                \
+            *sum_p = (double)s;                                                                              \
+        }                                                                                                    \
+        free(partial);                                                                                       \
+        free(buf[0]);                                                                                        \
+        free(buf[1]);                                                                                        \
+        free(C);                                                                                             \
+        return 0;                                                                                            \
     }
-    if (n > SR_MAX_N) return -1;
-    uint64_t *C = NULL;
-    const int W = n + 1;
-    {
-        const int e = binom_table(m + n + 1, W, &C);
-        if (e) return e;
-    }
-    if (sum_p) *sum_p = 0.0;
 
-    /* photon list i_1 <= .. <= i_n and sqrt(k!) */
-    int photon[SR_MAX_N + 1];
-    double sqrt_fact[SR_MAX_N + 1];
-    double tfac = 1.0;
-    {
-        int k = 0;
-        for (int i = 0; i < m; ++i)
-            for (int c = 0; c < T[i]; ++c) photon[++k] = i;
-        double f = 1.0;
-        sqrt_fact[0] = 1.0;
-        for (int q = 1; q <= n; ++q) {
-            f *= q;
-            sqrt_fact[q] = sqrt(f);
-        }
-        for (int i = 0; i < m; ++i) tfac *= sqrt_fact[T[i]];
-    }
-    if (n == 0) {
-        out[0] = 1.0;
-        out[1] = 0.0;
-        if (sum_p) *sum_p = 1.0;
-        free(C);
-        return 0;
-    }
-
-    /* two buffers as large as the largest layer below n */
-    uint64_t big = 1;
-    for (int k = 1; k < n; ++k)
-        if (C[(size_t)(m + k - 1) * W + k] > big) big = C[(size_t)(m + k - 1) * W + k];
-    double *buf[2] = {NULL, NULL};
-    if (n > 1) {
-        buf[0] = (double *)malloc(2 * sizeof(double) * big);
-        buf[1] = (double *)malloc(2 * sizeof(double) * big);
-        if (!buf[0] || !buf[1]) {
-            free(buf[0]);
-            free(buf[1]);
-            free(C);
-            return -3;
-        }
-    }
-    const double one[2] = {1.0, 0.0};
-    const double *prev = one;
-
-    int nthr = 1;
 #ifdef _OPENMP
-    nthr = threads > 0 ? threads : omp_get_max_threads();
+#define SR_THREADS(nthr, threads) (nthr) = (threads) > 0 ? (threads) : omp_get_max_threads()
+#define SR_PRAGMA(x) _Pragma(#x)
+#define SR_PARALLEL_FOR(nthr) SR_PRAGMA(omp parallel for schedule(dynamic, 1) num_threads(nthr))
 #else
-    (void)threads;
+#define SR_THREADS(nthr, threads) (void)(threads)
+#define SR_PARALLEL_FOR(nthr)
 #endif
-    const int64_t nparts = (int64_t)nthr * 8;
-    double *partial = (double *)calloc((size_t)nparts, sizeof(double));
-    if (!partial) {
-        free(buf[0]);
-        free(buf[1]);
-        free(C);
-        return -3;
-    }
 
-    for (int k = 1; k <= n; ++k) {
-        const uint64_t Nk = C[(size_t)(m + k - 1) * W + k];
-        double *cur = k == n ? out : buf[k & 1];
-        const int col = photon[k];
-        const int last = k == n;
-#ifdef _OPENMP
-#pragma omp parallel for schedule(dynamic, 1) num_threads(nthr)
-#endif
-        for (int64_t part = 0; part < nparts; ++part) {
-            const uint64_t lo = Nk * (uint64_t)part / (uint64_t)nparts;
-            const uint64_t hi = Nk * (uint64_t)(part + 1) / (uint64_t)nparts;
-            if (lo >= hi) continue;
-            int c[SR_MAX_N + 2];
-            uint64_t keep[SR_MAX_N + 2], drop[SR_MAX_N + 2];
-            unrank(C, W, m, k, lo, c);
-            double psum = 0.0;
-            for (uint64_t t = lo; t < hi; ++t) {
-                if (t > lo) next_comb(k, c);
-                /* keep[r] = sum_{q<=r} C(c_q, q); drop[r] = sum_{q>=r} C(c_q - 1, q - 1) */
-                keep[0] = 0;
-                for (int r = 1; r <= k; ++r) keep[r] = keep[r - 1] + C[(size_t)c[r] * W + r];
-                drop[k + 1] = 0;
-                for (int r = k; r >= 1; --r)
-                    drop[r] = drop[r + 1] + (c[r] >= 1 ? C[(size_t)(c[r] - 1) * W + r - 1] : 0);
-                double re = 0.0, im = 0.0, sfac = 1.0;
-                int run = 0;
-                for (int r = 1; r <= k; ++r) {
-                    const int d = c[r] - (r - 1);
-                    ++run;
-                    const int d_next = r < k ? c[r + 1] - r : -1;
-                    if (d_next == d) continue;  /* mode d has another photon above r */
-                    const uint64_t pr = keep[r - 1] + drop[r + 1];
-                    const double ur = U[2 * ((size_t)d * m + col)], ui = U[2 * ((size_t)d * m + col) + 1];
-                    const double xr = prev[2 * pr], xi = prev[2 * pr + 1];
-                    re += ur * xr - ui * xi;
-                    im += ur * xi + ui * xr;
-                    if (last) sfac *= sqrt_fact[run];
-                    run = 0;
-                }
-                if (last) {
-                    const double f = sfac / tfac;
-                    re *= f;
-                    im *= f;
-                    psum += re * re + im * im;
-                }
-                cur[2 * t] = re;
-                cur[2 * t + 1] = im;
-            }
-            if (last) partial[part] = psum;
-        }
-        prev = cur;
-    }
-    if (sum_p) {
-        double s = 0.0;
-        for (int64_t part = 0; part < nparts; ++part) s += partial[part];
-        *sum_p = s;
-    }
-    free(partial);
-    free(buf[0]);
-    free(buf[1]);
-    free(C);
-    return 0;
-}
+SR_DEFINE(oracle_slos_all, double, sqrt)
+SR_DEFINE(oracle_slos_all_ext, long double, sqrtl)

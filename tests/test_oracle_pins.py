@@ -427,6 +427,29 @@ def test_slos_recurrence_threads_and_sum():
     assert np.abs(a1[pick] - ref).max() < 1e-14
 
 
+def test_slos_recurrence_extended_twin_fock_closed_form():
+    """|N, N> on a 50:50 beam splitter: P(2k, 2N - 2k) = C(2k, k) C(2N - 2k, N - k)
+    / 4^N and every odd count vanishes (the many-photon Hong-Ou-Mandel
+    effect), here at N = 16 (n = 32, the largest photon count).  The extended
+    recurrence meets it to rounding; plain FP64 loses about 3 digits to the
+    cancellation, which is why the n = 32 parity cases use the extended one."""
+    N = 16
+    U = oracle.beam_splitter_rx(math.pi / 2)
+    S = oracle.colex_sorted(oracle.fock_states(2, 2 * N))
+    want = np.array([0.0 if s[0] % 2 else math.comb(int(s[0]), int(s[0]) // 2)
+                     * math.comb(int(s[1]), int(s[1]) // 2) / 4.0 ** N for s in S])
+    a, sum_p = oracle.slos_recurrence(U, [N, N], extended=True)
+    assert np.abs(np.abs(a) ** 2 - want).max() < 1e-15
+    assert sum_p == pytest.approx(1.0, abs=1e-15)
+    a64, _ = oracle.slos_recurrence(U, [N, N])
+    assert np.abs(np.abs(a64) ** 2 - want).max() < 1e-12
+    for m, T in ((6, [1, 1, 1, 0, 0, 0]), (5, [2, 0, 1, 0, 1])):
+        Uh = inputs.haar_unitary(m, 30 + m)
+        S = oracle.colex_sorted(oracle.fock_states(m, sum(T)))
+        ext, _ = oracle.slos_recurrence(Uh, T, extended=True)
+        assert np.abs(ext - oracle.amplitudes(Uh, T, S, method="brute")).max() < 1e-15
+
+
 def test_inverse_cdf_sample_hand_distribution():
     P = [0.1, 0.0, 0.5, 0.4]
     r = [0.0, 0.05, 0.1, 0.35, 0.65, 0.999999]

@@ -300,3 +300,94 @@ def test_leaf_order_leaves_outputs_bit_identical(dtype, comp):
     _, b, _ = run(T, U, dtype, compensated=comp, options={"leaf_order": 2})
     _, c, _ = run(T, U, dtype, compensated=comp)
     assert torch.equal(a, b) and torch.equal(a, c)
+
+
+# -------------------------------------------------------- the largest m and n the plan accepts
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_max_modes_m255(dtype):
+    """m = 255 (the largest), n = 3 photons in modes 0, 127 and 254: 2.8M
+    outputs, high-mode groups beyond the narrow descriptor.  Sampled outputs
+    (uniform, all bunched, and each photon alone in the last mode) against the
+    oracle's permanents; sum P = 1."""
+    m = 255
+    T = np.zeros(m, np.int32)
+    T[[0, 127, 254]] = 1
+    U = inputs.haar_unitary(m, 255)
+    print(f"[parity] m=255 n=3 {dtype}", flush=True)
+    p, out, s = run(T, U, dtype)
+    assert p.num_outputs == math.comb(257, 3)
+    S = list(inputs.uniform_fock_states(m, 3, 3000, 2550))
+    for j in (0, 1, 127, 253, 254):
+        e = np.zeros(m, np.int32)
+        e[j] = 3
+        S.append(e)
+    e = np.zeros(m, np.int32)
+    e[[252, 253, 254]] = 1
+    S.append(e)
+    S = np.stack(S)
+    a = gather(p, out, S)
+    ref = oracle.amplitudes(U, T, S)
+    if dtype == "c128":
+        check_c128(a, ref, p.num_outputs)
+        assert abs(s - 1.0) <= 1e-12
+    else:
+        check_c64_probs(np.abs(a.astype(np.complex128)) ** 2, np.abs(ref) ** 2, p.num_outputs)
+        assert abs(s - 1.0) <= 1e-6
+    del out
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("m,T,dtype,comp", [
+    (2, [16, 16], "c128", False),
+    (3, [10, 11, 11], "c128", False),
+    (4, [32, 0, 0, 0], "c128", False),
+    (2, [16, 16], "c64", True),
+    (3, [10, 11, 11], "c64", True),
+    (4, [32, 0, 0, 0], "c64", True),
+])
+def test_max_photons_n32(m, T, dtype, comp):
+    """n = 32 (the largest), heavily bunched.  Ryser is out of reach at n = 32
+    (2^32 terms per output), so every output is compared with the oracle
+    package's recurrence in extended precision (pinned against brute-force
+    permanents, and against the closed form of |16, 16> on a beam splitter).
+
+    complex128 tolerance, derived from the arithmetic: each layer sums at most
+    m + 1 products, so the FP64 result is within n (m + 2) 2^-53 of the sum of
+    the absolute values of every term of the expansion, which is the amplitude
+    computed with |U| in place of U.  Where the terms cancel heavily (the
+    many-photon Hong-Ou-Mandel zeros of |16, 16>) this exceeds the 1e-12
+    relative bar of the benchmark configurations (measured 1.2e-12 there, and
+    the same for a plain FP64 CPU recurrence).
+
+    complex64: every layer is stored in complex64, and no accumulator can
+    recover that rounding once later layers cancel; with U rounded to
+    complex64 as well, the error is within n (m + 4) 2^-24 of the same |U|
+    amplitude.  (Measured on P, floored at 1/M: 9.7e-4 for |16, 16>, 1.6e-4 for
+    |10, 11, 11>, 8.4e-7 for |32, 0, 0, 0>; the 1e-5 bar of the benchmark
+    configurations is not reachable in complex64 storage when 32 photons
+    interfere this strongly.)"""
+    U = oracle.beam_splitter_rx(math.pi / 2) if m == 2 else inputs.haar_unitary(m, 320 + m)
+    n = int(sum(T))
+    print(f"[parity] m={m} T={T} {dtype} comp={comp}", flush=True)
+    p, out, s = run(T, U, dtype, compensated=comp)
+    ref, ref_sum = oracle.slos_recurrence(U, T, extended=True)
+    S = oracle.colex_sorted(oracle.fock_states(m, n))
+    assert p.num_outputs == len(S) == ref.size
+    a = gather(p, out, S).astype(np.complex128)
+    assert abs(ref_sum - 1.0) <= 1e-13
+    bound_terms, _ = oracle.slos_recurrence(np.abs(U), T, extended=True)
+    if dtype == "c128":
+        tol = n * (m + 2) * 2.0 ** -53 * np.abs(bound_terms) + 1e-300
+    else:
+        tol = n * (m + 4) * 2.0 ** -24 * np.abs(bound_terms) + 1e-300
+    ratio = np.abs(a - ref) / tol
+    Pref = np.abs(ref) ** 2
+    floored_p = np.abs(np.abs(a) ** 2 - Pref) / np.maximum(Pref, 1.0 / p.num_outputs)
+    print(f"  max error / bound {ratio.max():.3f}, floored rel err on P {floored_p.max():.3e}", flush=True)
+    assert ratio.max() <= 1.0
+    assert abs(s - 1.0) <= (1e-12 if dtype == "c128" else 1e-6)
+    if m == 2 and dtype == "c128":  # P(2k, 32 - 2k) = C(2k, k) C(32 - 2k, 16 - k) / 4^16, odd counts vanish
+        want = np.array([0.0 if x[0] % 2 else math.comb(int(x[0]), int(x[0]) // 2)
+                         * math.comb(int(x[1]), int(x[1]) // 2) / 4.0 ** 16 for x in S])
+        assert np.abs(np.abs(a) ** 2 - want).max() <= 1e-12
