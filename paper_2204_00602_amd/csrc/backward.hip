@@ -254,8 +254,19 @@ struct PhaseFactors {
     }
 };
 
-// One wave per phase set (m <= 64); lane c owns column c of the running
-// product, so the sweeps share nothing between lanes and need no barriers.
+// One wave per phase set (m <= 64).  The MZIs of one mesh column act on
+// disjoint row pairs, so a whole column is applied (and differentiated) in one
+// step: lane l serves the column's MZI i = l / gc on matrix columns
+// l % gc, l % gc + gc, .., with gc = 64 / (most MZIs in a column) rounded down
+// to a power of two (8 at m = 12), and a barrier separates the m column steps.
+__device__ __forceinline__ int mesh_lanes_per_mzi(int m)
+{
+    const int most = m / 2 > 0 ? m / 2 : 1;
+    int gc = 1;
+    while (gc * 2 * most <= 64) gc *= 2;
+    return gc;
+}
+
 template <typename T>
 __global__ __launch_bounds__(64) void mesh_forward_kernel(int m, int nmzi, const double *__restrict__ phases,
                                                           typename Cb<T>::type *__restrict__ Uout, int stage)
@@ -265,28 +276,36 @@ __global__ __launch_bounds__(64) void mesh_forward_kernel(int m, int nmzi, const
     const int b = blockIdx.x;
     PhaseFactors pf{phases + (size_t)b * 2 * nmzi, stage ? Ush + m * m : nullptr};
     pf.stage(nmzi, threadIdx.x, blockDim.x);
-    const int c = threadIdx.x;
-    if (c >= m) return;
-    for (int r = 0; r < m; ++r) Ush[r * m + c] = Cd{r == c ? 1.0 : 0.0, 0.0};
-    int k = 0;
-    for (int col = 0; col < m; ++col)
-        for (int p0 = col % 2; p0 + 1 < m; p0 += 2, ++k) {
+    const int lane = threadIdx.x, gc = mesh_lanes_per_mzi(m), i = lane / gc, g = lane % gc;
+    for (int e = lane; e < m * m; e += 64) Ush[e] = Cd{e / m == e % m ? 1.0 : 0.0, 0.0};
+    __syncthreads();
+    int k0 = 0;
+    for (int col = 0; col < m; ++col) {
+        const int cnt = (m - col % 2) / 2;
+        if (i < cnt) {
+            const int p0 = col % 2 + 2 * i;
             Cd B[4], dA[4], dB[4];
-            pf.block(k, B, dA, dB);
-            const Cd x0 = Ush[p0 * m + c], x1 = Ush[(p0 + 1) * m + c];
-            Ush[p0 * m + c] = cadd(cmul(B[0], x0), cmul(B[1], x1));
-            Ush[(p0 + 1) * m + c] = cadd(cmul(B[2], x0), cmul(B[3], x1));
+            pf.block(k0 + i, B, dA, dB);
+            for (int c = g; c < m; c += gc) {
+                const Cd x0 = Ush[p0 * m + c], x1 = Ush[(p0 + 1) * m + c];
+                Ush[p0 * m + c] = cadd(cmul(B[0], x0), cmul(B[1], x1));
+                Ush[(p0 + 1) * m + c] = cadd(cmul(B[2], x0), cmul(B[3], x1));
+            }
         }
-    for (int r = 0; r < m; ++r) {
-        const Cd v = Ush[r * m + c];
-        Uout[(size_t)b * m * m + (size_t)r * m + c] = C{(T)v.x, (T)v.y};
+        k0 += cnt;
+        __syncthreads();
+    }
+    for (int e = lane; e < m * m; e += 64) {
+        const Cd v = Ush[e];
+        Uout[(size_t)b * m * m + e] = C{(T)v.x, (T)v.y};
     }
 }
 
 // Reverse sweep: with U = L_k T_k R_k, P = L_k^H G_U and Q = L_k^H U = T_k R_k,
 //   dL/dphi = Re sum conj(P) o (dT_k T_k^H Q),
-// then P <- T_k^H P and Q <- T_k^H Q move to the previous MZI.  The sum over
-// columns is a wave reduction.
+// then P <- T_k^H P and Q <- T_k^H Q move to the previous column (the MZIs of a
+// column commute, so they share P and Q).  Each MZI's sum over matrix columns
+// is per lane, then a reduction over its gc lanes in a fixed order.
 template <typename T>
 __global__ __launch_bounds__(64) void mesh_backward_kernel(int m, int nmzi, const double *__restrict__ phases,
                                                            const typename Cb<T>::type *__restrict__ GU,
@@ -298,69 +317,74 @@ __global__ __launch_bounds__(64) void mesh_backward_kernel(int m, int nmzi, cons
     const int b = blockIdx.x;
     PhaseFactors pf{phases + (size_t)b * 2 * nmzi, stage ? sh + 2 * m * m : nullptr};
     pf.stage(nmzi, threadIdx.x, blockDim.x);
-    const int c = threadIdx.x;
-    const bool own = c < m;
+    const int lane = threadIdx.x, gc = mesh_lanes_per_mzi(m), i = lane / gc, g = lane % gc;
     // Q = U (rebuilt here), P = G_U
-    if (own)
-        for (int r = 0; r < m; ++r) {
-            Q[r * m + c] = Cd{r == c ? 1.0 : 0.0, 0.0};
-            const auto g = GU[(size_t)b * m * m + (size_t)r * m + c];
-            P[r * m + c] = Cd{(double)g.x, (double)g.y};
-        }
-    int k = 0;
-    for (int col = 0; col < m; ++col)
-        for (int p0 = col % 2; p0 + 1 < m; p0 += 2, ++k) {
-            if (!own) continue;
-            Cd B[4], dA[4], dB[4];
-            pf.block(k, B, dA, dB);
-            const Cd x0 = Q[p0 * m + c], x1 = Q[(p0 + 1) * m + c];
-            Q[p0 * m + c] = cadd(cmul(B[0], x0), cmul(B[1], x1));
-            Q[(p0 + 1) * m + c] = cadd(cmul(B[2], x0), cmul(B[3], x1));
-        }
-    // MZIs in reverse: column by column from the last, top pair last within a column
-    k = nmzi;
-    for (int col = m - 1; col >= 0; --col) {
-        const int cnt = (m - 1 - (col % 2) + 1) / 2;
-        for (int i = cnt - 1; i >= 0; --i) {
-            --k;
+    for (int e = lane; e < m * m; e += 64) {
+        Q[e] = Cd{e / m == e % m ? 1.0 : 0.0, 0.0};
+        const auto v = GU[(size_t)b * m * m + e];
+        P[e] = Cd{(double)v.x, (double)v.y};
+    }
+    __syncthreads();
+    int k0 = 0;
+    for (int col = 0; col < m; ++col) {
+        const int cnt = (m - col % 2) / 2;
+        if (i < cnt) {
             const int p0 = col % 2 + 2 * i;
             Cd B[4], dA[4], dB[4];
-            pf.block(k, B, dA, dB);
+            pf.block(k0 + i, B, dA, dB);
+            for (int c = g; c < m; c += gc) {
+                const Cd x0 = Q[p0 * m + c], x1 = Q[(p0 + 1) * m + c];
+                Q[p0 * m + c] = cadd(cmul(B[0], x0), cmul(B[1], x1));
+                Q[(p0 + 1) * m + c] = cadd(cmul(B[2], x0), cmul(B[3], x1));
+            }
+        }
+        k0 += cnt;
+        __syncthreads();
+    }
+    // columns in reverse
+    for (int col = m - 1; col >= 0; --col) {
+        const int cnt = (m - col % 2) / 2;
+        k0 -= cnt;
+        double va = 0.0, vb = 0.0;
+        if (i < cnt) {
+            const int p0 = col % 2 + 2 * i;
+            Cd B[4], dA[4], dB[4];
+            pf.block(k0 + i, B, dA, dB);
             // D = dT T^H restricted to rows p0, p0+1 (2x2): D = dB B^H
             Cd Da[4], Db[4];
             for (int r = 0; r < 2; ++r)
-                for (int s = 0; s < 2; ++s) {
-                    Da[2 * r + s] =
-                        cadd(cmul(dA[2 * r], cconj(B[2 * s])), cmul(dA[2 * r + 1], cconj(B[2 * s + 1])));
-                    Db[2 * r + s] =
-                        cadd(cmul(dB[2 * r], cconj(B[2 * s])), cmul(dB[2 * r + 1], cconj(B[2 * s + 1])));
+                for (int s2 = 0; s2 < 2; ++s2) {
+                    Da[2 * r + s2] =
+                        cadd(cmul(dA[2 * r], cconj(B[2 * s2])), cmul(dA[2 * r + 1], cconj(B[2 * s2 + 1])));
+                    Db[2 * r + s2] =
+                        cadd(cmul(dB[2 * r], cconj(B[2 * s2])), cmul(dB[2 * r + 1], cconj(B[2 * s2 + 1])));
                 }
-            double va = 0.0, vb = 0.0;
-            if (own) {
+            for (int c = g; c < m; c += gc) {
                 const Cd q0 = Q[p0 * m + c], q1 = Q[(p0 + 1) * m + c];
                 const Cd pp0 = P[p0 * m + c], pp1 = P[(p0 + 1) * m + c];
                 const Cd ya0 = cadd(cmul(Da[0], q0), cmul(Da[1], q1));
                 const Cd ya1 = cadd(cmul(Da[2], q0), cmul(Da[3], q1));
                 const Cd yb0 = cadd(cmul(Db[0], q0), cmul(Db[1], q1));
                 const Cd yb1 = cadd(cmul(Db[2], q0), cmul(Db[3], q1));
-                va = pp0.x * ya0.x + pp0.y * ya0.y + pp1.x * ya1.x + pp1.y * ya1.y;
-                vb = pp0.x * yb0.x + pp0.y * yb0.y + pp1.x * yb1.x + pp1.y * yb1.y;
+                va += pp0.x * ya0.x + pp0.y * ya0.y + pp1.x * ya1.x + pp1.y * ya1.y;
+                vb += pp0.x * yb0.x + pp0.y * yb0.y + pp1.x * yb1.x + pp1.y * yb1.y;
                 // P <- T^H P, Q <- T^H Q on rows p0, p0+1
                 Q[p0 * m + c] = cadd(cmul(cconj(B[0]), q0), cmul(cconj(B[2]), q1));
                 Q[(p0 + 1) * m + c] = cadd(cmul(cconj(B[1]), q0), cmul(cconj(B[3]), q1));
                 P[p0 * m + c] = cadd(cmul(cconj(B[0]), pp0), cmul(cconj(B[2]), pp1));
                 P[(p0 + 1) * m + c] = cadd(cmul(cconj(B[1]), pp0), cmul(cconj(B[3]), pp1));
             }
-#pragma unroll
-            for (int o = 32; o > 0; o >>= 1) {
-                va += __shfl_xor(va, o, 64);
-                vb += __shfl_xor(vb, o, 64);
-            }
-            if (c == 0) {
-                gphases[(size_t)b * 2 * nmzi + 2 * k] = va;
-                gphases[(size_t)b * 2 * nmzi + 2 * k + 1] = vb;
-            }
         }
+        // sum over the gc lanes of each MZI (aligned groups of a power of two)
+        for (int o = gc / 2; o > 0; o >>= 1) {
+            va += __shfl_xor(va, o, 64);
+            vb += __shfl_xor(vb, o, 64);
+        }
+        if (i < cnt && g == 0) {
+            gphases[(size_t)b * 2 * nmzi + 2 * (k0 + i)] = va;
+            gphases[(size_t)b * 2 * nmzi + 2 * (k0 + i) + 1] = vb;
+        }
+        __syncthreads();
     }
 }
 
