@@ -42,6 +42,33 @@ def test_brute_force_definition_small_by_hand():
     assert oracle.perm(B, "brute") == pytest.approx(want)
 
 
+@pytest.mark.parametrize("n", [10, 12])
+def test_ryser_against_40_digit_glynn(n):
+    """At n = 10 and 12, where brute force is out of reach, the oracle's Ryser
+    (extended-precision sums) against Glynn's formula evaluated with 40
+    significant digits: relative error below 1e-13, the accuracy the complex128
+    parity bar (1e-12) needs from its reference."""
+    mpmath = pytest.importorskip("mpmath")
+    mpmath.mp.dps = 40
+    rng = np.random.default_rng(500 + n)
+    A = rand_c(rng, (n, n)) / math.sqrt(2 * n)
+    Am = [[mpmath.mpc(float(A[r, c].real), float(A[r, c].imag)) for c in range(n)] for r in range(n)]
+    total = mpmath.mpc(0)
+    for mask in range(1 << (n - 1)):  # delta_1 = +1; the others from the bits of mask
+        d = [1] + [(-1 if (mask >> i) & 1 else 1) for i in range(n - 1)]
+        prod = mpmath.mpc(1)
+        for c in range(n):
+            col = mpmath.mpc(0)
+            for r in range(n):
+                col += Am[r][c] if d[r] > 0 else -Am[r][c]
+            prod *= col
+        total += prod if sum(1 for x in d if x < 0) % 2 == 0 else -prod
+    ref = total / mpmath.mpf(2) ** (n - 1)
+    got = oracle.perm(A, "ryser")
+    err = abs(mpmath.mpc(got.real, got.imag) - ref) / abs(ref)
+    assert float(err) < 1e-13, float(err)
+
+
 @pytest.mark.parametrize("method", ["ryser", "glynn"])
 @pytest.mark.parametrize("n", [1, 2, 5, 8, 12])
 def test_perm_all_ones_is_factorial(method, n):
