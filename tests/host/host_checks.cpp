@@ -22,19 +22,45 @@ static int failures = 0;
         }                                                 \
     } while (0)
 
+static int64_t binom(int a, int b)
+{
+    if (b < 0 || a < b) return 0;
+    int64_t v = 1;
+    for (int i = 1; i <= b; ++i) v = v * (a - b + i) / i;
+    return v;
+}
+
+// rank <-> state is a bijection onto [0, C(m+n-1, n)); ranks follow colex order
+// (lexicographic on the occupations read from the last mode); and the states
+// whose highest photon sits at c = d_n + n - 1 fill ranks [C(c, n), C(c+1, n)).
 static void fock_bijection(int m, int n)
 {
     int64_t M = 0;
-    CHECK(slos_fock_count(m, n, &M) == SLOS_OK, "count m=%d n=%d", m, n);
-    std::vector<int32_t> s(m);
+    CHECK(slos_fock_count(m, n, &M) == SLOS_OK && M == binom(m + n - 1, n), "count m=%d n=%d", m, n);
+    std::vector<int32_t> s(m), prev(m);
     for (int64_t r = 0; r < M; ++r) {
         CHECK(slos_fock_unrank(m, n, r, s.data()) == SLOS_OK, "unrank %lld", (long long)r);
-        int sum = 0;
-        for (int j = 0; j < m; ++j) sum += s[j];
+        int sum = 0, top = -1;
+        for (int j = 0; j < m; ++j) {
+            sum += s[j];
+            if (s[j] > 0) top = j;
+        }
         CHECK(sum == n, "unrank %lld sums to %d", (long long)r, sum);
         int64_t back = -1;
         CHECK(slos_fock_rank(m, n, s.data(), &back) == SLOS_OK && back == r, "rank(unrank(%lld)) = %lld",
               (long long)r, (long long)back);
+        if (n > 0) {
+            const int c = top + n - 1;
+            CHECK(binom(c, n) <= r && r < binom(c + 1, n), "m=%d n=%d rank %lld outside its top block", m, n,
+                  (long long)r);
+        }
+        if (r > 0) {
+            int j = m - 1;
+            while (j >= 0 && s[j] == prev[j]) --j;
+            CHECK(j >= 0 && s[j] > prev[j], "m=%d n=%d ranks %lld, %lld out of colex order", m, n,
+                  (long long)r - 1, (long long)r);
+        }
+        prev = s;
     }
 }
 
@@ -78,8 +104,8 @@ static void host_plan(int m, const std::vector<int32_t> &T, int flags, const slo
 int main()
 {
     // Fock-space arithmetic
-    for (int m = 1; m <= 7; ++m)
-        for (int n = 0; n <= 5; ++n) fock_bijection(m, n);
+    for (int m = 1; m <= 14; ++m)
+        for (int n = 0; n <= 7; ++n) fock_bijection(m, n);
     int64_t c = 0;
     CHECK(slos_fock_count(255, 32, &c) == SLOS_ERR_SIZE_OVERFLOW || c > 0, "count(255, 32)");
     CHECK(slos_fock_count(0, 3, &c) != SLOS_OK, "m = 0 accepted");

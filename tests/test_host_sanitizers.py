@@ -4,7 +4,8 @@ plan.cpp (host C++, no device code) is compiled with g++ and the sanitizers,
 linked with stand-ins for the kernel launchers (tests/host/stubs.cpp) and the
 HIP runtime library, and driven by tests/host/host_checks.cpp: Fock-space
 arithmetic, host-only plans over many shapes (leaf tilings, inner tables and
-descriptors up to m = 255 and m = 24, n = 12), option validation and error
+descriptors up to m = 255 and m = 24, n = 12), the rank bijection, colex order and
+block structure for every m <= 14, n <= 7, option validation and error
 paths, and the batch and source planners up to their device check.  Any
 sanitizer report, leak or failed check fails the test.  Needs no GPU.
 """
