@@ -227,8 +227,10 @@ int slos_sample(slos_plan_t plan, const void *probs, const double *r, int64_t co
  * int32 occupations, each summing to n), without the full distribution: for
  * each target the recurrence of Section 3.2.3 runs over the states t <= S
  * alone, prod_j (s_j + 1) of them (2^n without bunching).  One workgroup per
- * target holds that sub-lattice in LDS, so prod_j (s_j + 1) must stay below
- * about 10K states (c64) or 6.7K (c128); larger targets are rejected.  U: device
+ * target holds that sub-lattice's amplitudes in LDS, so prod_j (s_j + 1) must
+ * stay within 19,456 states (c64) or 9,728 (c128); larger targets are
+ * rejected.  Targets with the same multiset of occupations share one
+ * layer-sorted table of their sub-lattice, built per call.  U: device
  * m x m (plan dtype); out: device, count amplitudes (plan dtype), out[i] =
  * a(target i).  Synchronises the stream before returning (the target
  * descriptors are uploaded from host memory).

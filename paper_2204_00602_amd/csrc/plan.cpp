@@ -13,9 +13,11 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <unordered_map>
 #include <new>
 #include <queue>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "slos_ext.h"
@@ -152,6 +154,16 @@ void order_leaves(std::vector<LeafRec> &lv, int d)
 
 } // namespace
 
+// FNV-1a over the bytes of a short key
+struct ByteVecHash {
+    size_t operator()(const std::vector<uint8_t> &v) const
+    {
+        uint64_t h = 1469598103934665603ull;
+        for (uint8_t b : v) h = (h ^ b) * 1099511628211ull;
+        return (size_t)h;
+    }
+};
+
 struct slos_plan_s {
     int m = 0, n = 0, flags = 0;
     bool c64 = true, comp = false, keep = false, host_only = false;
@@ -194,6 +206,18 @@ struct slos_plan_s {
     int64_t *d_pk_ends = nullptr;     // C(K+n-1, n) for K = 1..m
     double *d_ps_partials = nullptr;  // post-selection partial sums + reduction stage
     SelectTarget *d_sel = nullptr;    // target descriptors of the last slos_select call
+    SelectTarget *h_sel = nullptr;    // their pinned host staging (sel_cap entries)
+    std::vector<SelectTarget> sel_build;  // built here, then copied to the staging
+    // sub-lattice tables of every occupation multiset seen by slos_select so
+    // far (kept across calls; re-uploaded when a call adds one)
+    std::unordered_map<std::vector<uint8_t>, uint32_t, ByteVecHash> sel_pat_of;
+    std::unordered_map<uint64_t, uint32_t> sel_key;  // multiset key -> pattern
+    std::vector<SelectPattern> sel_pats;
+    std::vector<uint16_t> sel_state;
+    std::vector<uint32_t> sel_mask;
+    size_t sel_uploaded = 0;          // patterns on the device
+    unsigned char *d_sel_tab = nullptr;  // patterns, then states, then masks
+    size_t sel_tab_cap = 0, sel_st_bytes = 0;
     PsType *d_ps_types = nullptr;     // inner types of the last layer, table runs
     uint32_t *d_ps_type_off = nullptr;// first table entry per inner-type index
     uint8_t *d_ps_low = nullptr;      // group counts of every low state (per call)
@@ -426,6 +450,12 @@ struct slos_plan_s {
         d_ps_partials = nullptr;
         f(d_sel);
         d_sel = nullptr;
+        if (h_sel) (void)hipHostFree(h_sel);
+        h_sel = nullptr;
+        f(d_sel_tab);
+        d_sel_tab = nullptr;
+        sel_tab_cap = 0;
+        sel_uploaded = 0;
         f(d_ps_types);
         d_ps_types = nullptr;
         f(d_ps_type_off);
@@ -1322,6 +1352,60 @@ int slos_postselect(slos_plan_t p, const void *probs, const int32_t *group_of_mo
     return SLOS_OK;
 }
 
+// The sub-lattice of one occupation multiset (occupations descending): its
+// states in mixed radix, listed layer by layer, each with the mask of its
+// non-zero digits; appended to the plan's pools.
+static uint32_t select_pattern(slos_plan_s *p, const std::vector<uint8_t> &key, uint32_t R)
+{
+    auto it = p->sel_pat_of.find(key);
+    if (it != p->sel_pat_of.end()) return it->second;
+    const int n = p->n;
+    SelectPattern pt{};
+    pt.R = R;
+    pt.nocc = (uint32_t)key.size();
+    pt.off = (uint32_t)p->sel_state.size();
+    uint32_t st = 1;
+    for (size_t q = 0; q < key.size(); ++q) {
+        pt.stride[q] = st;
+        st *= (uint32_t)key[q] + 1u;
+    }
+    std::vector<uint8_t> layer(R);
+    std::vector<uint32_t> msk(R), cnt(n + 2, 0);
+    std::vector<uint32_t> digit(key.size(), 0);  // digits of x, counted up in mixed radix
+    for (uint32_t x = 0; x < R; ++x) {
+        uint32_t k = 0, mk = 0;
+        for (size_t q = 0; q < key.size(); ++q) {
+            k += digit[q];
+            if (digit[q]) mk |= 1u << q;
+        }
+        layer[x] = (uint8_t)k;
+        msk[x] = mk;
+        ++cnt[k];
+        for (size_t q = 0; q < key.size(); ++q) {  // x + 1
+            if (++digit[q] <= key[q]) break;
+            digit[q] = 0;
+        }
+    }
+    uint32_t run = 0;
+    for (int k = 0; k <= n; ++k) {
+        pt.lstart[k] = run;
+        run += cnt[k];
+        cnt[k] = pt.lstart[k];
+    }
+    pt.lstart[n + 1] = run;
+    p->sel_state.resize(p->sel_state.size() + R);
+    p->sel_mask.resize(p->sel_mask.size() + R);
+    for (uint32_t x = 0; x < R; ++x) {
+        const uint32_t pos = pt.off + cnt[layer[x]]++;
+        p->sel_state[pos] = (uint16_t)x;
+        p->sel_mask[pos] = msk[x];
+    }
+    const uint32_t pi = (uint32_t)p->sel_pats.size();
+    p->sel_pats.push_back(pt);
+    p->sel_pat_of.emplace(key, pi);
+    return pi;
+}
+
 int slos_select(slos_plan_t p, const void *U, const int32_t *targets, int64_t count, void *out, void *stream)
 {
     int rc = check_plan(p);
@@ -1331,59 +1415,165 @@ int slos_select(slos_plan_t p, const void *U, const int32_t *targets, int64_t co
     if (!U || !targets || !out) return fail(SLOS_ERR_INVALID_ARG, "U, targets and out must not be NULL");
     const int m = p->m, n = p->n;
     const size_t es = p->elem();
-    // largest sub-lattice whose amplitudes, layers and masks fit a workgroup's LDS
-    const uint64_t r_cap = SLOS_LDS_DYNAMIC_MAX / (es + 7);  // A, mask, sorted index, layer
-    std::vector<SelectTarget> h;
-    uint32_t r_max = 1;
-    try {
-        h.resize((size_t)count);
-    } catch (std::bad_alloc &) {
-        return fail(SLOS_ERR_OOM, "host allocation of %lld target descriptors failed", (long long)count);
-    }
-    for (int64_t i = 0; i < count; ++i) {
-        const int32_t *s = targets + (size_t)i * m;
-        SelectTarget t{};
-        uint64_t R = 1;
-        int tot = 0;
-        double f = 1.0;
-        for (int j = 0; j < m; ++j) {
-            if (s[j] < 0) return fail(SLOS_ERR_INVALID_ARG, "target %lld has a negative occupation", (long long)i);
-            if (s[j] == 0) continue;
-            tot += s[j];
-            if (tot > n) break;
-            t.mode[t.nocc] = (uint8_t)j;
-            t.mult[t.nocc] = (uint8_t)s[j];
-            ++t.nocc;
-            R *= (uint64_t)s[j] + 1;
-            for (int v = 2; v <= s[j]; ++v) f *= v;
-            if (R > r_cap) break;
-        }
-        if (R > r_cap)
-            return fail(SLOS_ERR_INVALID_ARG,
-                        "target %lld: prod(s_j + 1) exceeds %llu states (one workgroup's LDS)", (long long)i,
-                        (unsigned long long)r_cap);
-        if (tot != n)
-            return fail(SLOS_ERR_INVALID_ARG, "target %lld does not hold n = %d photons", (long long)i, n);
-        t.R = (uint32_t)R;
-        t.fac = std::sqrt(f) * p->norm_t;
-        r_max = std::max(r_max, t.R);
-        h[(size_t)i] = t;
-    }
+    // largest sub-lattice whose amplitudes fit a workgroup's LDS
+    const uint64_t r_cap = SLOS_LDS_DYNAMIC_MAX / es;
     if ((size_t)count > p->sel_cap) {
         if (p->d_sel) (void)hipFree(p->d_sel);
+        if (p->h_sel) (void)hipHostFree(p->h_sel);
         p->d_sel = nullptr;
+        p->h_sel = nullptr;
         p->sel_cap = 0;
         if ((rc = alloc_dev((void **)&p->d_sel, (size_t)count * sizeof(SelectTarget), "target descriptors")))
             return rc;
+        hipError_t he = hipHostMalloc((void **)&p->h_sel, (size_t)count * sizeof(SelectTarget), hipHostMallocDefault);
+        if (he != hipSuccess) {
+            p->h_sel = nullptr;
+            return hip_fail(he, "pinned staging of the target descriptors");
+        }
         p->sel_cap = (size_t)count;
     }
-    // the descriptors are read by the kernel: upload in order on the stream, then wait
-    hipError_t e = hipMemcpyAsync(p->d_sel, h.data(), (size_t)count * sizeof(SelectTarget), hipMemcpyHostToDevice,
+    // Targets are prepared in parallel (host threads over contiguous ranges):
+    // occupied modes in canonical order, the normalisation, and the multiset of
+    // occupations as a 64-bit key (the occupations in descending order, each
+    // written as that many one bits and a zero: at most n + 32 bits).  Patterns
+    // are then assigned in one serial pass over the keys.
+    std::vector<uint64_t> keys;
+    std::vector<uint32_t> rs;
+    try {
+        p->sel_build.resize((size_t)count);
+        keys.resize((size_t)count);
+        rs.resize((size_t)count);
+    } catch (std::bad_alloc &) {
+        return fail(SLOS_ERR_OOM, "host allocation of %lld target descriptors failed", (long long)count);
+    }
+    std::vector<int64_t> bad_at(1, -1);
+    std::vector<int> bad_kind(1, 0);
+    auto prepare = [&](int64_t lo, int64_t hi, int64_t &bad, int &kind) {
+        int occ_n[SLOS_SELECT_MAX_OCC], occ_j[SLOS_SELECT_MAX_OCC];
+        for (int64_t i = lo; i < hi; ++i) {
+            const int32_t *s = targets + (size_t)i * m;
+            int tot = 0, nocc = 0;
+            double f = 1.0;
+            uint64_t R = 1;
+            for (int j = 0; j < m; ++j) {
+                const int v = s[j];
+                if (v == 0) continue;
+                if (v < 0 || tot + v > n) {
+                    tot = v < 0 ? -1 : n + 1;
+                    break;
+                }
+                tot += v;
+                int q = nocc++;  // insert: occupation descending, then mode ascending
+                while (q > 0 && occ_n[q - 1] < v) {
+                    occ_n[q] = occ_n[q - 1];
+                    occ_j[q] = occ_j[q - 1];
+                    --q;
+                }
+                occ_n[q] = v;
+                occ_j[q] = j;
+                R *= (uint64_t)v + 1;
+                for (int w = 2; w <= v; ++w) f *= w;
+                if (R > r_cap) break;
+            }
+            if (tot != n || R > r_cap) {
+                bad = i;
+                kind = tot < 0 ? 1 : (R > r_cap ? 2 : 3);
+                return;
+            }
+            uint64_t key = 0;
+            for (int q = 0; q < nocc; ++q) key = (key << (occ_n[q] + 1)) | (((1ull << occ_n[q]) - 1) << 1);
+            keys[(size_t)i] = key;
+            rs[(size_t)i] = (uint32_t)R;
+            SelectTarget &t = p->sel_build[(size_t)i];
+            t = SelectTarget{};
+            t.nocc = (uint32_t)nocc;
+            for (int q = 0; q < nocc; ++q) t.mode[q] = (uint8_t)occ_j[q];
+            t.fac = std::sqrt(f) * p->norm_t;
+        }
+    };
+    const int nth = count >= 4096 ? (int)std::min<unsigned>(8u, std::max(1u, std::thread::hardware_concurrency())) : 1;
+    bad_at.assign(nth, -1);
+    bad_kind.assign(nth, 0);
+    if (nth == 1) {
+        prepare(0, count, bad_at[0], bad_kind[0]);
+    } else {
+        std::vector<std::thread> pool;
+        try {
+            for (int w = 0; w < nth; ++w)
+                pool.emplace_back(prepare, count * w / nth, count * (w + 1) / nth, std::ref(bad_at[w]),
+                                  std::ref(bad_kind[w]));
+        } catch (...) {
+            for (auto &th : pool) th.join();
+            return fail(SLOS_ERR_OOM, "could not start the host threads that prepare the targets");
+        }
+        for (auto &th : pool) th.join();
+    }
+    for (int w = 0; w < nth; ++w) {
+        if (bad_at[w] < 0) continue;
+        const long long i = (long long)bad_at[w];
+        if (bad_kind[w] == 1) return fail(SLOS_ERR_INVALID_ARG, "target %lld has a negative occupation", i);
+        if (bad_kind[w] == 2)
+            return fail(SLOS_ERR_INVALID_ARG, "target %lld: prod(s_j + 1) exceeds %llu states (one workgroup's LDS)",
+                        i, (unsigned long long)r_cap);
+        return fail(SLOS_ERR_INVALID_ARG, "target %lld does not hold n = %d photons", i, n);
+    }
+    uint32_t r_max = 1;
+    try {
+        std::vector<uint8_t> mult;
+        for (int64_t i = 0; i < count; ++i) {
+            auto it = p->sel_key.find(keys[(size_t)i]);
+            uint32_t pi;
+            if (it != p->sel_key.end()) {
+                pi = it->second;
+            } else {
+                mult.clear();  // decode the key: runs of ones, most significant first
+                const SelectTarget &t = p->sel_build[(size_t)i];
+                const int32_t *s = targets + (size_t)i * m;
+                for (uint32_t q = 0; q < t.nocc; ++q) mult.push_back((uint8_t)s[t.mode[q]]);
+                pi = select_pattern(p, mult, rs[(size_t)i]);
+                p->sel_key.emplace(keys[(size_t)i], pi);
+            }
+            p->sel_build[(size_t)i].pattern = pi;
+            r_max = std::max(r_max, rs[(size_t)i]);
+        }
+    } catch (std::bad_alloc &) {
+        return fail(SLOS_ERR_OOM, "host allocation of the sub-lattice tables failed");
+    }
+    // tables: patterns, then the state pool (2-byte entries, padded to 16
+    // bytes), then the masks; uploaded again only when this call added patterns
+    const size_t npat = p->sel_pats.size();
+    const size_t pat_bytes = npat * sizeof(SelectPattern);
+    const size_t st_bytes = (p->sel_state.size() * sizeof(uint16_t) + 15) / 16 * 16;
+    const size_t tab_bytes = pat_bytes + st_bytes + p->sel_mask.size() * sizeof(uint32_t);
+    if (npat != p->sel_uploaded) {
+        if (tab_bytes > p->sel_tab_cap) {
+            if (p->d_sel_tab) (void)hipFree(p->d_sel_tab);
+            p->d_sel_tab = nullptr;
+            p->sel_tab_cap = 0;
+            if ((rc = alloc_dev((void **)&p->d_sel_tab, 2 * tab_bytes, "sub-lattice tables"))) return rc;
+            p->sel_tab_cap = 2 * tab_bytes;
+        }
+        hipError_t e = hipMemcpy(p->d_sel_tab, p->sel_pats.data(), pat_bytes, hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(p->d_sel_tab + pat_bytes, p->sel_state.data(), p->sel_state.size() * sizeof(uint16_t),
+                          hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(p->d_sel_tab + pat_bytes + st_bytes, p->sel_mask.data(),
+                          p->sel_mask.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_fail(e, "sub-lattice table upload");
+        p->sel_uploaded = npat;
+        p->sel_st_bytes = st_bytes;
+    }
+    std::memcpy(p->h_sel, p->sel_build.data(), (size_t)count * sizeof(SelectTarget));
+    hipError_t e = hipMemcpyAsync(p->d_sel, p->h_sel, (size_t)count * sizeof(SelectTarget), hipMemcpyHostToDevice,
                                   (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "target upload");
     SelectParams sp{};
     sp.U = U;
     sp.targets = p->d_sel;
+    sp.patterns = (const SelectPattern *)p->d_sel_tab;
+    sp.state = (const uint16_t *)(p->d_sel_tab + pat_bytes);
+    sp.mask = (const uint32_t *)(p->d_sel_tab + pat_bytes + p->sel_st_bytes);
     sp.count = count;
     sp.out = out;
     sp.r_max = r_max;
@@ -1392,7 +1582,7 @@ int slos_select(slos_plan_t p, const void *U, const int32_t *targets, int64_t co
     for (int k = 0; k < n; ++k) sp.cols[k] = (uint8_t)p->photons[k];
     int ke = slos_launch_select(sp, p->c64 ? 1 : 0, stream);
     if (ke) return hip_fail((hipError_t)ke, "selected-output kernel");
-    e = hipStreamSynchronize((hipStream_t)stream);  // h must outlive the copy
+    e = hipStreamSynchronize((hipStream_t)stream);  // the staging buffer is reused by the next call
     if (e != hipSuccess) return hip_fail(e, "selected-output synchronisation");
     return SLOS_OK;
 }

@@ -54,16 +54,30 @@ int slos_launch_postselect_table(const PostselectParams &p, int c64, const int64
 
 // selected outputs (select.hip)
 #define SLOS_SELECT_MAX_OCC 32
+// A target's sub-lattice {t <= S} depends only on the multiset of its
+// occupations once the occupied modes are put in a canonical order
+// (occupation descending, then mode), so targets share one table per multiset:
+// the states numbered in mixed radix over the digits (radix s_q + 1), listed by
+// layer |t|, each with the mask of its non-zero digits.
+struct SelectPattern {
+    uint32_t R;                          // prod over digits of (s_q + 1)
+    uint32_t nocc;                       // digits
+    uint32_t off;                        // its states in the state and mask pools
+    uint32_t lstart[SLOS_MAX_PHOTONS + 2];  // layer k: pool positions [off + lstart[k], off + lstart[k+1])
+    uint32_t stride[SLOS_SELECT_MAX_OCC];   // t - e_q = index - stride[q]
+};
 struct SelectTarget {
-    uint32_t R;                          // prod over occupied modes of (s_j + 1)
+    uint32_t pattern;                    // its sub-lattice table
     uint32_t nocc;                       // occupied modes of the target
     double fac;                          // sqrt(prod s_j!) / sqrt(prod t_i!)
-    uint8_t mode[SLOS_SELECT_MAX_OCC];   // occupied modes, ascending
-    uint8_t mult[SLOS_SELECT_MAX_OCC];   // their occupations
+    uint8_t mode[SLOS_SELECT_MAX_OCC];   // occupied modes in the pattern's digit order
 };
 struct SelectParams {
     const void *U;                // m x m, plan dtype
     const SelectTarget *targets;  // device
+    const SelectPattern *patterns;  // device
+    const uint16_t *state;        // per pattern, its states by layer (mixed-radix index)
+    const uint32_t *mask;         // the non-zero digits of each listed state
     int64_t count;
     void *out;                    // count amplitudes, plan dtype
     uint32_t r_max;               // largest R of the call (LDS sizing)

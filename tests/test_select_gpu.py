@@ -87,6 +87,12 @@ def test_select_edge_cases():
     with pytest.raises(slos.SlosError):
         p.select(_u(np.eye(3), "c128"), [[3, -1, 0]])
     assert p.select(_u(np.eye(3), "c128"), np.zeros((0, 3), np.int32)).numel() == 0
-    big = slos.Plan([1] * 14, "c64")
-    with pytest.raises(slos.SlosError):                  # 2^14 states exceed one workgroup's LDS
-        big.select(_u(np.eye(14), "c64"), [[1] * 14])
+    # the sub-lattice must fit one workgroup's LDS: 19,456 complex64 or 9,728
+    # complex128 states
+    big = slos.Plan([1] * 14, "c64")                     # 2^14 states fit in complex64
+    a = big.select(_u(np.eye(14), "c64"), [[1] * 14]).cpu().numpy()
+    assert abs(a[0] - 1.0) <= 1e-6
+    with pytest.raises(slos.SlosError):                  # not in complex128
+        slos.Plan([1] * 14, "c128").select(_u(np.eye(14), "c128"), [[1] * 14])
+    with pytest.raises(slos.SlosError):                  # 2^15 exceed it in complex64 too
+        slos.Plan([1] * 15, "c64").select(_u(np.eye(15), "c64"), [[1] * 15])
