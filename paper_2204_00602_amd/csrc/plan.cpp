@@ -202,7 +202,7 @@ struct slos_plan_s {
     uint64_t g_stride = 0;            // elements per instance in d_g[b]
     uint64_t bpart_stride = 0;        // double2 per instance in d_bpart
     uint32_t *d_tickets = nullptr;    // SLOS_XCDS ticket counters per layer
-    double *d_cdf = nullptr;          // block prefix of the last slos_cdf input (nb + 1), run prefixes, chunk sums
+    double *d_cdf = nullptr;          // block prefix of the last slos_cdf input (nb + 1), run prefixes, chunk sums, search tree
     int64_t *d_pk_ends = nullptr;     // C(K+n-1, n) for K = 1..m
     double *d_ps_partials = nullptr;  // post-selection partial sums + reduction stage
     SelectTarget *d_sel = nullptr;    // target descriptors of the last slos_select call
@@ -854,7 +854,9 @@ int slos_plan_ex(int m, int n, const int32_t *input_state, int flags, const slos
         const uint64_t nsup = (nb + SLOS_CDF_BLOCK - 1) / SLOS_CDF_BLOCK;
         std::vector<int64_t> ends(m);
         for (int K = 1; K <= m; ++K) ends[K - 1] = (int64_t)p->B(K + n - 1, n);
-        if ((rc = alloc_dev((void **)&p->d_cdf, (nb + 1 + nsup + 1 + (uint64_t)(SLOS_CDF_BLOCK / 64) * nb) * sizeof(double),
+        if ((rc = alloc_dev((void **)&p->d_cdf,
+                            (nb + 1 + nsup + 1 + (uint64_t)(SLOS_CDF_BLOCK / 64) * nb +
+                             (uint64_t)cdf_tree_layout((int64_t)nb).total) * sizeof(double),
                             "cumulative probability table")) ||
             (rc = dev_upload(&p->d_pk_ends, ends.data(), ends.size(), "marginal bounds")) ||
             (rc = alloc_dev((void **)&p->d_ps_partials, (SLOS_PS_MAX_WAVES + SLOS_REDUCE_STAGE) * sizeof(double),

@@ -15,10 +15,12 @@
 // bp[0..nb] (bp[nb] = sum P), every step in a fixed order, so the table is
 // reproducible; the run prefixes stay after the table (sp = bp + nb + 1), and
 // the block kernel also keeps the sums of each block's 16 chunks of 64 states
-// (cs = sp + nsup + 1).  A sample finds its run with a 64-way search over sp,
-// its block with a 64-way search over that run's part of bp, its chunk from the
-// block's 16 chunk sums (one cache line), and then its state with a wave scan
-// of that chunk: about 400 bytes per sample instead of half a 4 KB block.
+// (cs = sp + nsup + 1), and a last pass copies every 16^l-th prefix into a
+// 16-ary search tree (after cs).  A sample takes 16 lanes, so a wave serves
+// four at once: it descends the tree, each level one 16-way step over 16
+// consecutive prefixes (one cache line), to its block, finds its chunk from the
+// block's 16 chunk sums (one line), and then its state with a 16-lane scan of
+// that chunk's 64 probabilities (four per lane): about 1 KB per sample.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -189,6 +191,19 @@ __global__ __launch_bounds__(256) void cdf_fix_kernel(double *__restrict__ bp, i
     if (gw == 0 && lane == 0) bp[nb] = sp[nsup];
 }
 
+// Levels 1.. of the search tree: level l entry i = bp[i * 16^l].
+__global__ __launch_bounds__(256) void cdf_tree_kernel(const double *__restrict__ bp, double *__restrict__ tree,
+                                                       CdfTree t)
+{
+    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t ni = (int64_t)gridDim.x * blockDim.x;
+    for (int l = 1; l < t.nlev; ++l) {
+        int64_t stride = 1;
+        for (int q = 0; q < l; ++q) stride *= 16;
+        for (int64_t i = i0; i < t.n[l]; i += ni) tree[t.off[l] + i] = bp[i * stride];
+    }
+}
+
 // pk[K-1] = sum of P over the first ends[K-1] states, K = 1..m; one wave per K.
 template <typename T>
 __global__ __launch_bounds__(256) void marginal_kernel(const T *__restrict__ P, const double *__restrict__ bp,
@@ -207,82 +222,102 @@ __global__ __launch_bounds__(256) void marginal_kernel(const T *__restrict__ P, 
     if (lane == 0) pk[K] = bp[b] + s;
 }
 
-// One wave per sample: ranks[s] = first state whose cumulative P exceeds r[s] * total.
+// Four samples per wave, 16 lanes each: ranks[s] = first state whose
+// cumulative P exceeds r[s] * total.  A group's lanes hold the same search state;
+// each step is one load instruction for all four groups.
 template <typename T>
 __global__ __launch_bounds__(256) void sample_kernel(const T *__restrict__ P, int64_t M, const double *__restrict__ bp,
                                                      int64_t nb, const double *__restrict__ r, int64_t count,
-                                                     int64_t *__restrict__ ranks)
+                                                     int64_t *__restrict__ ranks, CdfTree tr)
 {
     const int64_t nsup = (nb + SLOS_CDF_BLOCK - 1) / SLOS_CDF_BLOCK;
     const double *__restrict__ sp = bp + nb + 1;  // run prefixes, nsup + 1 entries
     const double *__restrict__ cs = sp + nsup + 1;  // chunk sums, kChunks per block
-    const int lane = threadIdx.x & 63;
+    const double *__restrict__ tree = cs + kChunks * nb;
+    const int lane = threadIdx.x & 63, g = lane >> 4, l16 = lane & 15;
     const int64_t gw = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
     const double total = bp[nb];
-    for (int64_t sidx = gw; sidx < count; sidx += nw) {
-        const double t = r[sidx] * total;
-        // the run of SLOS_CDF_BLOCK blocks first: largest s with sp[s] <= t over
-        // the small run-prefix table (cache resident), then the largest block b
-        // of that run with bp[b] <= t; both 64-way searches (the tables are
-        // non-decreasing and start at 0 <= t, so the predicate holds on a prefix)
-        int64_t lo = 0, hi = nsup;
-        while (hi - lo > 1) {
-            const int64_t step = (hi - lo + 63) / 64;
-            const int64_t pos = lo + (int64_t)lane * step;
-            const bool ok = pos < hi && sp[pos] <= t;
-            const uint64_t bal = __ballot(ok);
-            const int last = bal ? 63 - __builtin_clzll(bal) : 0;
-            lo = lo + (int64_t)last * step;
-            hi = min(lo + step, hi);
-        }
-        lo = lo * SLOS_CDF_BLOCK;
-        hi = min(lo + SLOS_CDF_BLOCK, nb);
-        while (hi - lo > 1) {
-            const int64_t step = (hi - lo + 63) / 64;
-            const int64_t pos = lo + (int64_t)lane * step;
-            const bool ok = pos < hi && bp[pos] <= t;
-            const uint64_t bal = __ballot(ok);
-            const int last = bal ? 63 - __builtin_clzll(bal) : 0;  // lane 0 holds for r >= 0
-            lo = lo + (int64_t)last * step;
-            hi = min(lo + step, hi);
+    // the group's 16 bits of a wave ballot
+    auto gbits = [&](bool pred) -> uint32_t { return (uint32_t)((__ballot(pred) >> (16 * g)) & 0xFFFFu); };
+    for (int64_t s0 = gw * 4; s0 < count; s0 += nw * 4) {
+        const int64_t sidx = s0 + g;
+        const bool live = sidx < count;
+        const double t = r[live ? sidx : s0] * total;
+        // down the tree: at each level the largest entry <= t among the 16
+        // children of the choice above (the tables are non-decreasing and
+        // start at 0 <= t, so the predicate holds on a prefix)
+        int64_t lo = 0;
+        for (int l = tr.nlev - 1; l >= 0; --l) {
+            const double *tab = l == 0 ? bp : tree + tr.off[l];
+            const int64_t first = lo * 16;  // < n[l]: entry lo above is bp[lo * 16^(l+1)]
+            const int64_t end = min(first + 16, tr.n[l]);
+            const uint32_t bal = gbits(first + l16 < end && tab[first + l16] <= t);
+            lo = first + (bal ? 31 - __builtin_clz(bal) : 0);  // lane 0 of the group holds: tab[first] <= t
         }
         // the block's chunk sums (one line): the first chunk whose running sum
         // exceeds t, else the last chunk of non-zero probability
         const int64_t base = lo * SLOS_CDF_BLOCK;
-        const double c_own = lane < kChunks ? cs[lo * kChunks + lane] : 0.0;
+        const double c_own = cs[lo * kChunks + l16];
         double c_inc = c_own;
 #pragma unroll
         for (int o = 1; o < kChunks; o <<= 1) {
-            const double u = __shfl_up(c_inc, o, 64);
-            if (lane >= o) c_inc += u;
+            const double u = __shfl_up(c_inc, o, 16);
+            if (l16 >= o) c_inc += u;
         }
-        const uint64_t c_cross = __ballot(lane < kChunks && bp[lo] + c_inc > t && c_own > 0.0);
-        const uint64_t c_pos = __ballot(lane < kChunks && c_own > 0.0);
-        const int i0 = c_cross ? __builtin_ctzll(c_cross) : (c_pos ? 63 - __builtin_clzll(c_pos) : 0);
-        // then the states of the chunks from i0 on (rounding between the chunk
-        // sums and this scan can move the crossing on to a later chunk)
-        double run = bp[lo] + __shfl(c_inc - c_own, i0, 64);
+        const double b0 = bp[lo];
+        const uint32_t c_cross = gbits(b0 + c_inc > t && c_own > 0.0);
+        const uint32_t c_pos = gbits(c_own > 0.0);
+        const int i0 = c_cross ? __builtin_ctz(c_cross) : (c_pos ? 31 - __builtin_clz(c_pos) : 0);
+        double run = b0 + __shfl(c_inc - c_own, i0, 16);
+        // then the states of the chunks from i0 on, four per lane (rounding
+        // between the chunk sums and this scan can move the crossing on to a
+        // later chunk)
         int64_t found = -1, last_pos = -1;
-        for (int i = i0; i < kChunks && found < 0; ++i) {
-            const int64_t x = base + i * 64 + lane;
-            const double v = x < M ? (double)P[x] : 0.0;
-            double c = v;
+        int ci = i0;
+        for (int it = 0; it < kChunks; ++it) {
+            const bool open = found < 0 && ci < kChunks;
+            if (!__ballot(open)) break;
+            double v[4];
+            const int64_t x0 = base + (int64_t)ci * 64 + 4 * l16;
 #pragma unroll
-            for (int o = 1; o < 64; o <<= 1) {
-                const double u = __shfl_up(c, o, 64);
-                if (lane >= o) c += u;
+            for (int e = 0; e < 4; ++e) v[e] = (open && x0 + e < M) ? (double)P[x0 + e] : 0.0;
+            double in[4];
+            in[0] = v[0];
+#pragma unroll
+            for (int e = 1; e < 4; ++e) in[e] = in[e - 1] + v[e];
+            double lsum = in[3];  // exclusive prefix of the lanes' sums over the group
+#pragma unroll
+            for (int o = 1; o < 16; o <<= 1) {
+                const double u = __shfl_up(lsum, o, 16);
+                if (l16 >= o) lsum += u;
             }
-            const uint64_t cross = __ballot(run + c > t && v > 0.0);
-            const uint64_t pos = __ballot(v > 0.0);
-            if (cross) found = base + i * 64 + __builtin_ctzll(cross);
-            if (pos) last_pos = base + i * 64 + 63 - __builtin_clzll(pos);
-            run += __shfl(c, 63, 64);
+            const double excl = lsum - in[3];
+            int first_e = -1, last_e = -1;
+#pragma unroll
+            for (int e = 3; e >= 0; --e) {
+                if (v[e] > 0.0 && run + excl + in[e] > t) first_e = e;
+                if (last_e < 0 && v[e] > 0.0) last_e = e;
+            }
+            const uint32_t cross = gbits(open && first_e >= 0);
+            const uint32_t pos = gbits(open && last_e >= 0);
+            if (open) {
+                if (cross) {
+                    const int src = __builtin_ctz(cross);
+                    found = base + (int64_t)ci * 64 + 4 * src + __shfl(first_e, src, 16);
+                }
+                if (pos) {
+                    const int src = 31 - __builtin_clz(pos);
+                    last_pos = base + (int64_t)ci * 64 + 4 * src + __shfl(last_e, src, 16);
+                }
+                run += __shfl(lsum, 15, 16);  // shuffles stay within the group, all of whose lanes are here
+                ++ci;
+            }
         }
         // rounding can leave the crossing past the block's recomputed sum:
         // take the block's last state of non-zero probability
         if (found < 0) found = last_pos >= 0 ? last_pos : min(base, M - 1);
-        if (lane == 0) ranks[sidx] = found;
+        if (l16 == 0 && live) ranks[sidx] = found;
     }
 }
 
@@ -304,6 +339,11 @@ int slos_launch_cdf(const void *P, int c64, int64_t M, double *bp, void *stream)
     hipLaunchKernelGGL(cdf_super_kernel, dim3(gsup), dim3(256), 0, s, (const double *)bp, nb, nsup, sp);
     hipLaunchKernelGGL(cdf_scan_kernel, dim3(1), dim3(1024), 0, s, sp, nsup);
     hipLaunchKernelGGL(cdf_fix_kernel, dim3(gsup), dim3(256), 0, s, bp, nb, (const double *)sp, nsup);
+    const CdfTree tr = cdf_tree_layout(nb);
+    if (tr.nlev > 1) {
+        const int gt = (int)std::max<int64_t>(1, std::min<int64_t>((tr.n[1] + 255) / 256, 1024));
+        hipLaunchKernelGGL(cdf_tree_kernel, dim3(gt), dim3(256), 0, s, (const double *)bp, cs + kChunks * nb, tr);
+    }
     return (int)hipGetLastError();
 }
 
@@ -323,13 +363,14 @@ int slos_launch_sample(const void *P, int c64, int64_t M, const double *bp, cons
                        int64_t *ranks, void *stream)
 {
     const int64_t nb = (M + SLOS_CDF_BLOCK - 1) / SLOS_CDF_BLOCK;
-    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((count + 3) / 4, 8192));
+    const int64_t waves = (count + 3) / 4;  // four samples per wave
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((waves + 3) / 4, 8192));
     hipStream_t s = (hipStream_t)stream;
     if (c64)
         hipLaunchKernelGGL(sample_kernel<float>, dim3(grid), dim3(256), 0, s, (const float *)P, M, bp, nb, r, count,
-                           ranks);
+                           ranks, cdf_tree_layout(nb));
     else
         hipLaunchKernelGGL(sample_kernel<double>, dim3(grid), dim3(256), 0, s, (const double *)P, M, bp, nb, r,
-                           count, ranks);
+                           count, ranks, cdf_tree_layout(nb));
     return (int)hipGetLastError();
 }

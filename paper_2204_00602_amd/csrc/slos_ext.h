@@ -10,6 +10,31 @@
 #define SLOS_CDF_BLOCK 1024
 
 // weak simulation (sample.hip)
+// A 16-ary search tree over the block prefix bp (level 0, nb entries): level l
+// holds bp[i * 16^l] for i < n[l] = ceil(nb / 16^l), up to the first level of
+// at most 16 entries, so that every step of a search reads 16 consecutive
+// values (one 128-byte line).  Levels 1.. are stored one after another at
+// tree + off[l].
+#define SLOS_CDF_TREE_MAX_LEVELS 12
+struct CdfTree {
+    int nlev;
+    int64_t n[SLOS_CDF_TREE_MAX_LEVELS];
+    int64_t off[SLOS_CDF_TREE_MAX_LEVELS];
+    int64_t total;  // doubles in levels 1..nlev-1
+};
+inline CdfTree cdf_tree_layout(int64_t nb)
+{
+    CdfTree t{};
+    t.n[0] = nb;
+    t.nlev = 1;
+    while (t.n[t.nlev - 1] > 16 && t.nlev < SLOS_CDF_TREE_MAX_LEVELS) {
+        t.n[t.nlev] = (t.n[t.nlev - 1] + 15) / 16;
+        t.off[t.nlev] = t.total;
+        t.total += t.n[t.nlev];
+        ++t.nlev;
+    }
+    return t;
+}
 int slos_launch_cdf(const void *P, int c64, int64_t M, double *bp, void *stream);
 int slos_launch_marginals(const void *P, int c64, const double *bp, const int64_t *ends, int m, double *pk,
                           void *stream);
