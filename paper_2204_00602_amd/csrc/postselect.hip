@@ -225,6 +225,23 @@ __global__ __launch_bounds__(256) void ps_leaf_kernel(PostselectParams p)
             for (int h = 0; h < SLOS_PS_MAX_GROUPS; ++h) hc[h] += (g == h) ? 1u : 0u;
         }
         const E *low = (const E *)p.low + p.type_off[tab];
+        // NARROW: the four group counts of an output are the bytes of
+        // (table entry + hp) (each at most n <= 32, so bytes never carry), and
+        // "lo_g <= c_g <= hi_g for every g" is one test on guard bits: with
+        // G = 0x80 in each byte, ((c | G) - lo) and ((hi | G) - c) keep bit 7 of
+        // byte g iff c_g >= lo_g and hi_g >= c_g (bounds clamped to 127, unused
+        // groups [0, 127]; no byte borrows).
+        uint32_t hp = 0, lo4 = 0, hi4 = 0;
+        if (NARROW) {
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                const bool used = g < p.ngroups;
+                const uint32_t a = p.cmin[g], b = p.cmax[g];
+                hp |= (used ? hc[g] : 0u) << (8 * g);
+                lo4 |= (used ? (a < 127u ? a : 127u) : 0u) << (8 * g);
+                hi4 |= (used ? (b < 127u ? b : 127u) : 127u) << (8 * g);
+            }
+        }
         // kSteps outputs per lane and step (x0 + 64u), loads first: P is read
         // once (non-temporal, so the shared low-state table stays in L2).
         // Measured at m=24, n=12: 4 per step 1.33 ms, 8 1.24 ms, 16 1.52 ms.
@@ -244,11 +261,17 @@ __global__ __launch_bounds__(256) void ps_leaf_kernel(PostselectParams p)
                 const uint32_t x = x0 + 64u * u;
                 if (x >= size) break;
                 bool ok = true;
+                if constexpr (NARROW) {
+                    constexpr uint32_t G = 0x80808080u;
+                    const uint32_t c = (uint32_t)w[u] + hp;
+                    ok = ((((c | G) - lo4) & ((hi4 | G) - c)) & G) == G;
+                } else {
 #pragma unroll
-                for (int g = 0; g < NG; ++g) {
-                    if (g < p.ngroups) {
-                        const uint32_t c = count_of(w[u], g) + hc[g];
-                        ok = ok && c >= p.cmin[g] && c <= p.cmax[g];
+                    for (int g = 0; g < NG; ++g) {
+                        if (g < p.ngroups) {
+                            const uint32_t c = count_of(w[u], g) + hc[g];
+                            ok = ok && c >= p.cmin[g] && c <= p.cmax[g];
+                        }
                     }
                 }
                 if (ok) acc += (double)v[u];
