@@ -196,9 +196,11 @@ int slos_plan_replay(slos_plan_t plan, void *stream);
  * colex order: fp32 for a C64 plan, fp64 for C128, e.g. the output of
  * slos_probs; need not be normalised).  FP64 sums of blocks of 1024 states and
  * their exclusive prefix, plus the sums of each block's 16 chunks of 64 states
- * (about 3% of P in FP64 for complex64 plans), kept by the plan (one table per
- * plan; a later call replaces it).  Deterministic.  slos_marginals and
- * slos_sample read this table together with the same `probs`.
+ * (about 3% of P in FP64 for complex64 plans) and a 16-ary search tree over the
+ * block prefix (every 16^l-th prefix, levels down to 16 entries), kept by the
+ * plan (one table per plan; a later call replaces it).  Deterministic.
+ * slos_marginals and slos_sample read this table together with the same
+ * `probs`.
  */
 int slos_cdf(slos_plan_t plan, const void *probs, void *stream);
 
