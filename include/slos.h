@@ -82,8 +82,8 @@ typedef struct slos_options {
     int32_t comp_from_layer; /* first compensated layer (default 1: every layer)     */
     int32_t block_threads;   /* threads per workgroup: 64, 128, 256 (default 256)    */
     int32_t grid_blocks;     /* cap on workgroups per layer launch (default 2048)    */
-    int32_t outputs_per_lane;/* 1, 2 or 4 outputs per lane per tile (default 4 for
-                                c64, 2 for c128)                                     */
+    int32_t outputs_per_lane;/* 1, 2 or 4 outputs per lane per tile (default 2; 4
+                                for c64 with SLOS_KEEP_LAYERS)                       */
     int32_t xcd_chunk;       /* consecutive leaves dealt to one XCD at a time
                                 (default 128; fewer when a layer has few leaves)    */
     int32_t ticket_leaves;   /* consecutive leaves a workgroup takes per work ticket
@@ -103,8 +103,9 @@ typedef struct slos_options {
     int32_t low_block_max;   /* largest low block a leaf may stage in LDS (states);
                                 leaves with larger ones are split further, so a
                                 workgroup needs less LDS and more of them fit on
-                                a CU.  0: default (40 KiB: 5120 for c64, 2560 for
-                                c128; no limit with SLOS_KEEP_LAYERS); -1: none */
+                                a CU.  0: default (3584 for c64, 28 KiB; 2560 for
+                                c128, 40 KiB; no limit with SLOS_KEEP_LAYERS);
+                                -1: none                                         */
 } slos_options_t;
 
 /* ---- Fock-space arithmetic (host only; no device needed) ------------------ */

@@ -27,7 +27,7 @@ from . import inputs, slos
 
 PLAN_SPACE: Dict[str, List[int]] = {
     "leaf_max": [2048, 4096, 8192, 16384, 32768],
-    "low_block_max": [2048, 3072, 4096, 5120, 6144],
+    "low_block_max": [2048, 3072, 3584, 4096, 5120],
     "outputs_per_lane": [1, 2, 4],
     "block_threads": [64, 128, 256],
     "grid_blocks": [1024, 2048, 4096, 8192],

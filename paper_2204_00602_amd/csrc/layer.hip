@@ -475,11 +475,12 @@ __device__ __forceinline__ const C *stage_low_team(const C *__restrict__ X, cons
 // come from per-XCD ticket counters in batches of p.ticket_leaves, so the
 // workgroups resident on an XCD work on neighbouring leaves of the colex order
 // and share that XCD's L2.
-// complex64 tiles are held to three waves per SIMD (168 VGPRs), the occupancy
-// the LDS of one low block per workgroup allows at the default leaf size;
-// complex128 tiles of up to two outputs per lane to four (128 VGPRs)
+// Register budgets: complex64 two-output tiles to five waves per SIMD (96
+// VGPRs, no spills; five workgroups' low blocks of up to 28 KiB fit a CU's
+// LDS), other complex64 tiles to three (168 VGPRs), complex128 tiles of up to
+// two outputs per lane to four (128 VGPRs)
 template <typename T, int MODE, int COMP, int RR, bool WIDE>
-__global__ __launch_bounds__(256, sizeof(T) == 4 ? 3 : (RR <= 2 ? 4 : 1)) void layer_kernel(LayerParams p)
+__global__ __launch_bounds__(256, sizeof(T) == 4 ? (RR == 2 ? 5 : 3) : (RR <= 2 ? 4 : 1)) void layer_kernel(LayerParams p)
 {
     using C = typename Cx<T>::type;
     if (blockIdx.y) {

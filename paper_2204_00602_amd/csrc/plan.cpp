@@ -222,6 +222,15 @@ struct slos_plan_s {
     uint32_t *d_ps_type_off = nullptr;// first table entry per inner-type index
     uint8_t *d_ps_low = nullptr;      // group counts of every low state (per call)
     uint32_t ps_ntypes = 0, ps_entries = 0;
+    // post-selection's own leaves of the last layer: it stages nothing in LDS,
+    // so they have no low-block cap and may be larger than the recurrence's
+    // (fewer per-leaf set-ups, while the low-state table of their shapes still
+    // fits the L2); their tab indexes ps_type_list, inner shapes only
+    std::vector<LeafRec> ps_leaves;
+    std::vector<PsType> ps_type_list;
+    std::map<std::pair<int, int>, uint32_t> ps_type_of;
+    bool ps_pass = false;             // gen_leaves is building ps_leaves
+    uint64_t ps_leaf_off = 0;         // ps_leaves in d_leaves
     size_t sel_cap = 0;
     // differentiation (SLOS_KEEP_LAYERS plans)
     std::vector<std::vector<BwdUnit>> units;   // per layer
@@ -289,6 +298,18 @@ struct slos_plan_s {
         return id;
     }
 
+    // inner shape (q, K) of a post-selection leaf: only its size is needed
+    uint32_t ps_type(int q, int K)
+    {
+        auto key = std::make_pair(q, K);
+        auto it = ps_type_of.find(key);
+        if (it != ps_type_of.end()) return it->second;
+        const uint32_t id = (uint32_t)ps_type_list.size();
+        ps_type_list.push_back(PsType{0, (uint32_t)B(q + K - 1, K), (uint16_t)q, (uint16_t)K, 0});
+        ps_type_of[key] = id;
+        return id;
+    }
+
     // Leaves of layer k: split F(j+1, K) by the occupation of mode j (blocks
     // t_j = 0, 1, .., K in colex order) until a block holds <= cap states.
     uint64_t low_cap = ~uint64_t(0);   // largest low block a leaf may have (elements)
@@ -304,7 +325,7 @@ struct slos_plan_s {
             L.nhp = (uint8_t)hm.size();
             for (size_t i = 0; i < hm.size(); ++i) L.hm[i] = hm[i];
             L.size = (uint32_t)size;
-            L.tab = inner_type(j + 1, K);
+            L.tab = ps_pass ? ps_type(j + 1, K) : inner_type(j + 1, K);
             // rank of the leaf's first state: low photons all in mode 0 add
             // C(r-1, r) = 0; high photon at position r = k - idx adds C(d+r-1, r)
             uint64_t base = 0;
@@ -600,13 +621,14 @@ int slos_plan_ex(int m, int n, const int32_t *input_state, int flags, const slos
     // m=24, n=12 on gfx950 (a c128 low block of an 8192-state leaf takes
     // enough LDS to halve the resident workgroups, hence the smaller leaves)
     if (o.leaf_max == 0) o.leaf_max = (flags & SLOS_KEEP_LAYERS) ? 1024 : (dt == SLOS_C64 ? 16384 : 8192);
-    // low blocks of at most 40 KiB: three workgroups' staging fits a CU's LDS,
-    // and the few leaves with larger low blocks are split further
-    if (o.low_block_max == 0) o.low_block_max = (flags & SLOS_KEEP_LAYERS) ? -1 : (dt == SLOS_C64 ? 5120 : 2560);
+    // low blocks of at most 28 KiB (c64: five workgroups of two-output tiles
+    // per CU, the occupancy their 96 VGPRs allow) or 40 KiB (c128: three); the
+    // leaves with larger low blocks are split further
+    if (o.low_block_max == 0) o.low_block_max = (flags & SLOS_KEEP_LAYERS) ? -1 : (dt == SLOS_C64 ? 3584 : 2560);
     if (o.comp_from_layer == 0) o.comp_from_layer = 1;
     if (o.block_threads == 0) o.block_threads = 256;
     if (o.grid_blocks == 0) o.grid_blocks = 2048;
-    if (o.outputs_per_lane == 0) o.outputs_per_lane = dt == SLOS_C64 ? 4 : 2;
+    if (o.outputs_per_lane == 0) o.outputs_per_lane = (dt == SLOS_C64 && (flags & SLOS_KEEP_LAYERS)) ? 4 : 2;
     if (o.xcd_chunk == 0) o.xcd_chunk = 128;
     if (o.ticket_leaves == 0) o.ticket_leaves = 2;
     if (o.max_batch == 0) o.max_batch = 1;
@@ -677,6 +699,16 @@ int slos_plan_ex(int m, int n, const int32_t *input_state, int flags, const slos
             // reached by removing their top photon run together)
             if (o.leaf_order >= 0) order_leaves(p->leaves[k], o.leaf_order > 0 ? o.leaf_order : 1);
         }
+        if (n > 0) {
+            const uint64_t saved = p->low_cap;
+            p->low_cap = ~uint64_t(0);
+            p->ps_pass = true;
+            std::vector<uint8_t> hm;
+            p->gen_leaves(n, m - 1, n, SLOS_PS_LEAF_MAX, hm, p->ps_leaves);
+            order_leaves(p->ps_leaves, 1);  // the grouped order (measured faster than colex here too)
+            p->ps_pass = false;
+            p->low_cap = saved;
+        }
         if (p->keep) {
             p->units.resize(n + 1);
             for (int k = 1; k <= n; ++k) p->build_units(k);
@@ -720,6 +752,8 @@ int slos_plan_ex(int m, int n, const int32_t *input_state, int flags, const slos
         all.insert(all.end(), p->leaves[k].begin(), p->leaves[k].end());
     }
     p->leaf_off[n + 1] = all.size();
+    p->ps_leaf_off = all.size();
+    all.insert(all.end(), p->ps_leaves.begin(), p->ps_leaves.end());
     std::vector<unsigned char> descs;
     p->desc_off.assign(n + 2, 0);
     p->desc_wide.assign(n + 1, 0);
@@ -867,21 +901,20 @@ int slos_plan_ex(int m, int n, const int32_t *input_state, int flags, const slos
         }
     }
     if (n > 0) {
-        // post-selection tables: the inner types the last layer's leaves use
-        std::vector<uint32_t> off(p->types.size(), 0xFFFFFFFFu);
-        std::vector<PsType> pt;
+        // post-selection tables: one run of low states per inner shape of
+        // its leaves, in the order the shapes were met (ascending off)
+        std::vector<uint32_t> off(p->ps_type_list.size(), 0);
+        std::vector<PsType> pt = p->ps_type_list;
         uint64_t entries = 0;
-        for (const LeafRec &L : p->leaves[n]) {
-            if (off[L.tab] != 0xFFFFFFFFu) continue;
-            const InnerType &ty = p->types[L.tab];
-            off[L.tab] = (uint32_t)entries;
-            pt.push_back(PsType{(uint32_t)entries, ty.size, ty.q, ty.K, 0});
-            entries += ty.size;
+        for (size_t i = 0; i < pt.size(); ++i) {
+            off[i] = (uint32_t)entries;
+            pt[i].off = (uint32_t)entries;
+            entries += pt[i].size;
         }
         if (entries >= (1ull << 32)) {
             p->free_device();
             delete p;
-            return fail(SLOS_ERR_SIZE_OVERFLOW, "post-selection table exceeds 2^32 entries; lower leaf_max");
+            return fail(SLOS_ERR_SIZE_OVERFLOW, "post-selection table exceeds 2^32 entries");
         }
         p->ps_ntypes = (uint32_t)pt.size();
         p->ps_entries = (uint32_t)entries;
@@ -1333,8 +1366,8 @@ int slos_postselect(slos_plan_t p, const void *probs, const int32_t *group_of_mo
     ps.run = (M + threads - 1) / threads;
     ps.partials = p->d_ps_partials;
     if (p->n > 0) {
-        ps.leaves = p->d_leaves + p->leaf_off[p->n];
-        ps.nleaves = p->leaves[p->n].size();
+        ps.leaves = p->d_leaves + p->ps_leaf_off;
+        ps.nleaves = p->ps_leaves.size();
         ps.type_off = p->d_ps_type_off;
         ps.types = p->d_ps_types;
         ps.ntypes = p->ps_ntypes;

@@ -44,8 +44,9 @@ int slos_launch_sample(const void *P, int c64, int64_t M, const double *bp, cons
 // post-selection (postselect.hip)
 #define SLOS_PS_MAX_GROUPS 16
 #define SLOS_PS_MAX_WAVES 8192  // partial sums per post-selection launch
-// an inner type used by the last layer: its low states occupy table entries
-// [off, off + size)
+#define SLOS_PS_LEAF_MAX 32768   // states per post-selection leaf
+// an inner shape (q low modes, K low photons) of the post-selection leaves:
+// its low states occupy table entries [off, off + size)
 struct PsType {
     uint32_t off;
     uint32_t size;
@@ -63,13 +64,14 @@ struct PostselectParams {
     double *partials;       // one FP64 partial per wave
     int8_t group[256];      // group of each mode, -1: unconstrained
     uint8_t cmin[SLOS_PS_MAX_GROUPS], cmax[SLOS_PS_MAX_GROUPS];
-    // leaf path: the last layer's leaves, and per inner type used by them a
-    // run of the low-state table (SLOS_PS_MAX_GROUPS group counts per state)
+    // leaf path: a leaf decomposition of the last layer of its own (leaves of
+    // up to SLOS_PS_LEAF_MAX states), and per inner shape used by them a run of
+    // the low-state table (SLOS_PS_MAX_GROUPS group counts per state)
     const LeafRec *leaves;
     uint64_t nleaves;
-    const uint32_t *type_off;    // per inner-type index: first table entry
+    const uint32_t *type_off;    // per inner-shape index: first table entry
     const PsType *types;         // ntypes entries, ascending off
-    uint32_t ntypes;             // inner types used by the last layer
+    uint32_t ntypes;             // inner shapes of the leaves
     uint32_t entries;            // table entries (low states)
     uint8_t *low;                // entries x SLOS_PS_MAX_GROUPS group counts
 };
