@@ -260,6 +260,24 @@ def test_low_block_cap_splits_leaves(cap):
         assert nxt == Nk
 
 
+@pytest.mark.parametrize("dt,cap", [("c64", 3584), ("c128", 2560)])
+def test_default_low_block_cap(dt, cap):
+    """With default options the low blocks stay within the documented cap
+    (3584 complex64 states = 28 KiB, five workgroups per CU; 2560 complex128
+    states = 40 KiB), and the cap is reached, so it is the one in force."""
+    T = [1] * 10 + [0] * 14  # last layer 92.6M states: leaves of the full 16384/8192 size
+    p = slos.Plan(T, dt, host_only=True)
+    Nk, nl = p.layer_info(10)
+    biggest = 0
+    for idx in range(nl):
+        base, q, K, hm = p.leaf(10, idx)
+        low = math.comb(q + K - 2, K - 1) if K > 0 else 0
+        assert low <= cap or q == 1, (q, K, low)
+        biggest = max(biggest, low)
+    assert biggest > cap * 3 // 4, biggest
+    p.close()
+
+
 def test_leaf_order_and_cap_validation():
     with pytest.raises(slos.SlosError):
         slos.Plan([1, 1, 0], "c64", host_only=True, options={"leaf_order": 5})

@@ -98,6 +98,36 @@ def test_config2_groups_match_oracle(dtype):
             assert tb[i] == pytest.approx(want, rel=1e-12, abs=1e-300), (gm, r)
 
 
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_many_leaves_match_oracle(dtype):
+    """m=16, n=8 (490,314 outputs): post-selection splits the last layer into
+    many leaves of its own (up to 32768 states each) with several inner shapes,
+    unlike config 2, which is a single leaf."""
+    m, n = 16, 8
+    T, U = inputs.first_modes_input(m, n), inputs.haar_unitary(m, 11)
+    print(f"[postselect] m={m} n={n} {dtype}", flush=True)
+    p, P = _probs(T, U, dtype)
+    S = oracle.colex_sorted(oracle.fock_states(m, n))
+    Pn = P.cpu().numpy().astype(np.float64)
+    Pref = oracle.probabilities(U, T, S) if dtype == "c128" else None
+    cases = [
+        ([0, 0, 1, 1] + [-1] * 10 + [2, 2], [1, 0, 0], [1, 1, 0]),
+        ([i % 3 for i in range(m)], [2, 2, 2], [3, 3, 3]),
+        ([i % 5 for i in range(m)], [0, 1, 0, 1, 0], [3, 3, 2, 3, 3]),   # 16-count entries
+        ([-1] * 8 + [0] * 8, [0], [0]),
+    ]
+    for gm, lo, hi in cases:
+        kept, masked, _ = p.postselect(P, gm, lo, hi, masked=True)
+        keep, tot_same = oracle.postselect(Pn, S, gm, lo, hi)
+        k = float(kept.item())
+        assert abs(k - tot_same) <= 1e-12 * max(1.0, tot_same), (gm, k, tot_same)
+        assert np.array_equal(masked.cpu().numpy(), np.where(keep, P.cpu().numpy(), 0)), gm
+        if Pref is not None:
+            _, tot_ref = oracle.postselect(Pref, S, gm, lo, hi)
+            assert abs(k - tot_ref) <= 1e-12, (gm, k, tot_ref)
+    p.close()
+
+
 def test_config3_groups_against_marginals_and_partition():
     m, n = 24, 12
     T, U = inputs.first_modes_input(m, n), inputs.haar_unitary(m, 3)
