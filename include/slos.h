@@ -87,7 +87,7 @@ typedef struct slos_options {
     int32_t xcd_chunk;       /* consecutive leaves dealt to one XCD at a time
                                 (default 128; fewer when a layer has few leaves)    */
     int32_t ticket_leaves;   /* consecutive leaves a workgroup takes per work ticket
-                                (default 2)                                          */
+                                (default 1 for c64, 2 for c128)                      */
     int32_t max_batch;       /* unitaries per *_many call, 1..65535 (default 1): the
                                 plan holds layer buffers for that many instances   */
     int32_t wide_descriptors;/* 1: use the 32-group, 64-bit-delta leaf descriptors on

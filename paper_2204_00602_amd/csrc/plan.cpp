@@ -630,7 +630,7 @@ int slos_plan_ex(int m, int n, const int32_t *input_state, int flags, const slos
     if (o.grid_blocks == 0) o.grid_blocks = 2048;
     if (o.outputs_per_lane == 0) o.outputs_per_lane = (dt == SLOS_C64 && (flags & SLOS_KEEP_LAYERS)) ? 4 : 2;
     if (o.xcd_chunk == 0) o.xcd_chunk = 128;
-    if (o.ticket_leaves == 0) o.ticket_leaves = 2;
+    if (o.ticket_leaves == 0) o.ticket_leaves = dt == SLOS_C64 ? 1 : 2;  // c64: the smaller leaves of its cap favour 1
     if (o.max_batch == 0) o.max_batch = 1;
     if (o.wide_descriptors < 0 || o.wide_descriptors > 1)
         return fail(SLOS_ERR_INVALID_ARG, "wide_descriptors must be 0 or 1");
