@@ -103,7 +103,7 @@ typedef struct slos_options {
     int32_t low_block_max;   /* largest low block a leaf may stage in LDS (states);
                                 leaves with larger ones are split further, so a
                                 workgroup needs less LDS and more of them fit on
-                                a CU.  0: default (3584 for c64, 28 KiB; 2560 for
+                                a CU.  0: default (3072 for c64, 24 KiB; 2560 for
                                 c128, 40 KiB; no limit with SLOS_KEEP_LAYERS);
                                 -1: none                                         */
 } slos_options_t;

@@ -283,12 +283,15 @@ __device__ __forceinline__ const C *stage_low(const C *__restrict__ X, const Lea
 // One tile: RT outputs per lane, x = t0 + i*64 + lane clamped to the leaf so
 // every load is in bounds.  tile_load issues all block loads (up to HS high
 // groups) and table loads (up to CS low terms) of the tile; tile_compute uses
-// them.
-constexpr int kHS = 8;
-constexpr int kCS = 8;
+// them, and loads the groups and terms past those from memory as it goes.
+// complex64 two-output tiles hold six of each (80 VGPRs: six waves per SIMD),
+// the other tiles eight.
+template <typename T, int RT> constexpr int tile_slots() { return (sizeof(T) == 4 && RT == 2) ? 6 : 8; }
 
 template <typename T, int RT>
 struct TileIn {
+    static constexpr int kHS = tile_slots<T, RT>();
+    static constexpr int kCS = tile_slots<T, RT>();
     typename Cx<T>::type v[kHS][RT];
     uint32_t e[kCS][RT];
     double lf[RT];
@@ -302,6 +305,7 @@ __device__ __forceinline__ void tile_load(TileIn<T, RT> &in, const LayerParams &
                                           int lane)
 {
     using C = typename Cx<T>::type;
+    constexpr int kHS = TileIn<T, RT>::kHS, kCS = TileIn<T, RT>::kCS;
 #pragma unroll
     for (int i = 0; i < RT; ++i) {
         const uint32_t x = t0 + (uint32_t)(i * 64 + lane);
@@ -363,6 +367,7 @@ __device__ __forceinline__ void tile_compute(const TileIn<T, RT> &in, const Laye
                                              float sigma, uint32_t t0, int lane, double &psum, float &omax)
 {
     using C = typename Cx<T>::type;
+    constexpr int kHS = TileIn<T, RT>::kHS, kCS = TileIn<T, RT>::kCS;
     const uint32_t *__restrict__ pred = p.pred + L.pred_off;
 
     // Visit every term (output i, mode j, predecessor value) of the tile:
@@ -475,12 +480,12 @@ __device__ __forceinline__ const C *stage_low_team(const C *__restrict__ X, cons
 // come from per-XCD ticket counters in batches of p.ticket_leaves, so the
 // workgroups resident on an XCD work on neighbouring leaves of the colex order
 // and share that XCD's L2.
-// Register budgets: complex64 two-output tiles to five waves per SIMD (96
-// VGPRs, no spills; five workgroups' low blocks of up to 28 KiB fit a CU's
-// LDS), other complex64 tiles to three (168 VGPRs), complex128 tiles of up to
-// two outputs per lane to four (128 VGPRs)
+// Register budgets: complex64 two-output tiles to six waves per SIMD (80
+// VGPRs; six workgroups' low blocks of up to 24 KiB fit a CU's LDS), other
+// complex64 tiles to three (168 VGPRs), complex128 tiles of up to two outputs
+// per lane to four (128 VGPRs)
 template <typename T, int MODE, int COMP, int RR, bool WIDE>
-__global__ __launch_bounds__(256, sizeof(T) == 4 ? (RR == 2 ? 5 : 3) : (RR <= 2 ? 4 : 1)) void layer_kernel(LayerParams p)
+__global__ __launch_bounds__(256, sizeof(T) == 4 ? (RR == 2 ? 6 : 3) : (RR <= 2 ? 4 : 1)) void layer_kernel(LayerParams p)
 {
     using C = typename Cx<T>::type;
     if (blockIdx.y) {

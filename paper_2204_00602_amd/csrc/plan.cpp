@@ -621,10 +621,10 @@ int slos_plan_ex(int m, int n, const int32_t *input_state, int flags, const slos
     // m=24, n=12 on gfx950 (a c128 low block of an 8192-state leaf takes
     // enough LDS to halve the resident workgroups, hence the smaller leaves)
     if (o.leaf_max == 0) o.leaf_max = (flags & SLOS_KEEP_LAYERS) ? 1024 : (dt == SLOS_C64 ? 16384 : 8192);
-    // low blocks of at most 28 KiB (c64: five workgroups of two-output tiles
-    // per CU, the occupancy their 96 VGPRs allow) or 40 KiB (c128: three); the
+    // low blocks of at most 24 KiB (c64: six workgroups of two-output tiles
+    // per CU, the occupancy their 80 VGPRs allow) or 40 KiB (c128: three); the
     // leaves with larger low blocks are split further
-    if (o.low_block_max == 0) o.low_block_max = (flags & SLOS_KEEP_LAYERS) ? -1 : (dt == SLOS_C64 ? 3584 : 2560);
+    if (o.low_block_max == 0) o.low_block_max = (flags & SLOS_KEEP_LAYERS) ? -1 : (dt == SLOS_C64 ? 3072 : 2560);
     if (o.comp_from_layer == 0) o.comp_from_layer = 1;
     if (o.block_threads == 0) o.block_threads = 256;
     if (o.grid_blocks == 0) o.grid_blocks = 2048;

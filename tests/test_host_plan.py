@@ -260,10 +260,10 @@ def test_low_block_cap_splits_leaves(cap):
         assert nxt == Nk
 
 
-@pytest.mark.parametrize("dt,cap", [("c64", 3584), ("c128", 2560)])
+@pytest.mark.parametrize("dt,cap", [("c64", 3072), ("c128", 2560)])
 def test_default_low_block_cap(dt, cap):
     """With default options the low blocks stay within the documented cap
-    (3584 complex64 states = 28 KiB, five workgroups per CU; 2560 complex128
+    (3072 complex64 states = 24 KiB, six workgroups per CU; 2560 complex128
     states = 40 KiB), and the cap is reached, so it is the one in force."""
     T = [1] * 10 + [0] * 14  # last layer 92.6M states: leaves of the full 16384/8192 size
     p = slos.Plan(T, dt, host_only=True)
