@@ -142,6 +142,17 @@ void slos_plan_destroy(slos_plan_t plan);
 /* Number of outputs M = C(m+n-1, n); -1 for a NULL plan. */
 int64_t slos_num_outputs(slos_plan_t plan);
 
+/* Colex rank of an output state of the plan (m int32 occupations summing to
+ * the plan's n): the index of a(state) in the arrays slos_amplitudes and
+ * slos_probs write (Section 4.2.1 defines the output set S_{m,n}; the order is
+ * colex, rank 0 holding every photon in mode 0).  INVALID_ARG for a NULL
+ * pointer or a state of the wrong photon number.  Host only, no device work. */
+int slos_rank(slos_plan_t plan, const int32_t *state, int64_t *rank);
+
+/* Inverse of slos_rank: writes the plan's m occupations of output `rank`
+ * (0 <= rank < slos_num_outputs) to `state`, which the caller owns. */
+int slos_unrank(slos_plan_t plan, int64_t rank, int32_t *state);
+
 /* Host-side inspection of the tiling of layer k (1..n): number of states N_k
  * and number of leaves.  Works on SLOS_HOST_ONLY plans. */
 int slos_plan_info(slos_plan_t plan, int k, int64_t *n_states, int64_t *n_leaves);

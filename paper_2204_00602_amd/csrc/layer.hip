@@ -3,7 +3,9 @@
 // One launch computes layer k of the recurrence of arXiv 2204.00602, Section
 // 3.2.3 (SLOS), in gather form:
 //     A_k[t] = sum_{j : t_j > 0} U[j, i_k] * A_{k-1}[t - e_j],
-// every output written by exactly one lane, no atomics.  The last layer fuses
+// every output written by exactly one lane, with no atomics on data (the work
+// tickets and the recorded maximum of a compensated layer are atomic counters
+// that schedule and bound, never outputs).  The last layer fuses
 // the normalisation a(S) = A_n[S] sqrt(prod s_j!) / sqrt(prod t_i!) (Eq.
 // eqperm), |a|^2 and an FP64 per-wave partial of sum_S P(S).
 //
@@ -559,12 +561,17 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? (RR == 2 ? 6 : 3) : (RR <= 2 
         const Leaf L = decode_head<WIDE>(cur);
         const C *lowbuf = stage_low_team<C>(X, L, slice, lane, wv, W);
         const bool refill = bat_next >= bat_end;
-        if (refill && threadIdx.x == 0) ticket_slot[it & 1] = atomicAdd(ticket, TB);
+        // Refills alternate between the two slots starting with slot 1: the
+        // slot written in iteration it is read after this iteration's barrier
+        // and written again only in iteration it + 2, after every wave has
+        // passed the barrier that ends iteration it + 1 (slot 0 holds the
+        // first ticket until the barrier that ends iteration 0).
+        if (refill && threadIdx.x == 0) ticket_slot[(it + 1) & 1] = atomicAdd(ticket, TB);
         // the staged block has landed in LDS for every wave
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
         if (refill) {
-            bat_next = ticket_slot[it & 1];
+            bat_next = ticket_slot[(it + 1) & 1];
             bat_end = bat_next + TB;
         }
         const uint64_t nli = to_leaf(bat_next++);

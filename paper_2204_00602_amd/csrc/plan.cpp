@@ -976,6 +976,29 @@ int64_t slos_num_outputs(slos_plan_t p)
     return (int64_t)p->Nk[p->n];
 }
 
+int slos_rank(slos_plan_t p, const int32_t *state, int64_t *rank)
+{
+    // host arithmetic only: host-only plans are accepted
+    if (!p) return fail(SLOS_ERR_INVALID_ARG, "plan is NULL");
+    int rc;
+    if (!rank) return fail(SLOS_ERR_INVALID_ARG, "rank is NULL");
+    if ((rc = check_state(p->m, p->n, state, "state"))) return rc;
+    *rank = (int64_t)colex_rank(p->B, p->m, state);
+    return SLOS_OK;
+}
+
+int slos_unrank(slos_plan_t p, int64_t rank, int32_t *state)
+{
+    // host arithmetic only: host-only plans are accepted
+    if (!p) return fail(SLOS_ERR_INVALID_ARG, "plan is NULL");
+    if (!state) return fail(SLOS_ERR_INVALID_ARG, "state is NULL");
+    const int64_t cnt = (int64_t)p->Nk[p->n];
+    if (rank < 0 || rank >= cnt)
+        return fail(SLOS_ERR_INVALID_ARG, "rank %lld outside [0, %lld)", (long long)rank, (long long)cnt);
+    colex_unrank(p->B, p->m, p->n, (uint64_t)rank, state);
+    return SLOS_OK;
+}
+
 int slos_plan_info(slos_plan_t p, int k, int64_t *n_states, int64_t *n_leaves)
 {
     if (!p) return fail(SLOS_ERR_INVALID_ARG, "plan is NULL");

@@ -77,6 +77,8 @@ def lib():
     L.slos_plan_destroy.restype = None
     L.slos_num_outputs.argtypes = [vp]
     L.slos_num_outputs.restype = ctypes.c_int64
+    L.slos_rank.argtypes = [vp, i32p, i64p]
+    L.slos_unrank.argtypes = [vp, ctypes.c_int64, i32p]
     L.slos_plan_info.argtypes = [vp, ctypes.c_int, i64p, i64p]
     L.slos_plan_leaf.argtypes = [vp, ctypes.c_int, ctypes.c_int64, i64p, i32p, i32p, i32p]
     L.slos_amplitudes.argtypes = [vp, vp, vp, vp, vp]
@@ -116,7 +118,7 @@ def lib():
     L.slos_plan_layer_ms.argtypes = [vp, ctypes.POINTER(ctypes.c_float), ctypes.c_int]
     L.slos_last_error.argtypes = []
     L.slos_last_error.restype = ctypes.c_char_p
-    for name in ("slos_fock_count", "slos_fock_rank", "slos_fock_unrank", "slos_plan",
+    for name in ("slos_fock_count", "slos_fock_rank", "slos_fock_unrank", "slos_rank", "slos_unrank", "slos_plan",
                  "slos_plan_ex", "slos_plan_info", "slos_plan_leaf", "slos_amplitudes",
                  "slos_probs", "slos_cdf", "slos_marginals", "slos_sample", "slos_postselect", "slos_select", "slos_amplitudes_many",
                  "slos_probs_many", "slos_backward_many", "slos_plan_set_timing", "slos_plan_layer_ms", "slos_backward",
@@ -453,13 +455,17 @@ class Plan:
         return kept, out, table
 
     def rank(self, state) -> int:
+        """Index of a(state) in this plan's outputs (slos_rank)."""
         s = _state_arr(state, self.m)
-        if int(s.sum()) != self.n:
-            raise ValueError("state has the wrong photon number")
-        return fock_rank(s)
+        r = ctypes.c_int64(0)
+        _check(self._lib.slos_rank(self._h, s.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), ctypes.byref(r)))
+        return int(r.value)
 
     def unrank(self, r: int) -> np.ndarray:
-        return fock_unrank(self.m, self.n, r)
+        """Output state at index r of this plan's outputs (slos_unrank)."""
+        s = np.zeros(self.m, np.int32)
+        _check(self._lib.slos_unrank(self._h, int(r), s.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+        return s
 
 
 class Batch:

@@ -3,6 +3,7 @@
 No GPU is touched: plans here use SLOS_HOST_ONLY, and device calls are only
 checked for their argument validation.
 """
+import ctypes
 import itertools
 import math
 import os
@@ -75,6 +76,39 @@ def test_rank_rejects_bad_states():
         slos.fock_rank([1, -1, 2])
     with pytest.raises(slos.SlosError):
         slos.fock_unrank(3, 2, 6)  # only 6 states: ranks 0..5
+
+
+@pytest.mark.parametrize("T", [[1, 1, 1, 0, 0, 0], [2, 0, 1, 0, 3], [0, 0, 4], [1] * 6 + [0] * 6])
+def test_plan_rank_unrank_match_independent_enumeration(T):
+    """slos_rank / slos_unrank of a plan: a bijection onto [0, M) that agrees
+    with the Fock-space functions, checked on the oracle's own enumeration of
+    the output states (recursive generation, no shared code)."""
+    import oracle
+    m, n = len(T), int(sum(T))
+    p = slos.Plan(T, "c64", host_only=True)
+    S = oracle.fock_states(m, n)
+    ranks = [p.rank(s) for s in S]
+    assert sorted(ranks) == list(range(math.comb(m + n - 1, n)))
+    for s, r in zip(S, ranks):
+        assert r == slos.fock_rank(s)
+        assert np.array_equal(p.unrank(r), s)
+
+
+def test_plan_rank_unrank_reject_bad_arguments():
+    p = slos.Plan([1, 1, 0], "c64", host_only=True)
+    with pytest.raises(slos.SlosError):
+        p.rank([1, 1, 1])          # three photons, the plan has two
+    with pytest.raises(slos.SlosError):
+        p.rank([3, -1, 0])
+    with pytest.raises(slos.SlosError):
+        p.unrank(6)                # C(4, 2) = 6 outputs: ranks 0..5
+    with pytest.raises(slos.SlosError):
+        p.unrank(-1)
+    L = slos.lib()
+    r = ctypes.c_int64(0)
+    st = (ctypes.c_int32 * 3)(1, 1, 0)
+    assert L.slos_rank(None, st, ctypes.byref(r)) == -1
+    assert L.slos_unrank(None, 0, st) == -1
 
 
 @pytest.mark.parametrize("m,T,leaf_max", [

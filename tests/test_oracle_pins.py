@@ -346,6 +346,85 @@ def test_mesh_is_unitary_and_layout_count():
     assert np.allclose(np.abs(bs) ** 2, 0.5)
 
 
+# The mesh convention (Section 2: Eq. eq:bs at theta = pi/2 and the phase
+# shifter e^{i phi}; Appendix B.2: BS, PS(phi_a) on mode 0, BS, PS(phi_b) on
+# mode 1).  With B = (1/sqrt2)[[1, i], [i, 1]]: B B = [[0, i], [i, 0]] and
+# B diag(-1, 1) B = diag(-1, 1), so an MZI with phi_a = 0 is a cross (mode p to
+# p+1 with amplitude i e^{i phi_b}, p+1 to p with i) and with phi_a = pi a bar
+# (mode p gets -1, mode p+1 gets e^{i phi_b}).
+
+def _mzi_cross(pb):
+    return np.array([[0, 1j], [1j * np.exp(1j * pb), 0]])
+
+
+def _mzi_bar(pb):
+    return np.diag([-1.0 + 0j, np.exp(1j * pb)])
+
+
+# phi_a in {0, pi} per MZI of the m = 4 layout (0,0) (0,2) (1,1) (2,0) (2,2)
+# (3,1), and distinct phi_b.  Tracing each input mode through the crosses and
+# bars by hand:
+#   mode 0: cross(0.3) -> 1 (i e^{0.3i}); bar(0.7) top -> 1 (-1); cross(1.1)
+#           bottom -> 0 (i); total e^{0.3i} at output 0
+#   mode 1: cross(0.3) bottom -> 0 (i); cross(1.1) top -> 1 (i e^{1.1i});
+#           bar(1.7) top (-1); total e^{1.1i} at output 1
+#   mode 2: bar(0.5) top (-1); bar(0.7) bottom (e^{0.7i}); cross(1.3) top -> 3
+#           (i e^{1.3i}); total -i e^{2.0i} at output 3
+#   mode 3: bar(0.5) bottom (e^{0.5i}); cross(1.3) bottom -> 2 (i); bar(1.7)
+#           bottom (e^{1.7i}); total i e^{2.2i} at output 2
+_MESH4_PA = [0.0, math.pi, math.pi, 0.0, 0.0, math.pi]
+_MESH4_PB = [0.3, 0.5, 0.7, 1.1, 1.3, 1.7]
+
+
+def _mesh4_expected():
+    E = np.zeros((4, 4), np.complex128)
+    E[0, 0] = np.exp(0.3j)
+    E[1, 1] = np.exp(1.1j)
+    E[3, 2] = -1j * np.exp(2.0j)
+    E[2, 3] = 1j * np.exp(2.2j)
+    return E
+
+
+def _mesh_pins_hold(mzi_fn, clements_fn):
+    """Every closed-form value of the mesh convention, as booleans."""
+    ok = []
+    for pb in (0.4, 1.9, -2.3):
+        ok.append(np.allclose(mzi_fn(math.pi, pb), _mzi_bar(pb), atol=1e-15))
+        ok.append(np.allclose(mzi_fn(0.0, pb), _mzi_cross(pb), atol=1e-15))
+    ph = np.array([v for ab in zip(_MESH4_PA, _MESH4_PB) for v in ab])
+    ok.append(np.allclose(clements_fn(4, ph), _mesh4_expected(), atol=1e-15))
+    return ok
+
+
+def test_mzi_closed_forms_and_phased_permutation_mesh():
+    assert oracle.clements_layout(4) == [(0, 0), (0, 2), (1, 1), (2, 0), (2, 2), (3, 1)]
+    assert all(_mesh_pins_hold(oracle.mzi, oracle.clements_unitary))
+
+
+def test_mesh_pins_catch_planted_convention_mistakes(monkeypatch):
+    """Each plausible mistake in the MZI convention, planted in the oracle,
+    fails the pins above: a reversed composition order, phi_a applied to mode
+    1, and e^{-i phi} for the phase shifter."""
+    bs = oracle.beam_splitter_rx(math.pi / 2.0)
+
+    def reversed_order(pa, pb):
+        return bs @ np.diag([np.exp(1j * pa), 1]) @ bs @ np.diag([1, np.exp(1j * pb)])
+
+    def phase_a_on_mode_1(pa, pb):
+        return np.diag([1, np.exp(1j * pb)]) @ bs @ np.diag([1, np.exp(1j * pa)]) @ bs
+
+    def conjugate_phase(pa, pb):
+        return np.diag([1, np.exp(-1j * pb)]) @ bs @ np.diag([np.exp(-1j * pa), 1]) @ bs
+
+    for wrong in (reversed_order, phase_a_on_mode_1, conjugate_phase):
+        monkeypatch.setattr(oracle, "mzi", wrong)
+        held = _mesh_pins_hold(oracle.mzi, oracle.clements_unitary)
+        assert not all(held[:6]), wrong.__name__      # a single-MZI closed form fails
+        assert not held[6], wrong.__name__            # and so does the 4-mode mesh
+    monkeypatch.undo()
+    assert all(_mesh_pins_hold(oracle.mzi, oracle.clements_unitary))
+
+
 def test_minor_gradient_matches_finite_differences():
     m, n = 5, 3
     T = inputs.first_modes_input(m, n)
