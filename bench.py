@@ -103,10 +103,12 @@ def time_variant(torch, slos, T, U_np, dtype, compensated, steps, warmup):
     return res
 
 
-def time_batched(torch, slos, steps, warmup, count=4096, seed=4):
+def time_batched(torch, slos, steps, warmup, count=4096, seed=4, with_c128=True):
     """4096 uneven instances (m in 6..14, n in 2..min(7, m), <= 2 photons per
     mode, Haar U each), complex64, one persistent launch replayed from a HIP
-    graph.  Launch options come from the autotuner (cached per device)."""
+    graph.  Launch options come from the autotuner: its MI355X results shipped
+    with the package (the options the config-4 parity test runs), else a
+    tuning run on this device."""
     from paper_2204_00602_amd import autotune, inputs
     inst = inputs.batch_instances(count, seed=seed)
     states = [t for (_, _, t, _) in inst]
@@ -145,6 +147,8 @@ def time_batched(torch, slos, steps, warmup, count=4096, seed=4):
     b.close()
     del out, sum_p, U
     torch.cuda.empty_cache()
+    if not with_c128:
+        return res
 
     # the same instances in complex128: batched (tuned, graph replay), and the
     # plain path, one plan per instance launched back to back on one stream
@@ -493,8 +497,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched and gradient workloads")
-    ap.add_argument("--only", choices=["c64comp", "c64", "c128"], default=None,
-                    help="time one variant only (for profiling runs)")
+    ap.add_argument("--only", choices=["c64comp", "c64", "c128", "batch"], default=None,
+                    help="time one variant, or the complex64 batch alone (for profiling runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 1 GiB device copy three times, so that a PMC "
                          "profile of this command holds the counters of a copy of known size")
@@ -520,6 +524,12 @@ def main():
         del src, dst
         torch.cuda.empty_cache()
         print("[bench] copy calibration: 3 x 1 GiB device-to-device copies", file=sys.stderr, flush=True)
+
+    if args.only == "batch":
+        res = time_batched(torch, slos, args.steps, args.warmup, with_c128=False)
+        print(f"[bench] batched: {res['ms_per_batch']:.3f} ms/batch", file=sys.stderr, flush=True)
+        print(json.dumps({"batched": res}), flush=True)
+        return
 
     m, n = M_MODES, N_PHOTONS
     T = inputs.first_modes_input(m, n)

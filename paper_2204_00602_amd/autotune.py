@@ -48,6 +48,20 @@ PLAN_START = {"leaf_max": 0, "low_block_max": 0, "outputs_per_lane": 0, "block_t
 BATCH_START = {"leaf_max": 0, "outputs_per_lane": 0, "block_threads": 0, "grid_blocks": 0}
 
 
+# The tuner's results on MI355X for the benchmark workloads, shipped with the
+# package and written by `python -m paper_2204_00602_amd.autotune ... --cache`
+# on that device.  tune_plan / tune_batch return an entry found here before
+# consulting the per-user cache, so the benchmark times, and the tests check,
+# exactly the options recorded here.
+SHIPPED_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_mi355x.json")
+
+
+def shipped_options(key: str) -> Optional[dict]:
+    """Options shipped for a workload key (see plan_key / batch_key), or None."""
+    hit = _load(SHIPPED_PATH).get(key)
+    return dict(hit["options"]) if hit else None
+
+
 def default_cache_path() -> str:
     return os.environ.get("SLOS_TUNE_CACHE",
                           os.path.join(os.path.expanduser("~"), ".cache", "slos_tune.json"))
@@ -142,6 +156,9 @@ def tune_plan(input_state: Sequence[int], dtype: str = "c64", compensated: bool 
     cache = cache or default_cache_path()
     key = plan_key(input_state, dtype, compensated)
     if not retune:
+        hit = shipped_options(key)
+        if hit:
+            return hit
         hit = _load(cache).get(key)
         if hit:
             return hit["options"]
@@ -177,6 +194,9 @@ def tune_batch(input_states, dtype: str = "c64", Us=None, reps: int = 5, warmup:
     cache = cache or default_cache_path()
     key = batch_key(input_states, dtype)
     if not retune:
+        hit = shipped_options(key)
+        if hit:
+            return hit
         hit = _load(cache).get(key)
         if hit:
             return hit["options"]

@@ -86,15 +86,32 @@ def test_batch_graph_replays_follow_new_inputs():
         assert np.abs(s.cpu().numpy() - 1.0).max() <= 1e-6
 
 
-def test_config4_sampled_instances():
+@pytest.mark.parametrize("launch", ["defaults", "benchmarked", "benchmarked-graph"])
+def test_config4_sampled_instances(launch):
     """4096 instances, m in 6..14, n in 2..min(7, m), <= 2 photons per mode, c64:
     sum P = 1 for every instance, and every output of a seeded subset of 64
-    instances (plus the largest) against the oracle."""
+    instances (plus the largest) against the oracle.  "benchmarked" runs the
+    options the benchmark times (the tuner's shipped MI355X result), the
+    "-graph" variant through the captured graph the benchmark replays."""
+    from paper_2204_00602_amd import autotune
     inst = inputs.batch_instances(4096, seed=4)
-    b = slos.Batch([t for (_, _, t, _) in inst], "c64")
+    states = [t for (_, _, t, _) in inst]
+    opts = None
+    if launch != "defaults":
+        opts = autotune.shipped_options(autotune.batch_key(states, "c64"))
+        assert opts is not None, "no shipped tuning entry for the config-4 workload on this device"
+        assert opts == autotune.tune_batch(states, "c64")
+        print(f"[batch] config 4 with the benchmarked options {opts}", flush=True)
+    b = slos.Batch(states, "c64", options=opts)
     U = b.pack_u([u for (_, _, _, u) in inst])
     s = torch.zeros(b.count, dtype=torch.float64, device="cuda")
-    out = b.amplitudes(U, sum_p=s)
+    if launch == "benchmarked-graph":
+        out = torch.empty(b.total_outputs, dtype=torch.complex64, device="cuda")
+        b.capture(U, out, s)
+        for _ in range(3):
+            b.replay()
+    else:
+        out = b.amplitudes(U, sum_p=s)
     torch.cuda.synchronize()
     assert np.abs(s.cpu().numpy() - 1.0).max() <= 1e-6
     rng = np.random.default_rng(404)
