@@ -179,6 +179,25 @@ int slos_amplitudes(slos_plan_t plan, const void *U, void *out, double *sum_p, v
 int slos_probs(slos_plan_t plan, const void *U, void *probs, double *sum_p, void *stream);
 
 /*
+ * slos_amplitudes for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments, results bit for bit those of slos_amplitudes, and no
+ * hipMalloc, hipFree or other allocating call: the pass's scratch (vacuum,
+ * the two intermediate layers, the FP64 partial sums and the work counters)
+ * lives in the library's static device area of 32 MiB per GPU, held from the
+ * first call on a GPU until the process ends, instead of in the plan's own
+ * buffers.  Plans whose scratch exceeds 32 MiB (about 4M complex64 states in
+ * the two largest intermediate layers together, e.g. m = 16, n = 8 fits and
+ * m = 20, n = 10 does not) are rejected with SLOS_ERR_SIZE_OVERFLOW, and plans
+ * built with SLOS_KEEP_LAYERS with SLOS_ERR_INVALID_ARG; the plan's device must
+ * be current.  Every call on one GPU shares that one area: calls that overlap
+ * in time on a GPU (on different streams, or from different threads) race and
+ * must be ordered by the caller.  Each call starts from what it writes itself,
+ * not from what an earlier call left.
+ */
+int slos_amplitudes_noalloc(slos_plan_t plan, const void *U, void *out, double *sum_p, void *stream);
+
+/*
  * The same input state through `batch` unitaries in one pass (one launch per
  * layer; instance b is blockIdx.y).  U: device, batch x m x m (instance b at
  * U + b*m*m); out / probs: device, batch x M (instance b at b*M); sum_p:

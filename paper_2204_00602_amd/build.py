@@ -15,7 +15,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libslos.so")
-SOURCES = ["plan.cpp", "layer.hip", "backward.hip", "sample.hip", "postselect.hip", "select.hip", "source.hip"]
+SOURCES = ["plan.cpp", "layer.hip", "backward.hip", "sample.hip", "postselect.hip", "select.hip", "source.hip",
+           "static_scratch.hip"]
 ARCH = os.environ.get("SLOS_OFFLOAD_ARCH", "gfx950")
 
 

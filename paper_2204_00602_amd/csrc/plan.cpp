@@ -1024,8 +1024,18 @@ int slos_plan_leaf(slos_plan_t p, int k, int64_t idx, int64_t *out_base, int32_t
     return SLOS_OK;
 }
 
+// Device buffers of one forward pass beyond its inputs and outputs: the vacuum
+// A_0, the two ping-pong layers, the FP64 partial sums (plus the reduction
+// stage after them) and the ticket counters.
+struct ForwardScratch {
+    void *vac;
+    void *buf[2];
+    double *partials;
+    uint32_t *tickets;
+};
+
 static int run_forward(slos_plan_t p, int batch, const void *U, void *out, double *sum_p, void *stream,
-                       int last_mode)
+                       int last_mode, const ForwardScratch *over = nullptr)
 {
     int rc = check_plan(p);
     if (rc) return rc;
@@ -1047,8 +1057,10 @@ static int run_forward(slos_plan_t p, int batch, const void *U, void *out, doubl
     const int wpb = p->opts.block_threads / 64;
     hipStream_t hs = (hipStream_t)stream;
     const uint64_t tstride = (uint64_t)(n + 1) * SLOS_XCDS * SLOS_TICKET_STRIDE;
+    const ForwardScratch sc = over ? *over : ForwardScratch{p->d_vac, {p->d_buf[0], p->d_buf[1]}, p->d_partials,
+                                                            p->d_tickets};
     {
-        int e = slos_launch_zero_u32(p->d_tickets, (int)(tstride * batch), stream);
+        int e = slos_launch_zero_u32(sc.tickets, (int)(tstride * batch), stream);
         if (e) return hip_fail((hipError_t)e, "ticket reset kernel");
     }
     if (p->timing) {
@@ -1064,8 +1076,8 @@ static int run_forward(slos_plan_t p, int batch, const void *U, void *out, doubl
             lp.x_stride = p->keep_stride * es;
             lp.y_stride = k == n ? out_bytes : p->keep_stride * es;
         } else {
-            lp.X = k == 1 ? p->d_vac : p->d_buf[(k - 1) & 1];
-            lp.Y = k == n ? out : p->d_buf[k & 1];
+            lp.X = k == 1 ? sc.vac : sc.buf[(k - 1) & 1];
+            lp.Y = k == n ? out : sc.buf[k & 1];
             lp.x_stride = k == 1 ? 0 : p->buf_stride[(k - 1) & 1] * es;  // every instance reads the one vacuum
             lp.y_stride = k == n ? out_bytes : p->buf_stride[k & 1] * es;
         }
@@ -1085,7 +1097,7 @@ static int run_forward(slos_plan_t p, int batch, const void *U, void *out, doubl
         lp.k = k;
         lp.col = p->photons[k - 1];
         lp.norm_t = p->norm_t;
-        lp.partials = p->d_partials;
+        lp.partials = sc.partials;
         LayerLaunch ll{};
         ll.c64 = p->c64;
         ll.mode = k == n ? last_mode : SLOS_MODE_MID;
@@ -1109,11 +1121,11 @@ static int run_forward(slos_plan_t p, int batch, const void *U, void *out, doubl
         // a layer with few leaves deals smaller chunks, so that every XCD gets some
         lp.xcd_chunk = (uint32_t)std::max<uint64_t>(
             1, std::min<uint64_t>((uint64_t)p->opts.xcd_chunk, lp.nleaves / (4 * SLOS_XCDS)));
-        lp.tickets = p->d_tickets + (size_t)k * SLOS_XCDS * SLOS_TICKET_STRIDE;
+        lp.tickets = sc.tickets + (size_t)k * SLOS_XCDS * SLOS_TICKET_STRIDE;
         const bool comp_k = ll.compensated == SLOS_COMP_BIASED;
         const bool comp_next = k < n && p->comp && !(p->flags & SLOS_COMP_KNUTH) && k + 1 >= p->opts.comp_from_layer;
         lp.vmax_in = (comp_k && k >= 2)
-                         ? p->d_tickets + (size_t)(k - 1) * SLOS_XCDS * SLOS_TICKET_STRIDE + SLOS_VMAX_SLOT
+                         ? sc.tickets + (size_t)(k - 1) * SLOS_XCDS * SLOS_TICKET_STRIDE + SLOS_VMAX_SLOT
                          : nullptr;
         lp.vmax_out = comp_next ? lp.tickets + SLOS_VMAX_SLOT : nullptr;
         lp.ticket_leaves = (uint32_t)p->opts.ticket_leaves;
@@ -1123,7 +1135,7 @@ static int run_forward(slos_plan_t p, int batch, const void *U, void *out, doubl
         if (p->timing && (e = (int)hipEventRecord(p->events[k], hs)))
             return hip_fail((hipError_t)e, "timing event");
         if (k == n && sum_p) {
-            e = slos_launch_reduce(p->d_partials, p->n_partials, p->d_partials + p->n_partials * p->batch_cap, sum_p,
+            e = slos_launch_reduce(sc.partials, p->n_partials, sc.partials + p->n_partials * p->batch_cap, sum_p,
                                    stream, batch, p->n_partials);
             if (e) return hip_fail((hipError_t)e, "sum reduction kernel");
             if (p->timing) {
@@ -1273,6 +1285,55 @@ int slos_amplitudes(slos_plan_t p, const void *U, void *out, double *sum_p, void
 int slos_probs(slos_plan_t p, const void *U, void *probs, double *sum_p, void *stream)
 {
     return run_forward(p, 1, U, probs, sum_p, stream, SLOS_MODE_PROB);
+}
+
+static size_t round256(size_t b) { return (b + 255) / 256 * 256; }
+
+int slos_amplitudes_noalloc(slos_plan_t p, const void *U, void *out, double *sum_p, void *stream)
+{
+    int rc = check_plan(p);
+    if (rc) return rc;
+    if (p->keep)
+        return fail(SLOS_ERR_INVALID_ARG, "slos_amplitudes_noalloc: the plan keeps its layers (SLOS_KEEP_LAYERS); "
+                                          "use slos_amplitudes");
+    if (!U || !out) return fail(SLOS_ERR_INVALID_ARG, "U and out must be device pointers");
+    const int n = p->n;
+    const size_t es = p->elem();
+    // the plan's own buffers for one instance, carved from the static area:
+    // vacuum | layer buffer 0 | layer buffer 1 | partials + reduction stage | tickets
+    const size_t b_vac = round256(es + SLOS_BUFFER_SLACK);
+    const size_t b_buf0 = p->buf_stride[0] ? round256(p->buf_stride[0] * es + SLOS_BUFFER_SLACK) : 0;
+    const size_t b_buf1 = p->buf_stride[1] ? round256(p->buf_stride[1] * es + SLOS_BUFFER_SLACK) : 0;
+    // (the reduction stage follows the partials of max_batch instances)
+    const size_t b_part = round256((size_t)(p->n_partials * p->batch_cap + SLOS_REDUCE_STAGE) * sizeof(double));
+    const size_t b_tick = round256((size_t)(n + 1) * SLOS_XCDS * SLOS_TICKET_STRIDE * sizeof(uint32_t));
+    const size_t need = b_vac + b_buf0 + b_buf1 + b_part + b_tick;
+    if (need > SLOS_STATIC_SCRATCH_BYTES)
+        return fail(SLOS_ERR_SIZE_OVERFLOW,
+                    "slos_amplitudes_noalloc: m = %d, n = %d needs %zu bytes of scratch; the static area holds %zu",
+                    p->m, n, need, (size_t)SLOS_STATIC_SCRATCH_BYTES);
+    void *base = nullptr;
+    int dev = -1;
+    int e = slos_static_scratch(&base, &dev);
+    if (e) return hip_fail((hipError_t)e, "static scratch address");
+    if (dev != p->device)
+        return fail(SLOS_ERR_INVALID_ARG, "slos_amplitudes_noalloc: the plan lives on device %d, device %d is current",
+                    p->device, dev);
+    char *c = (char *)base;
+    ForwardScratch sc{};
+    sc.vac = c;
+    sc.buf[0] = b_buf0 ? c + b_vac : nullptr;
+    sc.buf[1] = b_buf1 ? c + b_vac + b_buf0 : nullptr;
+    sc.partials = (double *)(c + b_vac + b_buf0 + b_buf1);
+    sc.tickets = (uint32_t *)(c + b_vac + b_buf0 + b_buf1 + b_part);
+    if (n > 0) {
+        // the area keeps whatever the last call left: A_0 = [1] is written afresh
+        // (the ticket counters are zeroed by the pass itself, and the partials
+        // and the reduction stage are written before they are read)
+        e = slos_launch_vacuum(sc.vac, p->c64, SLOS_MODE_AMPL, nullptr, stream);
+        if (e) return hip_fail((hipError_t)e, "vacuum kernel");
+    }
+    return run_forward(p, 1, U, out, sum_p, stream, SLOS_MODE_AMPL, &sc);
 }
 
 int slos_amplitudes_many(slos_plan_t p, int batch, const void *U, void *out, double *sum_p, void *stream)

@@ -179,6 +179,12 @@ int slos_launch_reduce(const double *partials, int64_t count, double *stage, dou
 int slos_launch_vacuum(void *out, int c64, int mode, double *sum_p, void *stream);
 int slos_launch_zero_u32(uint32_t *buf, int count, void *stream);
 
+// The static device scratch area (static_scratch.hip): SLOS_STATIC_SCRATCH_BYTES
+// per GPU.  slos_static_scratch returns the current device's address of it
+// (looked up once per device) and that device's index; a hipError_t as int.
+#define SLOS_STATIC_SCRATCH_BYTES ((size_t)32 << 20)
+int slos_static_scratch(void **ptr, int *device);
+
 // ---- differentiation ----------------------------------------------------------
 
 // One unit of the reverse layer k: the low block of a forward leaf of layer k

@@ -83,6 +83,7 @@ def lib():
     L.slos_plan_leaf.argtypes = [vp, ctypes.c_int, ctypes.c_int64, i64p, i32p, i32p, i32p]
     L.slos_amplitudes.argtypes = [vp, vp, vp, vp, vp]
     L.slos_probs.argtypes = [vp, vp, vp, vp, vp]
+    L.slos_amplitudes_noalloc.argtypes = [vp, vp, vp, vp, vp]
     L.slos_backward.argtypes = [vp, vp, vp, vp, vp]
     L.slos_amplitudes_many.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp]
     L.slos_probs_many.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp]
@@ -119,7 +120,7 @@ def lib():
     L.slos_last_error.argtypes = []
     L.slos_last_error.restype = ctypes.c_char_p
     for name in ("slos_fock_count", "slos_fock_rank", "slos_fock_unrank", "slos_rank", "slos_unrank", "slos_plan",
-                 "slos_plan_ex", "slos_plan_info", "slos_plan_leaf", "slos_amplitudes",
+                 "slos_plan_ex", "slos_plan_info", "slos_plan_leaf", "slos_amplitudes", "slos_amplitudes_noalloc",
                  "slos_probs", "slos_cdf", "slos_marginals", "slos_sample", "slos_postselect", "slos_select", "slos_amplitudes_many",
                  "slos_probs_many", "slos_backward_many", "slos_plan_set_timing", "slos_plan_layer_ms", "slos_backward",
                  "slos_mesh_unitary", "slos_mesh_backward", "slos_batch_plan", "slos_batch_offsets",

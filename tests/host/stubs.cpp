@@ -43,3 +43,4 @@ int slos_launch_postselect_table(const PostselectParams &, int, const int64_t *,
 {
     return no_launch();
 }
+int slos_static_scratch(void **, int *) { return no_launch(); }
