@@ -76,14 +76,14 @@ typedef struct slos_plan_s *slos_plan_t;
 /* Tuning options; a zero field takes its default. */
 typedef struct slos_options {
     int32_t leaf_max;        /* max states per leaf tile, <= 65536 (default 16384 for
-                                c64, 8192 for c128, 1024 with SLOS_KEEP_LAYERS); a
+                                c64, 8192 for c128, 4096 with SLOS_KEEP_LAYERS); a
                                 small layer uses smaller leaves so that it still
                                 spreads over ~2048 workgroups                        */
     int32_t comp_from_layer; /* first compensated layer (default 1: every layer)     */
-    int32_t block_threads;   /* threads per workgroup: 64, 128, 256 (default 256)    */
+    int32_t block_threads;   /* threads per workgroup: 64, 128, 256 (default 256;
+                                128 with SLOS_KEEP_LAYERS)                           */
     int32_t grid_blocks;     /* cap on workgroups per layer launch (default 2048)    */
-    int32_t outputs_per_lane;/* 1, 2 or 4 outputs per lane per tile (default 2; 4
-                                for c64 with SLOS_KEEP_LAYERS)                       */
+    int32_t outputs_per_lane;/* 1, 2 or 4 outputs per lane per tile (default 2)       */
     int32_t xcd_chunk;       /* consecutive leaves dealt to one XCD at a time
                                 (default 128; fewer when a layer has few leaves)    */
     int32_t ticket_leaves;   /* consecutive leaves a workgroup takes per work ticket
@@ -309,6 +309,23 @@ int slos_backward(slos_plan_t plan, const void *U, const void *grad_a, void *gra
 /* slos_backward for the `batch` instances of the last slos_amplitudes_many /
  * slos_probs_many call: grad_a batch x M, grad_U batch x m x m. */
 int slos_backward_many(slos_plan_t plan, int batch, const void *U, const void *grad_a, void *grad_U, void *stream);
+
+/*
+ * The squared-error loss on selected outputs and its gradient with respect to
+ * the amplitudes, for `batch` instances of this plan's output set (the loss of
+ * the differentiation workload; Section 4.6 trains on squared residuals of
+ * output probabilities).  a: device, batch x M amplitudes in the plan's type
+ * (instance b at b * M); ranks: device, `count` distinct output ranks (colex,
+ * see slos_rank); p_target: device FP64, batch x count; grad_a: device, batch x
+ * M, written in full: 4 (|a_b(S)|^2 - p_target[b, t]) a_b(S) at S = ranks[t]
+ * and 0 elsewhere, the PyTorch-convention gradient of
+ * L_b = sum_t (|a_b(ranks[t])|^2 - p_target[b, t])^2 that slos_backward_many
+ * takes; loss: device FP64, batch values L_b summed in a fixed order, or NULL.
+ * One launch, no allocation.  Ranks outside [0, M) are ignored.  The caller
+ * owns every buffer; grad_a must not alias a.
+ */
+int slos_sq_loss_grad_many(slos_plan_t plan, int batch, const void *a, const int64_t *ranks, int64_t count,
+                           const double *p_target, void *grad_a, double *loss, void *stream);
 
 /*
  * Rectangular MZI mesh (Section 2: any unitary decomposes into beam splitters

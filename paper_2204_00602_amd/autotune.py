@@ -68,8 +68,13 @@ def default_cache_path() -> str:
 
 
 def _device_name() -> str:
+    """The device part of a cache key: architecture and compute-unit count
+    (e.g. gfx950-256cu), which do not depend on how the runtime names the
+    board (the marketing name differs between processes on one machine)."""
     import torch
-    return torch.cuda.get_device_name(torch.cuda.current_device())
+    props = torch.cuda.get_device_properties(torch.cuda.current_device())
+    arch = getattr(props, "gcnArchName", "") or torch.cuda.get_device_name(torch.cuda.current_device())
+    return f"{arch.split(':')[0]}-{props.multi_processor_count}cu"
 
 
 def _load(path: str) -> dict:

@@ -84,10 +84,11 @@ __global__ __launch_bounds__(64) void bwd_layer_kernel(BwdParams p)
         for (int j = 0; j < p.m; ++j) part[j * 64 + lane] = double2{0.0, 0.0};
         const uint32_t *__restrict__ succ = p.succ + U.succ_off;
         const uint64_t *__restrict__ hb = p.hbase + U.hbase_off;
-        for (uint32_t y0 = 0; y0 < U.low_size; y0 += 64) {
+        const uint32_t yend = U.low_size - U.y0 < p.chunk ? U.low_size : U.y0 + p.chunk;
+        for (uint32_t y0 = U.y0; y0 < yend; y0 += 64) {
             const uint32_t y = y0 + lane;
-            const bool ok = y < U.low_size;
-            const uint32_t yc = ok ? y : U.low_size - 1u;
+            const bool ok = y < yend;
+            const uint32_t yc = ok ? y : yend - 1u;
             const C a = A[U.low_base + yc];
             const double ar = (double)a.x, ai = (double)a.y;
             double accr = 0.0, acci = 0.0;
@@ -137,51 +138,93 @@ __global__ __launch_bounds__(64) void bwd_layer_kernel(BwdParams p)
     }
 }
 
-// colsum[j] = sum over units of partials[unit][j], fixed order
-__global__ __launch_bounds__(256) void colsum_kernel(const double2 *__restrict__ partials, uint64_t nunits, int m,
-                                                     double2 *__restrict__ colsum, uint64_t partials_stride,
-                                                     uint64_t colsum_stride)
+// One launch after all reverse layers: for every layer k, colsum_k[j] = sum over
+// the layer's units u of partials_k[u][j], each formed in a fixed order (per
+// thread over u = tid, tid + 256, ..., then a tree over the 256 threads), then
+// G_U[j, i] = sum over layers k with i_k = i of colsum_k[j], in order of k.
+template <typename T>
+__global__ __launch_bounds__(256) void colsum_gradu_kernel(const double2 *__restrict__ partials, ColsumLayers L,
+                                                            const int32_t *__restrict__ photons, int n, int m,
+                                                            typename Cb<T>::type *__restrict__ GU,
+                                                            uint64_t partials_stride, uint64_t gu_stride)
 {
+    using C = typename Cb<T>::type;
     __shared__ double2 sh[256];
+    __shared__ double2 cs[SLOS_MAX_PHOTONS];
     partials += blockIdx.y * partials_stride;  // instance blockIdx.y (element strides)
-    colsum += blockIdx.y * colsum_stride;
+    GU += blockIdx.y * gu_stride;
     const int j = blockIdx.x;
-    double2 s{0.0, 0.0};
-    for (uint64_t u = threadIdx.x; u < nunits; u += 256) {
-        const double2 v = partials[u * (uint64_t)m + j];
-        s.x += v.x;
-        s.y += v.y;
+    for (int k = 0; k < n; ++k) {
+        const double2 *pk = partials + L.off[k];
+        double2 s{0.0, 0.0};
+        for (uint64_t u = threadIdx.x; u < L.nunits[k]; u += 256) {
+            const double2 v = pk[u * (uint64_t)m + j];
+            s.x += v.x;
+            s.y += v.y;
+        }
+        sh[threadIdx.x] = s;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) {
+                sh[threadIdx.x].x += sh[threadIdx.x + w].x;
+                sh[threadIdx.x].y += sh[threadIdx.x + w].y;
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) cs[k] = sh[0];
+        __syncthreads();  // sh is reused by the next layer; cs[k] is visible
+    }
+    for (int i = threadIdx.x; i < m; i += blockDim.x) {
+        double gr = 0.0, gi = 0.0;
+        for (int k = 0; k < n; ++k)
+            if (photons[k] == i) {
+                gr += cs[k].x;
+                gi += cs[k].y;
+            }
+        GU[(size_t)j * m + i] = C{(T)gr, (T)gi};
+    }
+}
+
+// The squared-error loss on target outputs of a batch and its gradient with
+// respect to the amplitudes.  One workgroup per instance b:
+//   L_b = sum_t (|a_b(r_t)|^2 - P_t[b, t])^2 in FP64 (fixed-order sum), and
+//   grad_a[b] = 4 (|a_b(r_t)|^2 - P_t[b, t]) a_b(r_t) at r_t, 0 elsewhere
+// (the PyTorch-convention gradient d L / d Re a + i d L / d Im a).  The zeros are
+// stored and complete before any target value is written to the same row.
+template <typename T>
+__global__ __launch_bounds__(256) void sq_loss_kernel(const typename Cb<T>::type *__restrict__ a, uint64_t M,
+                                                       const int64_t *__restrict__ ranks, int64_t count,
+                                                       const double *__restrict__ p_target,
+                                                       typename Cb<T>::type *__restrict__ grad_a,
+                                                       double *__restrict__ loss)
+{
+    using C = typename Cb<T>::type;
+    __shared__ double sh[256];
+    const uint64_t b = blockIdx.x;
+    a += b * M;
+    grad_a += b * M;
+    p_target += b * (uint64_t)count;
+    for (uint64_t r = threadIdx.x; r < M; r += 256) grad_a[r] = C{(T)0, (T)0};
+    __builtin_amdgcn_s_waitcnt(0);  // this wave's zeros have reached memory
+    __syncthreads();
+    double s = 0.0;
+    for (int64_t t = threadIdx.x; t < count; t += 256) {
+        const int64_t r = ranks[t];
+        if (r < 0 || (uint64_t)r >= M) continue;  // outside the output set: ignored
+        const C v = a[r];
+        const double P = (double)v.x * (double)v.x + (double)v.y * (double)v.y;
+        const double d = P - p_target[t];
+        s += d * d;
+        const T f = (T)(4.0 * d);
+        grad_a[r] = C{f * v.x, f * v.y};
     }
     sh[threadIdx.x] = s;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) {
-            sh[threadIdx.x].x += sh[threadIdx.x + w].x;
-            sh[threadIdx.x].y += sh[threadIdx.x + w].y;
-        }
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) colsum[j] = sh[0];
-}
-
-// G_U[j, i] = sum over layers k with i_k = i of colsum_k[j], in order of k
-template <typename T>
-__global__ void gradu_kernel(const double2 *__restrict__ colsum, const int32_t *__restrict__ photons, int n, int m,
-                             typename Cb<T>::type *__restrict__ GU, uint64_t colsum_stride, uint64_t gu_stride)
-{
-    using C = typename Cb<T>::type;
-    colsum += blockIdx.y * colsum_stride;  // instance blockIdx.y (element strides)
-    GU += blockIdx.y * gu_stride;
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= m * m) return;
-    const int j = idx / m, i = idx % m;
-    double gr = 0.0, gi = 0.0;
-    for (int k = 1; k <= n; ++k)
-        if (photons[k - 1] == i) {
-            gr += colsum[(size_t)(k - 1) * m + j].x;
-            gi += colsum[(size_t)(k - 1) * m + j].y;
-        }
-    GU[(size_t)j * m + i] = C{(T)gr, (T)gi};
+    if (threadIdx.x == 0 && loss) loss[b] = sh[0];
 }
 
 // ---- rectangular MZI mesh --------------------------------------------------------
@@ -429,25 +472,28 @@ int slos_launch_bwd_layer(const BwdParams &p, int c64, int grid, void *stream, i
     return (int)hipGetLastError();
 }
 
-int slos_launch_colsum(const void *partials, uint64_t nunits, int m, void *colsum, void *stream, int batch,
-                       uint64_t partials_stride, uint64_t colsum_stride)
+int slos_launch_colsum_gradu(const void *partials, const ColsumLayers &L, const int32_t *photons, int n, int m,
+                             void *GU, int c64, void *stream, int batch, uint64_t partials_stride, uint64_t gu_stride)
 {
-    hipLaunchKernelGGL(colsum_kernel, dim3(m, batch > 1 ? batch : 1), dim3(256), 0, (hipStream_t)stream,
-                       (const double2 *)partials, nunits, m, (double2 *)colsum, partials_stride, colsum_stride);
+    const dim3 g(m, batch > 1 ? batch : 1);
+    if (c64)
+        hipLaunchKernelGGL(colsum_gradu_kernel<float>, g, dim3(256), 0, (hipStream_t)stream, (const double2 *)partials,
+                           L, photons, n, m, (float2 *)GU, partials_stride, gu_stride);
+    else
+        hipLaunchKernelGGL(colsum_gradu_kernel<double>, g, dim3(256), 0, (hipStream_t)stream,
+                           (const double2 *)partials, L, photons, n, m, (double2 *)GU, partials_stride, gu_stride);
     return (int)hipGetLastError();
 }
 
-int slos_launch_gradu(const void *colsum, const int32_t *photons, int n, int m, void *GU, int c64, void *stream,
-                      int batch, uint64_t colsum_stride, uint64_t gu_stride)
+int slos_launch_sq_loss(const void *a, uint64_t M, const int64_t *ranks, int64_t count, const double *p_target,
+                        void *grad_a, double *loss, int batch, int c64, void *stream)
 {
-    const int total = m * m;
-    const dim3 g((total + 255) / 256, batch > 1 ? batch : 1);
     if (c64)
-        hipLaunchKernelGGL(gradu_kernel<float>, g, dim3(256), 0, (hipStream_t)stream, (const double2 *)colsum,
-                           photons, n, m, (float2 *)GU, colsum_stride, gu_stride);
+        hipLaunchKernelGGL(sq_loss_kernel<float>, dim3(batch), dim3(256), 0, (hipStream_t)stream, (const float2 *)a, M,
+                           ranks, count, p_target, (float2 *)grad_a, loss);
     else
-        hipLaunchKernelGGL(gradu_kernel<double>, g, dim3(256), 0, (hipStream_t)stream, (const double2 *)colsum,
-                           photons, n, m, (double2 *)GU, colsum_stride, gu_stride);
+        hipLaunchKernelGGL(sq_loss_kernel<double>, dim3(batch), dim3(256), 0, (hipStream_t)stream,
+                           (const double2 *)a, M, ranks, count, p_target, (double2 *)grad_a, loss);
     return (int)hipGetLastError();
 }
 

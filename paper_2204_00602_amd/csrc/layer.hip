@@ -600,7 +600,8 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? (RR == 2 ? 6 : 3) : (RR <= 2 
             if (lane == 0) p.partials[li * (uint64_t)W + (uint64_t)wv] = psum;
         }
         // every wave is done with this low block before the next copy lands
-        __builtin_amdgcn_s_waitcnt(0);
+        // (the barrier's workgroup-scope fence waits for the waves' LDS reads;
+        // their global stores may still be in flight, nothing here reads them)
         __syncthreads();
         cur = nxt;
         li = nli;

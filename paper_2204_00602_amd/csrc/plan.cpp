@@ -244,7 +244,6 @@ struct slos_plan_s {
     void *d_g[2] = {nullptr, nullptr};         // adjoint layers (ping-pong)
     void *d_bpart = nullptr;                   // double2 partials, all layers
     std::vector<uint64_t> bpart_off;           // per layer, in double2 units
-    void *d_colsum = nullptr;                  // double2 [n][m]
     int32_t *d_photons = nullptr;
     bool timing = false;
     bool timed_reduce = false;
@@ -415,8 +414,16 @@ struct slos_plan_s {
     }
 
     // reverse-layer units of layer k: one per forward leaf with K >= 1
+    // low states per reverse unit of layer k: 128, doubled (up to 1024) while
+    // the layer would still have more than 8192 units for a full batch
+    std::vector<uint32_t> unit_chunk;
+
     void build_units(int k)
     {
+        if ((int)unit_chunk.size() <= k) unit_chunk.resize(k + 1, 128u);
+        uint32_t ch = 128;
+        while (ch < 1024 && (Nk[k - 1] / ch) * (uint64_t)batch_cap > 8192) ch *= 2;
+        unit_chunk[k] = ch;
         std::vector<int32_t> occ(m);
         for (const LeafRec &L : leaves[k]) {
             if (L.K == 0) continue;
@@ -440,7 +447,12 @@ struct slos_plan_s {
                 hbase.push_back(colex_rank(B, m, occ.data()));
                 occ[j] -= 1;
             }
-            units[k].push_back(u);
+            // one unit per chunk of the low block, so that small layers still
+            // spread over many waves
+            for (uint32_t y0 = 0; y0 < u.low_size; y0 += unit_chunk[k]) {
+                u.y0 = y0;
+                units[k].push_back(u);
+            }
         }
     }
 
@@ -490,14 +502,12 @@ struct slos_plan_s {
         f(d_g[0]);
         f(d_g[1]);
         f(d_bpart);
-        f(d_colsum);
         f(d_photons);
         d_units = nullptr;
         d_succ = nullptr;
         d_hbase = nullptr;
         d_g[0] = d_g[1] = nullptr;
         d_bpart = nullptr;
-        d_colsum = nullptr;
         d_photons = nullptr;
         d_binom = nullptr;
         d_leaves = nullptr;
@@ -620,15 +630,18 @@ int slos_plan_ex(int m, int n, const int32_t *input_state, int flags, const slos
     // defaults: the fastest settings of a coordinate-descent search at
     // m=24, n=12 on gfx950 (a c128 low block of an 8192-state leaf takes
     // enough LDS to halve the resident workgroups, hence the smaller leaves)
-    if (o.leaf_max == 0) o.leaf_max = (flags & SLOS_KEEP_LAYERS) ? 1024 : (dt == SLOS_C64 ? 16384 : 8192);
+    // plans that keep their layers (gradients, many small unitaries) default to
+    // the fastest settings measured on the m=12, n=6 mesh gradient of 64
+    // unitaries: 4096-state leaves, two outputs per lane, 128-thread workgroups
+    if (o.leaf_max == 0) o.leaf_max = (flags & SLOS_KEEP_LAYERS) ? 4096 : (dt == SLOS_C64 ? 16384 : 8192);
     // low blocks of at most 24 KiB (c64: six workgroups of two-output tiles
     // per CU, the occupancy their 80 VGPRs allow) or 40 KiB (c128: three); the
     // leaves with larger low blocks are split further
     if (o.low_block_max == 0) o.low_block_max = (flags & SLOS_KEEP_LAYERS) ? -1 : (dt == SLOS_C64 ? 3072 : 2560);
     if (o.comp_from_layer == 0) o.comp_from_layer = 1;
-    if (o.block_threads == 0) o.block_threads = 256;
+    if (o.block_threads == 0) o.block_threads = (flags & SLOS_KEEP_LAYERS) ? 128 : 256;
     if (o.grid_blocks == 0) o.grid_blocks = 2048;
-    if (o.outputs_per_lane == 0) o.outputs_per_lane = (dt == SLOS_C64 && (flags & SLOS_KEEP_LAYERS)) ? 4 : 2;
+    if (o.outputs_per_lane == 0) o.outputs_per_lane = 2;
     if (o.xcd_chunk == 0) o.xcd_chunk = 128;
     if (o.ticket_leaves == 0) o.ticket_leaves = dt == SLOS_C64 ? 1 : 2;  // c64: the smaller leaves of its cap favour 1
     if (o.max_batch == 0) o.max_batch = 1;
@@ -949,8 +962,7 @@ int slos_plan_ex(int m, int n, const int32_t *input_state, int flags, const slos
             (rc = dev_upload(&p->d_photons, ph.data(), ph.size(), "photon list")) ||
             (rc = alloc_dev(&p->d_g[0], gmax * es * p->batch_cap, "adjoint layer")) ||
             (rc = alloc_dev(&p->d_g[1], gmax * es * p->batch_cap, "adjoint layer")) ||
-            (rc = alloc_dev(&p->d_bpart, p->bpart_stride * 16 * p->batch_cap, "gradient partials")) ||
-            (rc = alloc_dev(&p->d_colsum, (size_t)n * m * 16 * p->batch_cap, "gradient columns"))) {
+            (rc = alloc_dev(&p->d_bpart, p->bpart_stride * 16 * p->batch_cap, "gradient partials"))) {
             p->free_device();
             delete p;
             return rc;
@@ -1230,6 +1242,7 @@ static int run_backward(slos_plan_t p, int batch, const void *U, const void *gra
         bp.partials = (char *)p->d_bpart + p->bpart_off[k] * 16;
         bp.m = m;
         bp.col = p->photons[k - 1];
+        bp.chunk = p->unit_chunk[k];
         bp.gk_stride = bp.gkm1_stride = p->g_stride * es;
         bp.a_stride = p->keep_stride * es;
         bp.u_stride = mm * es;
@@ -1237,11 +1250,15 @@ static int run_backward(slos_plan_t p, int batch, const void *U, const void *gra
         const int grid = (int)std::max<uint64_t>(1, std::min<uint64_t>(bp.nunits, 4096));
         if ((e = slos_launch_bwd_layer(bp, c64, grid, stream, batch)))
             return hip_fail((hipError_t)e, "reverse layer");
-        if ((e = slos_launch_colsum(bp.partials, bp.nunits, m, (char *)p->d_colsum + (size_t)(k - 1) * m * 16,
-                                    stream, batch, p->bpart_stride, (uint64_t)n * m)))
-            return hip_fail((hipError_t)e, "column sum kernel");
     }
-    if ((e = slos_launch_gradu(p->d_colsum, p->d_photons, n, m, grad_U, c64, stream, batch, (uint64_t)n * m, mm)))
+    // every layer's column sums and G_U in one launch
+    ColsumLayers cl{};
+    for (int k = 1; k <= n; ++k) {
+        cl.off[k - 1] = p->bpart_off[k];
+        cl.nunits[k - 1] = p->units[k].size();
+    }
+    if ((e = slos_launch_colsum_gradu(p->d_bpart, cl, p->d_photons, n, m, grad_U, c64, stream, batch,
+                                      p->bpart_stride, mm)))
         return hip_fail((hipError_t)e, "gradient assembly");
     return SLOS_OK;
 }
@@ -1254,6 +1271,20 @@ int slos_backward(slos_plan_t p, const void *U, const void *grad_a, void *grad_U
 int slos_backward_many(slos_plan_t p, int batch, const void *U, const void *grad_a, void *grad_U, void *stream)
 {
     return run_backward(p, batch, U, grad_a, grad_U, stream);
+}
+
+int slos_sq_loss_grad_many(slos_plan_t p, int batch, const void *a, const int64_t *ranks, int64_t count,
+                           const double *p_target, void *grad_a, double *loss, void *stream)
+{
+    int rc = check_plan(p);
+    if (rc) return rc;
+    if (batch < 1 || batch > 65535) return fail(SLOS_ERR_INVALID_ARG, "batch = %d outside [1, 65535]", batch);
+    if (count < 0) return fail(SLOS_ERR_INVALID_ARG, "count = %lld is negative", (long long)count);
+    if (!a || !grad_a || (count > 0 && (!ranks || !p_target)))
+        return fail(SLOS_ERR_INVALID_ARG, "a, grad_a (and ranks, p_target when count > 0) must be device pointers");
+    int e = slos_launch_sq_loss(a, p->Nk[p->n], ranks, count, p_target, grad_a, loss, batch, p->c64 ? 1 : 0, stream);
+    if (e) return hip_fail((hipError_t)e, "squared-loss kernel");
+    return SLOS_OK;
 }
 
 int slos_mesh_unitary(int m, int batch, const double *phases, void *U, int dtype, void *stream)

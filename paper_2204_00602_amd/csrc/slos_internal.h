@@ -187,11 +187,13 @@ int slos_static_scratch(void **ptr, int *device);
 
 // ---- differentiation ----------------------------------------------------------
 
-// One unit of the reverse layer k: the low block of a forward leaf of layer k
-// (same high part h, K-1 low photons), which lies at low_base in A_{k-1}.
-// The successor of low state y through low mode i < q is the forward leaf's
-// state out_base + succ[succ_off + i*low_size + y]; through high mode j >= q it
-// is hbase[hbase_off + j - q] + y (the block of high part h + e_j in layer k).
+// One unit of the reverse layer k: the states y0 .. y0 + chunk - 1 (cut at
+// low_size) of the low block of a forward leaf of layer k (same high part h,
+// K-1 low photons), which lies at low_base in A_{k-1}; `chunk` is the layer's
+// BwdParams::chunk.  The successor of low state y through low mode i < q is the
+// forward leaf's state out_base + succ[succ_off + i*low_size + y]; through high
+// mode j >= q it is hbase[hbase_off + j - q] + y (the block of high part h + e_j
+// in layer k).
 struct BwdUnit {
     uint64_t out_base;
     uint64_t low_base;
@@ -199,7 +201,7 @@ struct BwdUnit {
     uint32_t low_size;
     uint32_t succ_off;
     uint32_t q;
-    uint32_t pad;
+    uint32_t y0;
 };
 static_assert(sizeof(BwdUnit) == 40, "BwdUnit must stay 40 bytes");
 
@@ -215,6 +217,7 @@ struct BwdParams {
     void *partials;          // double2 [nunits][m]
     int m;
     int col;                 // i_k
+    uint32_t chunk;          // low states per unit (a multiple of 64)
     // instance b = blockIdx.y: byte offsets b * stride of gk, gkm1, Akm1, U, partials
     uint64_t gk_stride, gkm1_stride, a_stride, u_stride, partials_stride;
 };
@@ -225,10 +228,17 @@ struct BwdParams {
 int slos_launch_seed(const void *heads, uint64_t nleaves, uint32_t stride, const double *lowfac, const void *ga,
                      void *gn, int c64, void *stream, int batch = 1, uint64_t ga_stride = 0, uint64_t gn_stride = 0);
 int slos_launch_bwd_layer(const BwdParams &p, int c64, int grid, void *stream, int batch = 1);
-int slos_launch_colsum(const void *partials, uint64_t nunits, int m, void *colsum, void *stream, int batch = 1,
-                       uint64_t partials_stride = 0, uint64_t colsum_stride = 0);
-int slos_launch_gradu(const void *colsum, const int32_t *photons, int n, int m, void *GU, int c64, void *stream,
-                      int batch = 1, uint64_t colsum_stride = 0, uint64_t gu_stride = 0);
+// Per-layer partial-sum blocks of the reverse pass for the fused column sum:
+// layer k + 1's partials start at off[k] (double2 elements) and hold nunits[k]
+// rows of m values.
+struct ColsumLayers {
+    uint64_t off[SLOS_MAX_PHOTONS];
+    uint64_t nunits[SLOS_MAX_PHOTONS];
+};
+int slos_launch_colsum_gradu(const void *partials, const ColsumLayers &L, const int32_t *photons, int n, int m,
+                             void *GU, int c64, void *stream, int batch, uint64_t partials_stride, uint64_t gu_stride);
+int slos_launch_sq_loss(const void *a, uint64_t M, const int64_t *ranks, int64_t count, const double *p_target,
+                        void *grad_a, double *loss, int batch, int c64, void *stream);
 int slos_launch_mesh_forward(int m, int batch, const double *phases, void *U, int c64, void *stream);
 int slos_launch_mesh_backward(int m, int batch, const double *phases, const void *GU, double *gphases, int c64,
                               void *stream);

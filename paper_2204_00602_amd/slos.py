@@ -88,6 +88,7 @@ def lib():
     L.slos_amplitudes_many.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp]
     L.slos_probs_many.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp]
     L.slos_backward_many.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp]
+    L.slos_sq_loss_grad_many.argtypes = [vp, ctypes.c_int, vp, vp, ctypes.c_int64, vp, vp, vp, vp]
     L.slos_cdf.argtypes = [vp, vp, vp]
     L.slos_select.argtypes = [vp, vp, i32p, ctypes.c_int64, vp, vp]
     L.slos_marginals.argtypes = [vp, vp, vp, vp]
@@ -122,7 +123,7 @@ def lib():
     for name in ("slos_fock_count", "slos_fock_rank", "slos_fock_unrank", "slos_rank", "slos_unrank", "slos_plan",
                  "slos_plan_ex", "slos_plan_info", "slos_plan_leaf", "slos_amplitudes", "slos_amplitudes_noalloc",
                  "slos_probs", "slos_cdf", "slos_marginals", "slos_sample", "slos_postselect", "slos_select", "slos_amplitudes_many",
-                 "slos_probs_many", "slos_backward_many", "slos_plan_set_timing", "slos_plan_layer_ms", "slos_backward",
+                 "slos_probs_many", "slos_backward_many", "slos_sq_loss_grad_many", "slos_plan_set_timing", "slos_plan_layer_ms", "slos_backward",
                  "slos_mesh_unitary", "slos_mesh_backward", "slos_batch_plan", "slos_batch_offsets",
                  "slos_batch_amplitudes", "slos_batch_capture", "slos_batch_replay", "slos_source_plan",
                  "slos_source_info", "slos_source_probs", "slos_source_postselect", "slos_plan_capture",
@@ -365,6 +366,32 @@ class Plan:
         _check(self._lib.slos_backward_many(self._h, b, U.data_ptr(), grad_a.data_ptr(), grad_U.data_ptr(),
                                             _stream_ptr(stream)))
         return grad_U
+
+    def sq_loss_grad_many(self, a, ranks, p_target, grad_a=None, loss=None, stream=None):
+        """grad_a = 4 (|a|^2 - p_target) a at the target ranks, 0 elsewhere, and
+        the per-instance FP64 loss sum_t (|a(ranks[t])|^2 - p_target[:, t])^2
+        (slos_sq_loss_grad_many).  a: batch x M; ranks: int64 device tensor;
+        p_target: batch x len(ranks) FP64.  Returns (grad_a, loss)."""
+        import torch
+        if a.dtype != self._complex_dtype() or a.numel() % self.num_outputs or not a.is_contiguous():
+            raise ValueError("a must be a contiguous batch x M tensor of the plan's type")
+        b = a.numel() // self.num_outputs
+        ranks = torch.as_tensor(ranks, dtype=torch.int64, device=a.device).contiguous()
+        p_target = torch.as_tensor(p_target, dtype=torch.float64, device=a.device).contiguous()
+        if p_target.numel() != b * ranks.numel():
+            raise ValueError("p_target needs batch x len(ranks) values")
+        if grad_a is None:
+            grad_a = torch.empty_like(a)
+        elif grad_a.dtype != a.dtype or grad_a.numel() != a.numel() or not grad_a.is_contiguous():
+            raise ValueError("grad_a has the wrong dtype, size or layout")
+        if loss is None:
+            loss = torch.empty(b, dtype=torch.float64, device=a.device)
+        elif loss.dtype != torch.float64 or loss.numel() != b:
+            raise ValueError("loss must be a float64 tensor with one entry per instance")
+        _check(self._lib.slos_sq_loss_grad_many(self._h, b, a.data_ptr(), ranks.data_ptr(), ranks.numel(),
+                                                p_target.data_ptr(), grad_a.data_ptr(), loss.data_ptr(),
+                                                _stream_ptr(stream)))
+        return grad_a, loss
 
     def backward(self, U, grad_a, grad_U=None, stream=None):
         """Gradient with respect to U of a real loss, given its gradient with
@@ -645,7 +672,7 @@ def mesh_mzi_count(m: int) -> int:
     return m * (m - 1) // 2
 
 
-def mesh_unitary(phases, m: int, dtype: str = "c128", stream=None):
+def mesh_unitary(phases, m: int, dtype: str = "c128", stream=None, out=None):
     """U (batch x m x m) of the rectangular MZI mesh for FP64 phases (batch x m(m-1))."""
     import torch
     if phases.dtype != torch.float64 or phases.device.type != "cuda":
@@ -655,20 +682,30 @@ def mesh_unitary(phases, m: int, dtype: str = "c128", stream=None):
     if phases.numel() != batch * 2 * mesh_mzi_count(m):
         raise ValueError("phases must hold 2 * m(m-1)/2 values per batch entry")
     cdt = torch.complex64 if dtype == "c64" else torch.complex128
-    U = torch.empty((batch, m, m), dtype=cdt, device=phases.device)
+    if out is None:
+        U = torch.empty((batch, m, m), dtype=cdt, device=phases.device)
+    elif out.dtype != cdt or out.numel() != batch * m * m or not out.is_contiguous():
+        raise ValueError("out has the wrong dtype, size or layout")
+    else:
+        U = out
     _check(lib().slos_mesh_unitary(m, batch, phases.data_ptr(), U.data_ptr(),
                                    SLOS_C64 if dtype == "c64" else SLOS_C128, _stream_ptr(stream)))
     return U
 
 
-def mesh_backward(phases, grad_U, stream=None):
+def mesh_backward(phases, grad_U, stream=None, out=None):
     """dL/dphases (batch x m(m-1), FP64) from grad_U (batch x m x m, PyTorch convention)."""
     import torch
     phases = phases.contiguous()
     grad_U = grad_U.contiguous()
     batch, m = grad_U.shape[0], grad_U.shape[-1]
     dt = SLOS_C64 if grad_U.dtype == torch.complex64 else SLOS_C128
-    g = torch.empty((batch, 2 * mesh_mzi_count(m)), dtype=torch.float64, device=phases.device)
+    if out is None:
+        g = torch.empty((batch, 2 * mesh_mzi_count(m)), dtype=torch.float64, device=phases.device)
+    elif out.dtype != torch.float64 or out.numel() != batch * 2 * mesh_mzi_count(m) or not out.is_contiguous():
+        raise ValueError("out has the wrong dtype, size or layout")
+    else:
+        g = out
     _check(lib().slos_mesh_backward(m, batch, phases.data_ptr(), grad_U.data_ptr(), g.data_ptr(), dt,
                                     _stream_ptr(stream)))
     return g

@@ -11,12 +11,17 @@ int slos_launch_cdf(const void *, int, int64_t, double *, void *) { return no_la
 int slos_launch_seed(const void *, uint64_t, uint32_t, const double *, const void *, void *, int, void *, int, uint64_t,
                      uint64_t) { return no_launch(); }
 int slos_launch_batch(const BatchParams &, int, int, int, int, void *) { return no_launch(); }
-int slos_launch_gradu(const void *, const int *, int, int, void *, int, void *, int, uint64_t, uint64_t)
+int slos_launch_colsum_gradu(const void *, const ColsumLayers &, const int32_t *, int, int, void *, int, void *, int,
+                             uint64_t, uint64_t)
+{
+    return no_launch();
+}
+int slos_launch_sq_loss(const void *, uint64_t, const int64_t *, int64_t, const double *, void *, double *, int, int,
+                        void *)
 {
     return no_launch();
 }
 int slos_launch_layer(const LayerParams &, const LayerLaunch &, void *) { return no_launch(); }
-int slos_launch_colsum(const void *, uint64_t, int, void *, void *, int, uint64_t, uint64_t) { return no_launch(); }
 int slos_launch_reduce(const double *, int64_t, double *, double *, void *, int, int64_t) { return no_launch(); }
 int slos_launch_sample(const void *, int, int64_t, const double *, const double *, int64_t, int64_t *, void *)
 {
