@@ -518,7 +518,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched and gradient workloads")
-    ap.add_argument("--only", choices=["c64comp", "c64", "c128", "batch"], default=None,
+    ap.add_argument("--only", choices=["c64comp", "c64fp64", "c64", "c128", "batch"], default=None,
                     help="time one variant, or the complex64 batch alone (for profiling runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 1 GiB device copy three times, so that a PMC "
@@ -558,7 +558,11 @@ def main():
     N = layer_sizes(m, n)
     M = N[n]
 
-    variants = [("c64comp", "c64", True), ("c64", "c64", False), ("c128", "c128", False)]
+    # c64comp: the two-sum compensated accumulation; c64fp64: the same
+    # complex64 storage with every term's product formed exactly in FP64 and
+    # summed with FP64 FMAs
+    variants = [("c64comp", "c64", True), ("c64fp64", "c64", "fp64"), ("c64", "c64", False),
+                ("c128", "c128", False)]
     if args.only:
         variants = [v for v in variants if v[0] == args.only]
     results = {}

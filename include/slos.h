@@ -64,6 +64,11 @@ extern "C" {
 #define SLOS_COMP_KNUTH 0x800  /* with SLOS_COMPENSATED: FMA two-product plus
                                   Knuth's branch-free two-sum instead (10 flops per
                                   real product; same error order)                  */
+#define SLOS_COMP_FP64 0x1000  /* with SLOS_COMPENSATED: widen each term's factors
+                                  to FP64 (their product is then exact) and sum
+                                  with FP64 FMAs (4 FMAs and 2 conversions per
+                                  complex term; one FP64 rounding per real
+                                  product)                                         */
 #define SLOS_KEEP_LAYERS 0x200 /* keep A_0..A_{n-1} on the device (for backward)   */
 #define SLOS_HOST_ONLY 0x400   /* build the host tables only; no device memory;
                                   for slos_plan_info / slos_plan_leaf inspection  */

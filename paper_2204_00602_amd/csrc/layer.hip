@@ -134,6 +134,28 @@ template <> struct Acc<float, SLOS_COMP_BIASED> {
     __device__ __forceinline__ double im() const { return (double)(si - sigma) + (double)ci; }
 };
 
+// FP64 mode: each term's complex64 factors are widened to FP64, where their
+// products are exact (24-bit significands), and the products are summed with
+// FP64 FMAs: one FP64 rounding per real product, four FMAs and up to four
+// conversions per complex term (the FP64 FMA issues at the FP32 rate here).
+template <> struct Acc<float, SLOS_COMP_F64> {
+    double r, i;
+    __device__ __forceinline__ void zero() { r = i = 0.0; }
+    __device__ __forceinline__ void start(float) {}
+    __device__ __forceinline__ void mac(const float2 uf, const float2 v)
+    {
+        const double2 u{(double)uf.x, (double)uf.y};
+        const double vr = (double)v.x, vi = (double)v.y;
+        r = __builtin_fma(u.x, vr, r);
+        r = __builtin_fma(-u.y, vi, r);
+        i = __builtin_fma(u.x, vi, i);
+        i = __builtin_fma(u.y, vr, i);
+    }
+    __device__ __forceinline__ float2 value() const { return float2{(float)r, (float)i}; }
+    __device__ __forceinline__ double re() const { return r; }
+    __device__ __forceinline__ double im() const { return i; }
+};
+
 // cache-policy operand of the global-to-LDS copy: bit 1 = non-temporal
 #define SLOS_CPOL_NT 2
 
@@ -501,8 +523,14 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? (RR == 2 ? 6 : 3) : (RR <= 2 
         if (p.vmax_in) p.vmax_in += b * p.ticket_stride;
         if (p.vmax_out) p.vmax_out += b * p.ticket_stride;
     }
+    // Column p.col of U; entries m..255 stay zero (padded predecessor
+    // entries name mode SLOS_ZERO_MODE = 255).
     __shared__ C u_lds[256];
     __shared__ uint32_t ticket_slot[2];
+    // the low-block slice; 16-byte aligned for the 16-byte LDS reads of
+    // complex128 elements
+    extern __shared__ __align__(16) unsigned char dyn_lds[];
+    unsigned char *slice = dyn_lds;
     const C *__restrict__ X = (const C *)p.X;
     const C *__restrict__ Um = (const C *)p.U;
     for (int j = threadIdx.x; j < 256; j += blockDim.x) {
@@ -530,9 +558,6 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? (RR == 2 ? 6 : 3) : (RR <= 2 
     };
     uint32_t *ticket = p.tickets + (size_t)xcd * SLOS_TICKET_STRIDE;
     const uint32_t TB = p.ticket_leaves;
-
-    extern __shared__ unsigned char dyn_lds[];
-    unsigned char *slice = dyn_lds;
 
     // first batch
     if (threadIdx.x == 0) ticket_slot[0] = atomicAdd(ticket, TB);
@@ -679,7 +704,7 @@ __global__ __launch_bounds__(MAXT) void batch_kernel(BatchParams bp)
     using C = typename Cx<T>::type;
     __shared__ C u_lds[256];
     __shared__ double wsum[MAXT / 64];
-    extern __shared__ unsigned char dyn_lds[];
+    extern __shared__ __align__(16) unsigned char dyn_lds[];
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int W = blockDim.x >> 6;
@@ -872,6 +897,7 @@ int slos_launch_layer(const LayerParams &p, const LayerLaunch &l, void *stream)
     if (l.c64) {
         if (l.compensated == SLOS_COMP_BIASED) return (int)launch_mode<float, SLOS_COMP_BIASED>(p, l, s);
         if (l.compensated == SLOS_COMP_TWOSUM) return (int)launch_mode<float, SLOS_COMP_TWOSUM>(p, l, s);
+        if (l.compensated == SLOS_COMP_F64) return (int)launch_mode<float, SLOS_COMP_F64>(p, l, s);
         return (int)launch_mode<float, SLOS_COMP_NONE>(p, l, s);
     }
     return (int)launch_mode<double, SLOS_COMP_NONE>(p, l, s);

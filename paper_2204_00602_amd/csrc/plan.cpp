@@ -613,7 +613,8 @@ int slos_plan_ex(int m, int n, const int32_t *input_state, int flags, const slos
         return fail(SLOS_ERR_INVALID_ARG, "n = %d outside [0, %d]", n, SLOS_MAX_PHOTONS);
     int rc = check_state(m, n, input_state, "input_state");
     if (rc) return rc;
-    const int known = SLOS_C64 | SLOS_C128 | SLOS_COMPENSATED | SLOS_COMP_KNUTH | SLOS_KEEP_LAYERS | SLOS_HOST_ONLY;
+    const int known = SLOS_C64 | SLOS_C128 | SLOS_COMPENSATED | SLOS_COMP_KNUTH | SLOS_COMP_FP64 | SLOS_KEEP_LAYERS |
+                      SLOS_HOST_ONLY;
     if (flags & ~known) return fail(SLOS_ERR_INVALID_ARG, "unknown flag bits 0x%x", flags & ~known);
     int dt = flags & (SLOS_C64 | SLOS_C128);
     if (dt != SLOS_C64 && dt != SLOS_C128)
@@ -622,6 +623,10 @@ int slos_plan_ex(int m, int n, const int32_t *input_state, int flags, const slos
         return fail(SLOS_ERR_DTYPE, "SLOS_COMPENSATED applies to SLOS_C64 plans only");
     if ((flags & SLOS_COMP_KNUTH) && !(flags & SLOS_COMPENSATED))
         return fail(SLOS_ERR_INVALID_ARG, "SLOS_COMP_KNUTH needs SLOS_COMPENSATED");
+    if ((flags & SLOS_COMP_FP64) && !(flags & SLOS_COMPENSATED))
+        return fail(SLOS_ERR_INVALID_ARG, "SLOS_COMP_FP64 needs SLOS_COMPENSATED");
+    if ((flags & SLOS_COMP_FP64) && (flags & SLOS_COMP_KNUTH))
+        return fail(SLOS_ERR_INVALID_ARG, "SLOS_COMP_FP64 and SLOS_COMP_KNUTH exclude each other");
     int64_t M;
     if ((rc = slos_fock_count(m, n, &M))) return rc;
 
@@ -1114,7 +1119,9 @@ static int run_forward(slos_plan_t p, int batch, const void *U, void *out, doubl
         ll.c64 = p->c64;
         ll.mode = k == n ? last_mode : SLOS_MODE_MID;
         ll.compensated = (p->comp && k >= p->opts.comp_from_layer)
-                             ? ((p->flags & SLOS_COMP_KNUTH) ? SLOS_COMP_TWOSUM : SLOS_COMP_BIASED)
+                             ? ((p->flags & SLOS_COMP_KNUTH)  ? SLOS_COMP_TWOSUM
+                                : (p->flags & SLOS_COMP_FP64) ? SLOS_COMP_F64
+                                                              : SLOS_COMP_BIASED)
                              : SLOS_COMP_NONE;
         ll.rr = p->opts.outputs_per_lane;
         ll.batch = batch;
@@ -1135,7 +1142,8 @@ static int run_forward(slos_plan_t p, int batch, const void *U, void *out, doubl
             1, std::min<uint64_t>((uint64_t)p->opts.xcd_chunk, lp.nleaves / (4 * SLOS_XCDS)));
         lp.tickets = sc.tickets + (size_t)k * SLOS_XCDS * SLOS_TICKET_STRIDE;
         const bool comp_k = ll.compensated == SLOS_COMP_BIASED;
-        const bool comp_next = k < n && p->comp && !(p->flags & SLOS_COMP_KNUTH) && k + 1 >= p->opts.comp_from_layer;
+        const bool comp_next = k < n && p->comp && !(p->flags & (SLOS_COMP_KNUTH | SLOS_COMP_FP64)) &&
+                               k + 1 >= p->opts.comp_from_layer;
         lp.vmax_in = (comp_k && k >= 2)
                          ? sc.tickets + (size_t)(k - 1) * SLOS_XCDS * SLOS_TICKET_STRIDE + SLOS_VMAX_SLOT
                          : nullptr;

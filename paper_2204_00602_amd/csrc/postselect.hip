@@ -61,7 +61,7 @@ __device__ __forceinline__ void count_groups(const PostselectParams &p, const ui
 template <typename T>
 __global__ __launch_bounds__(256) void postselect_kernel(PostselectParams p)
 {
-    extern __shared__ unsigned char lds[];
+    extern __shared__ __align__(16) unsigned char lds[];
     // the group table in LDS (per-lane lookups), then one row per thread:
     // occupations t[0..m) and group counts cnt[0..SLOS_PS_MAX_GROUPS)
     int8_t *grp = (int8_t *)lds;
@@ -147,7 +147,7 @@ __device__ void unrank_q(const PostselectParams &p, int q, int K, uint64_t rank,
 
 __global__ __launch_bounds__(256) void ps_low_kernel(PostselectParams p)
 {
-    extern __shared__ unsigned char lds[];
+    extern __shared__ __align__(16) unsigned char lds[];
     uint8_t *t = lds + (size_t)threadIdx.x * 256;  // occupations of up to 255 low modes
     const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= p.entries) return;
@@ -289,7 +289,7 @@ template <typename T>
 __global__ __launch_bounds__(64) void postselect_table_kernel(PostselectParams p, const int64_t *ranks,
                                                               int64_t nranks, const double *sum, double *table)
 {
-    extern __shared__ unsigned char lds[];
+    extern __shared__ __align__(16) unsigned char lds[];
     uint8_t *t = lds + (size_t)threadIdx.x * (p.m + SLOS_PS_MAX_GROUPS);
     uint8_t *cnt = t + p.m;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

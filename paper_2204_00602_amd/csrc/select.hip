@@ -30,7 +30,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void select_kernel(SelectParams p)
 {
     using C = typename Cs<T>::type;
-    extern __shared__ unsigned char lds[];
+    extern __shared__ __align__(16) unsigned char lds[];
     C *A = (C *)lds;                                               // R_max states
     __shared__ C uk[SLOS_SELECT_MAX_OCC];                          // U[mode_q, i_k]
     const C *Um = (const C *)p.U;

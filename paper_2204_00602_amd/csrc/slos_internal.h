@@ -71,6 +71,7 @@ static_assert(sizeof(LeafDescWide) == 336, "LeafDescWide must stay 336 bytes");
 #define SLOS_COMP_NONE 0
 #define SLOS_COMP_BIASED 1
 #define SLOS_COMP_TWOSUM 2
+#define SLOS_COMP_F64 3
 // per-layer leaf cap: min(leaf_max, max(SLOS_MIN_LEAF, N_k / SLOS_TARGET_LEAVES))
 #define SLOS_MIN_LEAF 512
 #define SLOS_TARGET_LEAVES 2048u

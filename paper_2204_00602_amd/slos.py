@@ -20,6 +20,7 @@ SLOS_C64 = 0x1
 SLOS_C128 = 0x2
 SLOS_COMPENSATED = 0x100
 SLOS_COMP_KNUTH = 0x800
+SLOS_COMP_FP64 = 0x1000
 SLOS_KEEP_LAYERS = 0x200
 SLOS_HOST_ONLY = 0x400
 MAX_MODES = 255
@@ -182,8 +183,9 @@ class Plan:
     def __init__(self, input_state: Sequence[int], dtype: str = "c64", compensated=False,
                  keep_layers: bool = False, host_only: bool = False,
                  options: Optional[dict] = None):
-        """compensated: False, True (biased-FMA error recovery) or "knuth"
-        (two-product + Knuth two-sum); complex64 only."""
+        """compensated: False, True (biased-FMA error recovery), "knuth"
+        (two-product + Knuth two-sum) or "fp64" (terms widened to FP64 and
+        summed with FP64 FMAs); complex64 only."""
         self.input_state = _state_arr(input_state)
         self.m = int(self.input_state.size)
         self.n = int(self.input_state.sum())
@@ -195,6 +197,10 @@ class Plan:
             flags |= SLOS_COMPENSATED
             if compensated == "knuth":
                 flags |= SLOS_COMP_KNUTH
+            elif compensated == "fp64":
+                flags |= SLOS_COMP_FP64
+            elif compensated is not True:
+                raise ValueError("compensated must be False, True, 'knuth' or 'fp64'")
         if keep_layers:
             flags |= SLOS_KEEP_LAYERS
         if host_only:

@@ -120,7 +120,7 @@ def test_tilings_and_launch_shapes_agree(opts):
     assert abs(s - 1.0) <= 1e-12
 
 
-@pytest.mark.parametrize("comp", [False, True, "knuth"])
+@pytest.mark.parametrize("comp", [False, True, "knuth", "fp64"])
 def test_wide_descriptors_every_variant(comp):
     """The 32-group descriptor form (normally only for > 16 occupied high modes
     or layers of 2^32 states) forced on a small case, c64 variants and c128."""
@@ -133,7 +133,7 @@ def test_wide_descriptors_every_variant(comp):
     assert np.abs(gather(p, out, S) - Pref).max() <= 1e-12 * max(1.0, Pref.max())
 
 
-@pytest.mark.parametrize("comp", [False, True])
+@pytest.mark.parametrize("comp", [False, True, "fp64"])
 def test_compensated_c64_and_probs_api(comp):
     T, U = haar_case(10, [1, 0, 2, 0, 1, 0, 0, 1, 0, 0], 12)
     S = oracle.fock_states(10, 5)
@@ -298,7 +298,7 @@ def test_config3_m24_n12_c128_sampled():
     torch.cuda.empty_cache()
 
 
-@pytest.mark.parametrize("dtype,comp", [("c64", True), ("c128", False)])
+@pytest.mark.parametrize("dtype,comp", [("c64", True), ("c64", "fp64"), ("c128", False)])
 def test_leaf_order_leaves_outputs_bit_identical(dtype, comp):
     """Each output is one thread's fixed-order sum, so the order in which the
     leaves are processed cannot change a single bit of the amplitudes."""

@@ -2,7 +2,8 @@
 
 Variants: complex128; complex64; complex64 with compensated accumulation on
 every layer (biased-FMA error recovery, the default), on the last two layers
-only, and with FMA two-product + Knuth two-sum on every layer.
+only, with FMA two-product + Knuth two-sum on every layer, and with every
+term widened to FP64 and summed in FP64 on every layer.
 Per config the test prints, and writes to $SLOS_REPORT_DIR/precision.json
 when that is set:
   * max and median over the checked outputs of |dP| / max(P_ref, 1/M),
@@ -30,6 +31,7 @@ VARIANTS = [
     ("c64comp", "c64", True, None),             # biased-FMA compensation, every layer
     ("c64comp_deep", "c64", True, -2),          # the same on layers n-1 and n only
     ("c64comp_knuth", "c64", "knuth", None),    # two-product + Knuth two-sum, every layer
+    ("c64comp_fp64", "c64", "fp64", None),      # FP64 sums of exact products, every layer
 ]
 
 REPORT = {}
