@@ -109,8 +109,8 @@ typedef struct slos_options {
                                 leaves with larger ones are split further, so a
                                 workgroup needs less LDS and more of them fit on
                                 a CU.  0: default (3072 for c64, 24 KiB; 2560 for
-                                c128, 40 KiB; no limit with SLOS_KEEP_LAYERS);
-                                -1: none                                         */
+                                c128, 40 KiB; no limit with SLOS_KEEP_LAYERS or
+                                for batches); -1: none                           */
 } slos_options_t;
 
 /* ---- Fock-space arithmetic (host only; no device needed) ------------------ */

@@ -36,16 +36,17 @@ PLAN_SPACE: Dict[str, List[int]] = {
 }
 
 BATCH_SPACE: Dict[str, List[int]] = {
-    "leaf_max": [64, 128, 256, 512, 1024, 4096],
+    "leaf_max": [64, 128, 256, 512, 1024, 2048, 4096, 5120, 6144, 8192],
     "outputs_per_lane": [1, 2, 4],
     "block_threads": [64, 128, 256, 512, 1024],
     "grid_blocks": [256, 512, 1024, 2048, 4096],
+    "low_block_max": [0, 1536, 2048],
 }
 
 # the library defaults the search starts from (0 = library default)
 PLAN_START = {"leaf_max": 0, "low_block_max": 0, "outputs_per_lane": 0, "block_threads": 0, "grid_blocks": 0,
               "ticket_leaves": 0, "xcd_chunk": 0}
-BATCH_START = {"leaf_max": 0, "outputs_per_lane": 0, "block_threads": 0, "grid_blocks": 0}
+BATCH_START = {"leaf_max": 0, "outputs_per_lane": 0, "block_threads": 0, "grid_blocks": 0, "low_block_max": 0}
 
 
 # The tuner's results on MI355X for the benchmark workloads, shipped with the

@@ -1865,7 +1865,7 @@ int slos_batch_plan(int count, const int32_t *ms, const int32_t *inputs, int fla
         (o.block_threads != 64 && o.block_threads != 128 && o.block_threads != 256 && o.block_threads != 512 &&
          o.block_threads != 1024) ||
         o.grid_blocks < 1 || o.grid_blocks > (1 << 20) ||
-        (o.outputs_per_lane != 1 && o.outputs_per_lane != 2 && o.outputs_per_lane != 4))
+        (o.outputs_per_lane != 1 && o.outputs_per_lane != 2 && o.outputs_per_lane != 4) || o.low_block_max < -1)
         return fail(SLOS_ERR_INVALID_ARG, "invalid batch options");
 
     int maxm = 0, maxn = 0;
@@ -1895,6 +1895,7 @@ int slos_batch_plan(int count, const int32_t *ms, const int32_t *inputs, int fla
     try {
         slos_plan_s &P = b->builder;
         P.opts = o;
+        if (o.low_block_max > 0) P.low_cap = (uint64_t)o.low_block_max;  // default: no cap
         P.B.build(maxm + maxn, maxn);
         b->inst.resize(count);
         b->out_off.assign(count + 1, 0);
