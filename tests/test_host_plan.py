@@ -150,6 +150,9 @@ def test_plan_argument_validation():
         ((3, 1, [1, 0, 0], 0), -4),
         ((3, 1, [1, 0, 0], slos.SLOS_C128 | slos.SLOS_COMPENSATED), -4),
         ((3, 1, [1, 0, 0], slos.SLOS_C64 | 0x8000), -1),
+        ((3, 1, [1, 0, 0], slos.SLOS_C64 | slos.SLOS_COMP_FP64), -1),             # needs COMPENSATED
+        ((3, 1, [1, 0, 0], slos.SLOS_C64 | slos.SLOS_COMPENSATED | slos.SLOS_COMP_FP64
+          | slos.SLOS_COMP_KNUTH), -1),                                           # two modes at once
         ((256, 1, [1] + [0] * 255, slos.SLOS_C64), -1),
         ((2, 33, [33, 0], slos.SLOS_C64), -1),
     ]

@@ -234,9 +234,10 @@ def test_reciprocity_through_the_gpu():
         assert gather(pb, ob, [T])[0] == pytest.approx(fwd[index[tuple(s)]], abs=1e-14)
 
 
-def test_bitwise_determinism():
+@pytest.mark.parametrize("comp", [True, "fp64"])
+def test_bitwise_determinism(comp):
     T, U = haar_case(12, [1] * 6 + [0] * 6, 22)
-    p = slos.Plan(T, "c64", compensated=True)
+    p = slos.Plan(T, "c64", compensated=comp)
     Ud = dev_u(U, "c64")
     a1 = p.amplitudes(Ud).clone()
     a2 = p.amplitudes(Ud)
@@ -254,13 +255,16 @@ def _sampled_states(m, n, P_gpu_dev, seed):
     return np.concatenate([uni, bunched, topS])
 
 
-def test_config3_m24_n12_c64_compensated_sampled():
-    """Headline size, launched as the benchmark launches it: 10k uniform
-    seeded outputs, the 100 most bunched and the 100 largest P vs the oracle."""
+@pytest.mark.parametrize("comp", [True, "fp64"])
+def test_config3_m24_n12_c64_compensated_sampled(comp):
+    """Headline size, launched as the benchmark launches it (the two-sum
+    compensated variant, and the FP64-accumulation variant timed beside it):
+    10k uniform seeded outputs, the 100 most bunched and the 100 largest P vs
+    the oracle."""
     m, n = 24, 12
     T = inputs.first_modes_input(m, n)
     U = inputs.haar_unitary(m, 3)
-    p = slos.Plan(T, "c64", compensated=True)
+    p = slos.Plan(T, "c64", compensated=comp)
     Ud = dev_u(U, "c64")
     s = torch.zeros(1, dtype=torch.float64, device="cuda")
     out = p.amplitudes(Ud, sum_p=s)
@@ -272,7 +276,7 @@ def test_config3_m24_n12_c64_compensated_sampled():
     ref = oracle.amplitudes(U, T, S)
     M = p.num_outputs
     err = check_c64_probs(np.abs(a) ** 2, np.abs(ref) ** 2, M)
-    print(f"config3 c64+comp max floored rel err on P: {err:.3e}")
+    print(f"config3 c64 comp={comp} max floored rel err on P: {err:.3e}")
     del out, P_dev
     torch.cuda.empty_cache()
 
