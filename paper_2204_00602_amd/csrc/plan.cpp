@@ -424,8 +424,15 @@ struct slos_plan_s {
         uint32_t ch = 128;
         while (ch < 1024 && (Nk[k - 1] / ch) * (uint64_t)batch_cap > 8192) ch *= 2;
         unit_chunk[k] = ch;
+        // The units come from a leaf split of their own, at the full leaf size:
+        // the forward splits small layers into many small leaves to spread
+        // them over the chip, which would leave many units of a few states
+        // each (the chunks above spread the reverse layer instead).
+        std::vector<LeafRec> lv;
+        std::vector<uint8_t> hm0;
+        gen_leaves(k, m - 1, k, (uint64_t)opts.leaf_max, hm0, lv);
         std::vector<int32_t> occ(m);
-        for (const LeafRec &L : leaves[k]) {
+        for (const LeafRec &L : lv) {
             if (L.K == 0) continue;
             BwdUnit u{};
             LeafDescHead h;
