@@ -48,9 +48,11 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def load_traffic(variant):
-    """HBM bytes per launch of the last layer from a committed rocprofv3 PMC
-    summary, if it was taken on the current kernel source; else None."""
+def load_profile(variant):
+    """The last layer's entry of the committed rocprofv3 summary
+    (profiles/traffic_layer12_m24n12.json: PMC bytes per launch, the profiled
+    command's mean duration of the timed launches), if it was taken on the
+    current kernel source; else None."""
     path = os.path.join(ROOT, "profiles", "traffic_layer12_m24n12.json")
     if not os.path.exists(path):
         return None
@@ -60,8 +62,7 @@ def load_traffic(variant):
         return None
     if d.get("kernel_source_hash") != kernel_source_hash():
         return None
-    v = d.get("variants", {}).get(variant)
-    return None if v is None else v.get("hbm_bytes_per_launch")
+    return d.get("variants", {}).get(variant)
 
 
 def time_variant(torch, slos, T, U_np, dtype, compensated, steps, warmup):
@@ -580,7 +581,8 @@ def main():
     last_bytes = w * (N[n - 1] + N[n])
     last_ms = head["layer_ms_mean"][n - 1]
     achieved = last_bytes / (last_ms * 1e-3) / 1e9
-    traffic = load_traffic(head_name)
+    prof = load_profile(head_name)
+    traffic = None if prof is None else prof.get("hbm_bytes_per_launch")
 
     line = {
         "metric": METRIC,
@@ -611,6 +613,10 @@ def main():
             "traffic": traffic,
             "kernel": f"layer_kernel (last layer k={n}), {last_bytes} algorithmic bytes per launch, "
                       f"{last_ms:.4f} ms average over {args.steps} launches",
+            # the same fraction from the committed rocprofv3 kernel trace (mean
+            # of the profiled command's timed launches), when it matches this source
+            "frac_rocprof": None if prof is None else last_bytes / (prof["steady_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBPS,
+            "rocprof_ms": None if prof is None else prof["steady_ms"],
         },
         "sum_p": head["sum_p"],
         "layer_ms": head["layer_ms_mean"],
