@@ -307,7 +307,8 @@ int slos_postselect(slos_plan_t plan, const void *probs, const int32_t *group_of
  * gradient with respect to U in the same convention.  Uses the layers
  * A_0..A_{n-1} kept by the last slos_amplitudes / slos_probs call on this plan,
  * which must have used the same U.  Needs SLOS_KEEP_LAYERS (else
- * SLOS_ERR_NOT_KEPT) and m <= 64.  Deterministic: no atomics.
+ * SLOS_ERR_NOT_KEPT); any m the plan takes (the gradient partials of each
+ * reverse layer are formed 64 modes per pass).  Deterministic: no atomics.
  */
 int slos_backward(slos_plan_t plan, const void *U, const void *grad_a, void *grad_U, void *stream);
 

@@ -54,7 +54,7 @@ __global__ __launch_bounds__(64) void bwd_layer_kernel(BwdParams p)
 {
     using C = typename Cb<T>::type;
     __shared__ C uc[256];                  // conj(U[j, i_k])
-    extern __shared__ double2 part[];      // [m][64] gradient partials of this wave
+    extern __shared__ double2 part[];      // [jn][64] gradient partials of this wave
     if (blockIdx.y) {
         // instance blockIdx.y of a batch of unitaries through one plan
         const uint64_t b = blockIdx.y;
@@ -81,7 +81,7 @@ __global__ __launch_bounds__(64) void bwd_layer_kernel(BwdParams p)
 
     for (uint64_t u = blockIdx.x; u < p.nunits; u += gridDim.x) {
         const BwdUnit U = p.units[u];
-        for (int j = 0; j < p.m; ++j) part[j * 64 + lane] = double2{0.0, 0.0};
+        for (int j = 0; j < p.jn; ++j) part[j * 64 + lane] = double2{0.0, 0.0};
         const uint32_t *__restrict__ succ = p.succ + U.succ_off;
         const uint64_t *__restrict__ hb = p.hbase + U.hbase_off;
         const uint32_t yend = U.low_size - U.y0 < p.chunk ? U.low_size : U.y0 + p.chunk;
@@ -92,13 +92,17 @@ __global__ __launch_bounds__(64) void bwd_layer_kernel(BwdParams p)
             const C a = A[U.low_base + yc];
             const double ar = (double)a.x, ai = (double)a.y;
             double accr = 0.0, acci = 0.0;
+            // the pass that forms g_{k-1} visits every mode, the others only
+            // their block of partials
+            const int jlo = p.write_g ? 0 : p.jb;
+            const int jhi = p.write_g ? p.m : p.jb + p.jn;
             // four successor modes per step, their loads issued first (modes in
             // ascending order within and across steps, so the sums keep one order)
-            for (int j0 = 0; j0 < p.m; j0 += 4) {
+            for (int j0 = jlo; j0 < jhi; j0 += 4) {
                 C sv[4];
 #pragma unroll
                 for (int d = 0; d < 4; ++d) {
-                    const int j = j0 + d < p.m ? j0 + d : j0;
+                    const int j = j0 + d < jhi ? j0 + d : j0;
                     // successor t' + e_j: inside the forward leaf for a low mode,
                     // the aligned block of the high part + e_j otherwise
                     const uint64_t pos = j < (int)U.q ? U.out_base + succ[(size_t)j * U.low_size + yc]
@@ -108,31 +112,32 @@ __global__ __launch_bounds__(64) void bwd_layer_kernel(BwdParams p)
 #pragma unroll
                 for (int d = 0; d < 4; ++d) {
                     const int j = j0 + d;
-                    if (j >= p.m) break;
+                    if (j >= jhi) break;
                     const double sr = (double)sv[d].x, si = (double)sv[d].y;
                     const double ur = (double)uc[j].x, ui = (double)uc[j].y;
                     accr += ur * sr - ui * si;
                     acci += ur * si + ui * sr;
-                    if (ok) {
+                    const int jj = j - p.jb;
+                    if (ok && jj >= 0 && jj < p.jn) {
                         // s * conj(a)
-                        double2 &pj = part[j * 64 + lane];
+                        double2 &pj = part[jj * 64 + lane];
                         pj.x += sr * ar + si * ai;
                         pj.y += si * ar - sr * ai;
                     }
                 }
             }
-            if (ok) gkm1[U.low_base + y] = C{(T)accr, (T)acci};
+            if (ok && p.write_g) gkm1[U.low_base + y] = C{(T)accr, (T)acci};
         }
         // reduce this unit's partials over lanes in a fixed tree
         __syncthreads();
-        for (int j = 0; j < p.m; ++j) {
+        for (int j = 0; j < p.jn; ++j) {
             double2 v = part[j * 64 + lane];
 #pragma unroll
             for (int off = 32; off > 0; off >>= 1) {
                 v.x += __shfl_xor(v.x, off, 64);
                 v.y += __shfl_xor(v.y, off, 64);
             }
-            if (lane == 0) ((double2 *)p.partials)[u * (uint64_t)p.m + j] = v;
+            if (lane == 0) ((double2 *)p.partials)[u * (uint64_t)p.m + p.jb + j] = v;
         }
         __syncthreads();
     }
@@ -463,7 +468,7 @@ int slos_launch_bwd_layer(const BwdParams &p, int c64, int grid, void *stream, i
     static bool a32 = false, a64 = false;
     hipError_t e = c64 ? allow_lds(bwd_layer_kernel<float>, a32) : allow_lds(bwd_layer_kernel<double>, a64);
     if (e != hipSuccess) return (int)e;
-    const size_t lds = (size_t)p.m * 64 * sizeof(double2);
+    const size_t lds = (size_t)p.jn * 64 * sizeof(double2);
     const dim3 g(grid, batch > 1 ? batch : 1);
     if (c64)
         hipLaunchKernelGGL(bwd_layer_kernel<float>, g, dim3(64), lds, (hipStream_t)stream, p);

@@ -1227,8 +1227,6 @@ static int run_backward(slos_plan_t p, int batch, const void *U, const void *gra
     if (batch < 1 || batch > p->batch_cap)
         return fail(SLOS_ERR_INVALID_ARG, "batch = %d outside [1, max_batch = %d]", batch, p->batch_cap);
     const int n = p->n, m = p->m;
-    if (m > SLOS_BWD_MAX_MODES)
-        return fail(SLOS_ERR_INVALID_ARG, "slos_backward supports m <= %d", SLOS_BWD_MAX_MODES);
     const int c64 = p->c64 ? 1 : 0;
     const size_t es = p->elem();
     const uint64_t mm = (uint64_t)m * m;
@@ -1263,8 +1261,15 @@ static int run_backward(slos_plan_t p, int batch, const void *U, const void *gra
         bp.u_stride = mm * es;
         bp.partials_stride = p->bpart_stride * 16;
         const int grid = (int)std::max<uint64_t>(1, std::min<uint64_t>(bp.nunits, 4096));
-        if ((e = slos_launch_bwd_layer(bp, c64, grid, stream, batch)))
-            return hip_fail((hipError_t)e, "reverse layer");
+        // one pass per block of SLOS_BWD_MODE_BLOCK modes' gradient partials;
+        // the first also forms g_{k-1}, which the next layer's passes read
+        for (int jb = 0; jb < m; jb += SLOS_BWD_MODE_BLOCK) {
+            bp.jb = jb;
+            bp.jn = std::min(SLOS_BWD_MODE_BLOCK, m - jb);
+            bp.write_g = jb == 0;
+            if ((e = slos_launch_bwd_layer(bp, c64, grid, stream, batch)))
+                return hip_fail((hipError_t)e, "reverse layer");
+        }
     }
     // every layer's column sums and G_U in one launch
     ColsumLayers cl{};

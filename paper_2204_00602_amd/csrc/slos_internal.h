@@ -219,11 +219,14 @@ struct BwdParams {
     int m;
     int col;                 // i_k
     uint32_t chunk;          // low states per unit (a multiple of 64)
+    // Gradient partials of modes [jb, jb + jn) (jn <= SLOS_BWD_MODE_BLOCK); the
+    // pass with write_g = 1 also forms g_{k-1} over every mode
+    int jb, jn, write_g;
     // instance b = blockIdx.y: byte offsets b * stride of gk, gkm1, Akm1, U, partials
     uint64_t gk_stride, gkm1_stride, a_stride, u_stride, partials_stride;
 };
 
-#define SLOS_BWD_MAX_MODES 64   // the reverse layer keeps m x 64 FP64 partials in LDS
+#define SLOS_BWD_MODE_BLOCK 64  // modes whose 64 lanes' FP64 gradient partials one reverse pass keeps in LDS
 #define SLOS_MESH_MAX_MODES 64  // the mesh kernels keep two m x m FP64 matrices in LDS
 
 int slos_launch_seed(const void *heads, uint64_t nleaves, uint32_t stride, const double *lowfac, const void *ga,

@@ -60,6 +60,33 @@ def test_grad_U_matches_minor_permanents(dtype, tol, m, T, leaf_max):
     assert err <= tol, err
 
 
+@pytest.mark.parametrize("dtype,tol", [("c128", 1e-11), ("c64", 2e-5)])
+@pytest.mark.parametrize("m,occupied", [(64, [0, 63]), (65, [0, 64]), (130, [3, 64, 129]), (255, [0, 127, 254])])
+def test_grad_U_beyond_one_mode_block(dtype, tol, m, occupied):
+    """More modes than one reverse pass keeps partials for (64): the
+    gradient partials are formed 64 modes per pass.  Photons placed so that
+    every block of modes holds an input mode; outputs sampled uniformly plus
+    the bunched states of the occupied modes; against minor permanents."""
+    T = np.zeros(m, np.int32)
+    T[occupied] = 1
+    n = int(T.sum())
+    U = inputs.haar_unitary(m, 300 + m)
+    S = inputs.uniform_fock_states(m, n, 400, 301 + m)
+    extra = []
+    for j in occupied:
+        e = np.zeros(m, np.int32)
+        e[j] = n
+        extra.append(e)
+    S = np.concatenate([S, np.stack(extra)])
+    rng = np.random.default_rng(302)
+    w = rng.standard_normal(S.shape[0])
+    G, _ = gpu_grad_U(T, U, S, w, dtype)
+    a = oracle.amplitudes(U, T, S)
+    Gref = oracle.grad_U(U, T, S, 2.0 * w * a)
+    err = np.abs(G - Gref).max() / np.abs(Gref).max()
+    assert err <= tol, (m, err)
+
+
 def test_backward_edge_cases():
     # single photon: a(e_j) = U[j, i]  ->  G[j, i] = w_j-weighted 2 U[j, i]
     m = 4
