@@ -356,6 +356,8 @@ def test_max_modes_m255(dtype):
     (2, [16, 16], "c64", True),
     (3, [10, 11, 11], "c64", True),
     (4, [32, 0, 0, 0], "c64", True),
+    (2, [16, 16], "c64", "fp64"),
+    (4, [32, 0, 0, 0], "c64", "fp64"),
 ])
 def test_max_photons_n32(m, T, dtype, comp):
     """n = 32 (the largest), heavily bunched.  Ryser is out of reach at n = 32
