@@ -48,6 +48,27 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
+# VALU issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane-instructions/s
+# (one wave64 instruction per SIMD every 4 cycles; FP32 without packed math and
+# FP64 both issue at this rate: 78.6 TFLOP/s counting an FMA as two flops)
+VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
+
+
+def load_sq(variant):
+    """Shader counters of the last layer from the committed rocprofv3 summary
+    (taken for the compensated variant), if they match the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "traffic_layer12_m24n12.json")
+    if variant != "c64comp" or not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return d.get("sq_layer12_c64comp")
+
+
 def load_profile(variant):
     """The last layer's entry of the committed rocprofv3 summary
     (profiles/traffic_layer12_m24n12.json: PMC bytes per launch, the profiled
@@ -583,6 +604,13 @@ def main():
     achieved = last_bytes / (last_ms * 1e-3) / 1e9
     prof = load_profile(head_name)
     traffic = None if prof is None else prof.get("hbm_bytes_per_launch")
+    sq = load_sq(head_name)
+    alu = None
+    if sq is not None:
+        lane_ops = sq["SQ_INSTS_VALU"] * 64
+        alu = {"bound": "alu", "achieved": lane_ops / (last_ms * 1e-3), "peak": VALU_PEAK_LANE_OPS,
+               "unit": "VALU lane-instructions/s", "frac": lane_ops / (last_ms * 1e-3) / VALU_PEAK_LANE_OPS,
+               "per_output": lane_ops / M}
 
     line = {
         "metric": METRIC,
@@ -617,6 +645,10 @@ def main():
             # of the profiled command's timed launches), when it matches this source
             "frac_rocprof": None if prof is None else last_bytes / (prof["steady_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBPS,
             "rocprof_ms": None if prof is None else prof["steady_ms"],
+            # the co-limit of the compensated layer: VALU lane-instructions per
+            # launch (SQ_INSTS_VALU x 64 from the committed counters) over the
+            # live duration, against the issue peak
+            "alu": alu,
         },
         "sum_p": head["sum_p"],
         "layer_ms": head["layer_ms_mean"],
