@@ -209,6 +209,15 @@ def test_batch_plan_validation():
     assert L.slos_batch_plan(0, ms.ctypes.data_as(i32p), ok.ctypes.data_as(i32p), slos.SLOS_C64, None,
                              ctypes.byref(h)) == -1
     assert L.slos_batch_plan(2, ms.ctypes.data_as(i32p), ok.ctypes.data_as(i32p), 0, None, ctypes.byref(h)) == -4
+    # option checks come before any device work: a low-block cap below -1, or a
+    # leaf size whose low blocks overflow a workgroup's LDS, is refused
+    for opts in ({"low_block_max": -2}, {"leaf_max": 0x10001}, {"outputs_per_lane": 3}):
+        o = slos.Options()
+        for k, v in opts.items():
+            setattr(o, k, v)
+        rc = L.slos_batch_plan(2, ms.ctypes.data_as(i32p), ok.ctypes.data_as(i32p), slos.SLOS_C64,
+                               ctypes.byref(o), ctypes.byref(h))
+        assert rc == -1 and not h.value, (opts, rc)
     L.slos_batch_destroy(None)
 
 
