@@ -106,7 +106,7 @@ template <typename T> struct Acc<T, SLOS_COMP_NONE> {
 };
 template <> struct Acc<float, SLOS_COMP_TWOSUM> {
     CompAcc a;
-    __device__ __forceinline__ void zero() { a.s = float2{0.f, 0.f}; a.c = float2{0.f, 0.f}; }
+    __device__ __forceinline__ void zero() { a.s = float2{0.f, 0.f}; a.c = float2{-0.f, -0.f}; }
     __device__ __forceinline__ void start(float) {}
     __device__ __forceinline__ void mac(const float2 u, const float2 v) { cmac_comp(a, u, v); }
     __device__ __forceinline__ float2 value() const { return float2{a.s.x + a.c.x, a.s.y + a.c.y}; }
@@ -115,7 +115,13 @@ template <> struct Acc<float, SLOS_COMP_TWOSUM> {
 };
 template <> struct Acc<float, SLOS_COMP_BIASED> {
     float sr, si, cr, ci, sigma;
-    __device__ __forceinline__ void zero() { sr = si = cr = ci = sigma = 0.f; }
+    // the error sums start at -0, the identity of IEEE addition, so the first
+    // term's addition folds away
+    __device__ __forceinline__ void zero()
+    {
+        sr = si = sigma = 0.f;
+        cr = ci = -0.f;
+    }
     __device__ __forceinline__ void start(float bias)
     {
         sigma = bias;
@@ -279,6 +285,26 @@ __device__ __forceinline__ V ld_off(const void *base, uint32_t off)
     return *(const V *)((const char *)base + off);
 }
 
+// complex64 load through a buffer resource made from a wave-uniform base (no
+// range limit: word 2 = 0xFFFFFFFF; word 3 = the 32-bit data format that raw
+// loads need on this chip family) and a 32-bit per-lane byte offset.  The
+// resource is built with scalar instructions, so a block base costs no vector
+// instruction per lane.
+#define SLOS_RSRC_WORD3 0x00020000
+__device__ __forceinline__ float2 ld_buf_c64(const void *base, uint32_t off)
+{
+    const __amdgpu_buffer_rsrc_t r =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, -1, SLOS_RSRC_WORD3);
+    return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+// 32-bit table load: per-lane offset `off` plus a wave-uniform offset `soff`
+__device__ __forceinline__ uint32_t ld_buf_u32(const void *base, uint32_t off, uint32_t soff)
+{
+    const __amdgpu_buffer_rsrc_t r =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, -1, SLOS_RSRC_WORD3);
+    return (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(r, off, soff, 0);
+}
+
 // Stage A_{k-1}[low_base, low_base + low_size) into this wave's LDS slice with
 // direct global-to-LDS copies of 16-byte chunks (64 lanes x 16 B per
 // instruction).  The copy starts at the 16-byte boundary at or below the
@@ -323,7 +349,11 @@ struct TileIn {
     uint32_t off[RT];
 };
 
-template <typename T, int MODE, int RT, bool WIDE>
+// BUF_HI / BUF_PRED: complex64 block and table loads through buffer
+// resources (no vector address arithmetic) instead of scalar-base global
+// loads.  Both forms read the same bytes; which one schedules better depends
+// on the kernel around the tile (measured per kernel).
+template <typename T, int MODE, int RT, bool WIDE, bool BUF_HI, bool BUF_PRED>
 __device__ __forceinline__ void tile_load(TileIn<T, RT> &in, const LayerParams &p, const DescRegs<WIDE> &dr,
                                           const Leaf &L, const typename Cx<T>::type *__restrict__ X, uint32_t t0,
                                           int lane)
@@ -358,20 +388,26 @@ __device__ __forceinline__ void tile_load(TileIn<T, RT> &in, const LayerParams &
                 in.e[c][i] = ld_off<uint32_t>(pred, live ? ((uint32_t)c * L.size + in.xc[i]) * 4u : 0u);
         }
     } else {
+        // block and table bases are wave-uniform; each lane adds its own
+        // 32-bit offset
 #pragma unroll
         for (int g = 0; g < kHS; ++g) {
             if (g < L.nh) {
                 const C *Xb = X + group_base<WIDE>(dr, L, g);
 #pragma unroll
-                for (int i = 0; i < RT; ++i) in.v[g][i] = ld_off<C>(Xb, in.off[i]);
+                for (int i = 0; i < RT; ++i) in.v[g][i] = BUF_HI ? ld_buf_c64(Xb, in.off[i]) : ld_off<C>(Xb, in.off[i]);
             }
         }
+        uint32_t xo[RT];
+#pragma unroll
+        for (int i = 0; i < RT; ++i) xo[i] = in.xc[i] * 4u;
 #pragma unroll
         for (int c = 0; c < kCS; ++c) {
             if (c < L.cmax) {
 #pragma unroll
                 for (int i = 0; i < RT; ++i)
-                    in.e[c][i] = ld_off<uint32_t>(pred, ((uint32_t)c * L.size + in.xc[i]) * 4u);
+                    in.e[c][i] = BUF_PRED ? ld_buf_u32(pred, xo[i], (uint32_t)c * L.size * 4u)
+                                          : ld_off<uint32_t>(pred + (size_t)c * L.size, xo[i]);
             }
         }
     }
@@ -397,6 +433,13 @@ __device__ __forceinline__ void tile_compute(const TileIn<T, RT> &in, const Laye
     // Visit every term (output i, mode j, predecessor value) of the tile:
     // high groups from registers (or, past kHS groups, straight from memory),
     // low terms from the staged block.
+    // low-block element of a table entry: its 24-bit index times the element
+    // size with one 24-bit multiply-add, which ignores the mode byte on top
+    // (the size is hidden from the optimiser, which would otherwise turn the
+    // multiply into a shift and a mask)
+    uint32_t esz = (uint32_t)sizeof(C);
+    asm volatile("" : "+v"(esz));
+    auto low_at = [&](uint32_t e) -> C { return *(const C *)((const char *)lowbuf + __umul24(e, esz)); };
     auto terms = [&](auto &&f) {
 #pragma unroll
         for (int g = 0; g < kHS; ++g) {
@@ -416,14 +459,14 @@ __device__ __forceinline__ void tile_compute(const TileIn<T, RT> &in, const Laye
         for (int c = 0; c < kCS; ++c) {
             if (c < L.cmax) {
 #pragma unroll
-                for (int i = 0; i < RT; ++i) f(i, (int)(in.e[c][i] >> 24), lowbuf[in.e[c][i] & SLOS_PRED_MASK]);
+                for (int i = 0; i < RT; ++i) f(i, (int)(in.e[c][i] >> 24), low_at(in.e[c][i]));
             }
         }
         for (int c = kCS; c < L.cmax; ++c) {  // inner states with more than kCS low terms
 #pragma unroll
             for (int i = 0; i < RT; ++i) {
                 const uint32_t ec = ld_off<uint32_t>(pred, ((uint32_t)c * L.size + in.xc[i]) * 4u);
-                f(i, (int)(ec >> 24), lowbuf[ec & SLOS_PRED_MASK]);
+                f(i, (int)(ec >> 24), low_at(ec));
             }
         }
     };
@@ -436,16 +479,17 @@ __device__ __forceinline__ void tile_compute(const TileIn<T, RT> &in, const Laye
     for (int i = 0; i < RT; ++i) acc[i].start(sigma);
     terms([&](int i, int j, const C x) { acc[i].mac(u_lds[j], x); });
 
-    // ---- store
+    // ---- store (through the leaf's wave-uniform output base)
+    T *Yb = (T *)p.Y + (MODE == SLOS_MODE_PROB ? 1u : 2u) * L.out_base;
 #pragma unroll
     for (int i = 0; i < RT; ++i) {
         if (t0 + (uint32_t)(i * 64 + lane) >= L.size) continue;
-        const uint64_t o = L.out_base + in.xc[i];
         if (MODE == SLOS_MODE_MID) {
             const C a = acc[i].value();
             if (sizeof(T) == 4) omax = fmaxf(omax, (float)(fabs(a.x) + fabs(a.y)));
-            __builtin_nontemporal_store(a.x, &((T *)p.Y)[2 * o]);
-            __builtin_nontemporal_store(a.y, &((T *)p.Y)[2 * o + 1]);
+            T *y = (T *)((char *)Yb + in.off[i]);
+            __builtin_nontemporal_store(a.x, y);
+            __builtin_nontemporal_store(a.y, y + 1);
         } else {
             const double f = L.fac_hi * in.lf[i];
             const double ar = acc[i].re() * f;
@@ -453,23 +497,28 @@ __device__ __forceinline__ void tile_compute(const TileIn<T, RT> &in, const Laye
             const double pr = ar * ar + ai * ai;
             psum += pr;
             if (MODE == SLOS_MODE_AMPL) {
-                __builtin_nontemporal_store((T)ar, &((T *)p.Y)[2 * o]);
-                __builtin_nontemporal_store((T)ai, &((T *)p.Y)[2 * o + 1]);
+                T *y = (T *)((char *)Yb + in.off[i]);
+                __builtin_nontemporal_store((T)ar, y);
+                __builtin_nontemporal_store((T)ai, y + 1);
             } else {
-                __builtin_nontemporal_store((T)pr, &((T *)p.Y)[o]);
+                __builtin_nontemporal_store((T)pr, (T *)((char *)Yb + in.off[i] / 2u));
             }
         }
     }
 }
 
-template <typename T, int MODE, int COMP, int RT, bool WIDE>
+// The compensated layers take both loads through buffer resources; the plain
+// ones take the blocks through scalar-base global loads and the tables through
+// buffer resources only inside the batch kernel (BATCH).
+template <typename T, int MODE, int COMP, int RT, bool WIDE, bool BATCH = false>
 __device__ __forceinline__ void tile(const LayerParams &p, const DescRegs<WIDE> &dr, const Leaf &L,
                                      const typename Cx<T>::type *__restrict__ X,
                                      const typename Cx<T>::type *u_lds, const typename Cx<T>::type *lowbuf,
                                      float sigma, uint32_t t0, int lane, double &psum, float &omax)
 {
     TileIn<T, RT> in;
-    tile_load<T, MODE, RT, WIDE>(in, p, dr, L, X, t0, lane);
+    constexpr bool comp = COMP != SLOS_COMP_NONE;
+    tile_load<T, MODE, RT, WIDE, comp, comp || BATCH>(in, p, dr, L, X, t0, lane);
     tile_compute<T, MODE, COMP, RT, WIDE>(in, p, dr, L, X, u_lds, lowbuf, sigma, t0, lane, psum, omax);
 }
 
@@ -682,16 +731,16 @@ __device__ __forceinline__ void batch_layer_leaves(const BatchParams &bp, const 
         const uint32_t full = L.size / (64u * RR);
         if (k == n) {
             for (uint32_t t = 0; t < full; ++t)
-                tile<T, SLOS_MODE_AMPL, SLOS_COMP_NONE, RR, false>(lp, d, L, X, u, lowbuf, 0.f, t * 64u * RR, lane,
+                tile<T, SLOS_MODE_AMPL, SLOS_COMP_NONE, RR, false, true>(lp, d, L, X, u, lowbuf, 0.f, t * 64u * RR, lane,
                                                                   psum, bmax);
             for (uint32_t t0 = full * 64u * RR; t0 < L.size; t0 += 64u)
-                tile<T, SLOS_MODE_AMPL, SLOS_COMP_NONE, 1, false>(lp, d, L, X, u, lowbuf, 0.f, t0, lane, psum, bmax);
+                tile<T, SLOS_MODE_AMPL, SLOS_COMP_NONE, 1, false, true>(lp, d, L, X, u, lowbuf, 0.f, t0, lane, psum, bmax);
         } else {
             for (uint32_t t = 0; t < full; ++t)
-                tile<T, SLOS_MODE_MID, SLOS_COMP_NONE, RR, false>(lp, d, L, X, u, lowbuf, 0.f, t * 64u * RR, lane,
+                tile<T, SLOS_MODE_MID, SLOS_COMP_NONE, RR, false, true>(lp, d, L, X, u, lowbuf, 0.f, t * 64u * RR, lane,
                                                                  psum, bmax);
             for (uint32_t t0 = full * 64u * RR; t0 < L.size; t0 += 64u)
-                tile<T, SLOS_MODE_MID, SLOS_COMP_NONE, 1, false>(lp, d, L, X, u, lowbuf, 0.f, t0, lane, psum, bmax);
+                tile<T, SLOS_MODE_MID, SLOS_COMP_NONE, 1, false, true>(lp, d, L, X, u, lowbuf, 0.f, t0, lane, psum, bmax);
         }
         __builtin_amdgcn_s_waitcnt(0);
         __builtin_amdgcn_wave_barrier();
