@@ -334,6 +334,31 @@ int slos_sq_loss_grad_many(slos_plan_t plan, int batch, const void *a, const int
                            const double *p_target, void *grad_a, double *loss, void *stream);
 
 /*
+ * Normalisation factors of chosen outputs: scales[t] = c_S for S = ranks[t],
+ * where a(S) = c_S A_n[S] with c_S = sqrt(prod_j s_j!) / sqrt(prod_i t_i!)
+ * (Eq. eqperm's normalisation of the permanent), the same double the adjoint's
+ * seed applies.  ranks, scales: host arrays of `count` entries; a rank outside
+ * [0, M) gets 0.  Host arithmetic only (host-only plans are accepted).
+ */
+int slos_output_scales(slos_plan_t plan, const int64_t *ranks, int64_t count, double *scales);
+
+/*
+ * slos_sq_loss_grad_many followed by slos_backward_many without the dense
+ * dL/da in between: the loss kernel writes the adjoint's seed
+ * g_n = c_S * 4 (|a_b(S)|^2 - p_target[b, t]) a_b(S) at S = ranks[t] (0
+ * elsewhere) straight into the plan's last-layer gradient buffer, then the
+ * reverse layers run as in slos_backward_many.  grad_U and loss come out
+ * bit-identical to the two calls.  scales: device FP64, `count` values from
+ * slos_output_scales for the same ranks (computed once for a fixed target
+ * set).  a, ranks, p_target, grad_U, loss: as in the two calls.  Needs
+ * SLOS_KEEP_LAYERS, batch <= max_batch and n >= 1 (the vacuum has no adjoint
+ * layers: SLOS_ERR_INVALID_ARG).  Launches only, no allocation.
+ */
+int slos_sq_loss_backward_many(slos_plan_t plan, int batch, const void *U, const void *a, const int64_t *ranks,
+                               const double *scales, int64_t count, const double *p_target, void *grad_U,
+                               double *loss, void *stream);
+
+/*
  * Rectangular MZI mesh (Section 2: any unitary decomposes into beam splitters
  * and phase shifters in a square array).  MZI k = PS_1(phi_b) BS PS_0(phi_a) BS
  * with BS of Eq. eq:bs at theta = pi/2 (the composition BS, PS(phi_a) on mode 0,

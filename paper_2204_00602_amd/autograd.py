@@ -83,11 +83,12 @@ class MeshLossGradient:
     of Clements meshes, recorded once into a HIP graph and replayed.
 
     One replay runs the mesh (phases -> U), the amplitudes of every unitary
-    through one plan (slos_amplitudes_many), the loss and its gradient with
-    respect to the amplitudes on the targets (slos_sq_loss_grad_many: dL/da =
-    4 (P - P_t) a in the PyTorch convention, zero elsewhere), the adjoint of the
-    recurrence (slos_backward_many) and the mesh adjoint, all library kernels on
-    bound buffers: write new phases into `phases` and replay().
+    through one plan (slos_amplitudes_many), the loss with the adjoint of the
+    recurrence (slos_sq_loss_backward_many: dL/da = 4 (P - P_t) a in the
+    PyTorch convention on the targets, zero elsewhere, seeded straight into the
+    reverse layers with the targets' normalisation factors, which
+    slos_output_scales computes once here) and the mesh adjoint, all library
+    kernels on bound buffers: write new phases into `phases` and replay().
 
     plan: built with keep_layers=True and max_batch >= batch.
     targets: ranks of the target outputs (int64, device); p_target: batch x
@@ -106,7 +107,7 @@ class MeshLossGradient:
         self.phases = torch.zeros((batch, 2 * k), dtype=torch.float64, device=dev)
         self.U = torch.empty((batch, m, m), dtype=cdt, device=dev)
         self.a = torch.empty((batch, plan.num_outputs), dtype=cdt, device=dev)
-        self.grad_a = torch.zeros_like(self.a)
+        self.scales = torch.from_numpy(plan.output_scales(self.targets.cpu().numpy())).to(dev)
         self.grad_U = torch.empty_like(self.U)
         self.grad_phases = torch.empty((batch, 2 * k), dtype=torch.float64, device=dev)
         self.losses = torch.zeros(batch, dtype=torch.float64, device=dev)
@@ -115,8 +116,8 @@ class MeshLossGradient:
     def _step(self):
         slos.mesh_unitary(self.phases, self.m, self.dtype, out=self.U)
         self.plan.amplitudes_many(self.U, out=self.a)
-        self.plan.sq_loss_grad_many(self.a, self.targets, self.p_target, grad_a=self.grad_a, loss=self.losses)
-        self.plan.backward_many(self.U, self.grad_a, grad_U=self.grad_U)
+        self.plan.sq_loss_backward_many(self.U, self.a, self.targets, self.scales, self.p_target, grad_U=self.grad_U,
+                                        loss=self.losses)
         slos.mesh_backward(self.phases, self.grad_U, out=self.grad_phases)
 
     def eager(self, phases=None):

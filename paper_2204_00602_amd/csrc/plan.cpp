@@ -1218,30 +1218,15 @@ int slos_plan_layer_ms(slos_plan_t p, float *ms, int count)
     return SLOS_OK;
 }
 
-static int run_backward(slos_plan_t p, int batch, const void *U, const void *grad_a, void *grad_U, void *stream)
+// The reverse layers n..1 from g_n (already in d_g[n & 1]) and the assembly of
+// G_U; n >= 1.
+static int run_reverse(slos_plan_t p, int batch, const void *U, void *grad_U, void *stream)
 {
-    int rc = check_plan(p);
-    if (rc) return rc;
-    if (!p->keep) return fail(SLOS_ERR_NOT_KEPT, "slos_backward needs a plan built with SLOS_KEEP_LAYERS");
-    if (!U || !grad_a || !grad_U) return fail(SLOS_ERR_INVALID_ARG, "U, grad_a and grad_U must be device pointers");
-    if (batch < 1 || batch > p->batch_cap)
-        return fail(SLOS_ERR_INVALID_ARG, "batch = %d outside [1, max_batch = %d]", batch, p->batch_cap);
     const int n = p->n, m = p->m;
     const int c64 = p->c64 ? 1 : 0;
     const size_t es = p->elem();
     const uint64_t mm = (uint64_t)m * m;
     int e;
-    if (n == 0) {
-        // a(vacuum) = 1 does not depend on U
-        if ((e = slos_launch_zero_u32((uint32_t *)grad_U, (int)(mm * es * batch / 4), stream)))
-            return hip_fail((hipError_t)e, "zero kernel");
-        return SLOS_OK;
-    }
-    const size_t rec = p->desc_wide[n] ? sizeof(LeafDescWide) : sizeof(LeafDescNarrow);
-    // g_n = c_S g_a
-    if ((e = slos_launch_seed(p->d_desc + p->desc_off[n], p->leaves[n].size(), (uint32_t)rec, p->d_lowfac, grad_a,
-                              p->d_g[n & 1], c64, stream, batch, p->Nk[n], p->g_stride)))
-        return hip_fail((hipError_t)e, "seed kernel");
     for (int k = n; k >= 1; --k) {
         BwdParams bp{};
         bp.gk = p->d_g[k & 1];
@@ -1283,6 +1268,41 @@ static int run_backward(slos_plan_t p, int batch, const void *U, const void *gra
     return SLOS_OK;
 }
 
+static int check_backward(slos_plan_t p, int batch, const void *U, void *grad_U)
+{
+    int rc = check_plan(p);
+    if (rc) return rc;
+    if (!p->keep) return fail(SLOS_ERR_NOT_KEPT, "slos_backward needs a plan built with SLOS_KEEP_LAYERS");
+    if (!U || !grad_U) return fail(SLOS_ERR_INVALID_ARG, "U and grad_U must be device pointers");
+    if (batch < 1 || batch > p->batch_cap)
+        return fail(SLOS_ERR_INVALID_ARG, "batch = %d outside [1, max_batch = %d]", batch, p->batch_cap);
+    return SLOS_OK;
+}
+
+// G_U = 0 for the vacuum: a(vacuum) = 1 does not depend on U
+static int zero_grad_u(slos_plan_t p, int batch, void *grad_U, void *stream)
+{
+    const uint64_t mm = (uint64_t)p->m * p->m;
+    int e = slos_launch_zero_u32((uint32_t *)grad_U, (int)(mm * p->elem() * batch / 4), stream);
+    return e ? hip_fail((hipError_t)e, "zero kernel") : SLOS_OK;
+}
+
+static int run_backward(slos_plan_t p, int batch, const void *U, const void *grad_a, void *grad_U, void *stream)
+{
+    int rc = check_backward(p, batch, U, grad_U);
+    if (rc) return rc;
+    if (!grad_a) return fail(SLOS_ERR_INVALID_ARG, "grad_a must be a device pointer");
+    const int n = p->n;
+    if (n == 0) return zero_grad_u(p, batch, grad_U, stream);
+    const size_t rec = p->desc_wide[n] ? sizeof(LeafDescWide) : sizeof(LeafDescNarrow);
+    // g_n = c_S g_a
+    int e;
+    if ((e = slos_launch_seed(p->d_desc + p->desc_off[n], p->leaves[n].size(), (uint32_t)rec, p->d_lowfac, grad_a,
+                              p->d_g[n & 1], p->c64 ? 1 : 0, stream, batch, p->Nk[n], p->g_stride)))
+        return hip_fail((hipError_t)e, "seed kernel");
+    return run_reverse(p, batch, U, grad_U, stream);
+}
+
 int slos_backward(slos_plan_t p, const void *U, const void *grad_a, void *grad_U, void *stream)
 {
     return run_backward(p, 1, U, grad_a, grad_U, stream);
@@ -1305,6 +1325,61 @@ int slos_sq_loss_grad_many(slos_plan_t p, int batch, const void *a, const int64_
     int e = slos_launch_sq_loss(a, p->Nk[p->n], ranks, count, p_target, grad_a, loss, batch, p->c64 ? 1 : 0, stream);
     if (e) return hip_fail((hipError_t)e, "squared-loss kernel");
     return SLOS_OK;
+}
+
+int slos_output_scales(slos_plan_t p, const int64_t *ranks, int64_t count, double *scales)
+{
+    // host arithmetic only: host-only plans are accepted
+    if (!p) return fail(SLOS_ERR_INVALID_ARG, "plan is NULL");
+    if (count < 0) return fail(SLOS_ERR_INVALID_ARG, "count = %lld is negative", (long long)count);
+    if (count > 0 && (!ranks || !scales)) return fail(SLOS_ERR_INVALID_ARG, "ranks and scales must be host arrays");
+    const int n = p->n;
+    const uint64_t M = p->Nk[n];
+    if (n == 0) {
+        for (int64_t t = 0; t < count; ++t) scales[t] = ranks[t] == 0 ? 1.0 : 0.0;
+        return SLOS_OK;
+    }
+    // the last layer's leaves tile [0, N_n) by their first ranks
+    const std::vector<LeafRec> &lv = p->leaves[n];
+    std::vector<uint32_t> ord(lv.size());
+    for (uint32_t i = 0; i < (uint32_t)ord.size(); ++i) ord[i] = i;
+    std::sort(ord.begin(), ord.end(), [&](uint32_t x, uint32_t y) { return lv[x].out_base < lv[y].out_base; });
+    for (int64_t t = 0; t < count; ++t) {
+        const int64_t r = ranks[t];
+        if (r < 0 || (uint64_t)r >= M) {
+            scales[t] = 0.0;  // outside the output set (the loss ignores it)
+            continue;
+        }
+        // last leaf whose first rank is <= r
+        size_t lo = 0, hi = ord.size();
+        while (hi - lo > 1) {
+            const size_t mid = (lo + hi) / 2;
+            if (lv[ord[mid]].out_base <= (uint64_t)r) lo = mid;
+            else hi = mid;
+        }
+        const LeafRec &L = lv[ord[lo]];
+        const uint64_t x = (uint64_t)r - L.out_base;
+        // the factor the seed of the adjoint applies: fac_hi * inner factor
+        scales[t] = L.fac_hi * p->lowfac[p->types[L.tab].fac_off + x];
+    }
+    return SLOS_OK;
+}
+
+int slos_sq_loss_backward_many(slos_plan_t p, int batch, const void *U, const void *a, const int64_t *ranks,
+                               const double *scales, int64_t count, const double *p_target, void *grad_U,
+                               double *loss, void *stream)
+{
+    int rc = check_backward(p, batch, U, grad_U);
+    if (rc) return rc;
+    if (count < 0) return fail(SLOS_ERR_INVALID_ARG, "count = %lld is negative", (long long)count);
+    if (!a || (count > 0 && (!ranks || !scales || !p_target)))
+        return fail(SLOS_ERR_INVALID_ARG, "a (and ranks, scales, p_target when count > 0) must be device pointers");
+    const int n = p->n;
+    if (n == 0) return fail(SLOS_ERR_INVALID_ARG, "n = 0: the vacuum has no adjoint layers");
+    int e = slos_launch_sq_loss_seed(a, p->Nk[n], ranks, scales, count, p_target, p->d_g[n & 1], p->g_stride, loss,
+                                     batch, p->c64 ? 1 : 0, stream);
+    if (e) return hip_fail((hipError_t)e, "squared-loss seed kernel");
+    return run_reverse(p, batch, U, grad_U, stream);
 }
 
 int slos_mesh_unitary(int m, int batch, const double *phases, void *U, int dtype, void *stream)

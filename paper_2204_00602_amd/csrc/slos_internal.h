@@ -243,6 +243,9 @@ int slos_launch_colsum_gradu(const void *partials, const ColsumLayers &L, const 
                              void *GU, int c64, void *stream, int batch, uint64_t partials_stride, uint64_t gu_stride);
 int slos_launch_sq_loss(const void *a, uint64_t M, const int64_t *ranks, int64_t count, const double *p_target,
                         void *grad_a, double *loss, int batch, int c64, void *stream);
+int slos_launch_sq_loss_seed(const void *a, uint64_t M, const int64_t *ranks, const double *scale, int64_t count,
+                             const double *p_target, void *gn, uint64_t gn_stride, double *loss, int batch, int c64,
+                             void *stream);
 int slos_launch_mesh_forward(int m, int batch, const double *phases, void *U, int c64, void *stream);
 int slos_launch_mesh_backward(int m, int batch, const double *phases, const void *GU, double *gphases, int c64,
                               void *stream);

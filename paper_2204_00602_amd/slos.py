@@ -90,6 +90,8 @@ def lib():
     L.slos_probs_many.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp]
     L.slos_backward_many.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp]
     L.slos_sq_loss_grad_many.argtypes = [vp, ctypes.c_int, vp, vp, ctypes.c_int64, vp, vp, vp, vp]
+    L.slos_output_scales.argtypes = [vp, vp, ctypes.c_int64, vp]
+    L.slos_sq_loss_backward_many.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp, ctypes.c_int64, vp, vp, vp, vp]
     L.slos_cdf.argtypes = [vp, vp, vp]
     L.slos_select.argtypes = [vp, vp, i32p, ctypes.c_int64, vp, vp]
     L.slos_marginals.argtypes = [vp, vp, vp, vp]
@@ -124,7 +126,8 @@ def lib():
     for name in ("slos_fock_count", "slos_fock_rank", "slos_fock_unrank", "slos_rank", "slos_unrank", "slos_plan",
                  "slos_plan_ex", "slos_plan_info", "slos_plan_leaf", "slos_amplitudes", "slos_amplitudes_noalloc",
                  "slos_probs", "slos_cdf", "slos_marginals", "slos_sample", "slos_postselect", "slos_select", "slos_amplitudes_many",
-                 "slos_probs_many", "slos_backward_many", "slos_sq_loss_grad_many", "slos_plan_set_timing", "slos_plan_layer_ms", "slos_backward",
+                 "slos_probs_many", "slos_backward_many", "slos_sq_loss_grad_many", "slos_output_scales",
+                 "slos_sq_loss_backward_many", "slos_plan_set_timing", "slos_plan_layer_ms", "slos_backward",
                  "slos_mesh_unitary", "slos_mesh_backward", "slos_batch_plan", "slos_batch_offsets",
                  "slos_batch_amplitudes", "slos_batch_capture", "slos_batch_replay", "slos_source_plan",
                  "slos_source_info", "slos_source_probs", "slos_source_postselect", "slos_plan_capture",
@@ -398,6 +401,44 @@ class Plan:
                                                 p_target.data_ptr(), grad_a.data_ptr(), loss.data_ptr(),
                                                 _stream_ptr(stream)))
         return grad_a, loss
+
+    def output_scales(self, ranks):
+        """c_S of the outputs at `ranks` (host int64 array): a(S) = c_S A_n[S]
+        (slos_output_scales).  Returns a float64 numpy array."""
+        r = np.ascontiguousarray(np.asarray(ranks, dtype=np.int64).reshape(-1))
+        out = np.empty(r.size, dtype=np.float64)
+        _check(self._lib.slos_output_scales(self._h, r.ctypes.data if r.size else None, r.size,
+                                            out.ctypes.data if r.size else None))
+        return out
+
+    def sq_loss_backward_many(self, U, a, ranks, scales, p_target, grad_U=None, loss=None, stream=None):
+        """The squared-error loss on the target ranks and its gradient with
+        respect to each U of the batch in one call (slos_sq_loss_backward_many):
+        the same results as sq_loss_grad_many followed by backward_many.
+        scales: device FP64 values of output_scales(ranks).  Returns (grad_U, loss)."""
+        import torch
+        b = self._check_many(U)
+        if not (self.flags & SLOS_KEEP_LAYERS):
+            raise SlosError(-6, "plan was built without keep_layers=True")
+        if a.dtype != self._complex_dtype() or a.numel() != b * self.num_outputs or not a.is_contiguous():
+            raise ValueError("a must be a contiguous batch x M tensor of the plan's type")
+        ranks = torch.as_tensor(ranks, dtype=torch.int64, device=a.device).contiguous()
+        scales = torch.as_tensor(scales, dtype=torch.float64, device=a.device).contiguous()
+        p_target = torch.as_tensor(p_target, dtype=torch.float64, device=a.device).contiguous()
+        if scales.numel() != ranks.numel():
+            raise ValueError("scales needs one value per rank")
+        if p_target.numel() != b * ranks.numel():
+            raise ValueError("p_target needs batch x len(ranks) values")
+        if grad_U is None:
+            grad_U = torch.empty_like(U)
+        if loss is None:
+            loss = torch.empty(b, dtype=torch.float64, device=a.device)
+        elif loss.dtype != torch.float64 or loss.numel() != b:
+            raise ValueError("loss must be a float64 tensor with one entry per instance")
+        _check(self._lib.slos_sq_loss_backward_many(self._h, b, U.data_ptr(), a.data_ptr(), ranks.data_ptr(),
+                                                    scales.data_ptr(), ranks.numel(), p_target.data_ptr(),
+                                                    grad_U.data_ptr(), loss.data_ptr(), _stream_ptr(stream)))
+        return grad_U, loss
 
     def backward(self, U, grad_a, grad_U=None, stream=None):
         """Gradient with respect to U of a real loss, given its gradient with

@@ -98,6 +98,15 @@ static void host_plan(int m, const std::vector<int32_t> &T, int flags, const slo
         CHECK(slos_plan_leaf(p, k, nl, &base, nullptr, nullptr, nullptr) != SLOS_OK, "leaf past the end accepted");
     }
     CHECK(slos_plan_info(p, n + 1, nullptr, nullptr) != SLOS_OK || n == 0, "layer past n accepted");
+    // normalisation factors of a spread of outputs (and two outside the set)
+    {
+        std::vector<int64_t> rk = {-1, M, 0, M - 1};
+        for (int64_t r = 1; r < M - 1; r += 1 + M / 97) rk.push_back(r);
+        std::vector<double> sc(rk.size(), -1.0);
+        CHECK(slos_output_scales(p, rk.data(), (int64_t)rk.size(), sc.data()) == SLOS_OK, "output scales");
+        CHECK(sc[0] == 0.0 && sc[1] == 0.0, "ranks outside the output set must get 0");
+        for (size_t t = 2; t < rk.size(); ++t) CHECK(sc[t] > 0.0 && sc[t] < 1e30, "scale of rank %lld", (long long)rk[t]);
+    }
     slos_plan_destroy(p);
 }
 

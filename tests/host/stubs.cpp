@@ -21,6 +21,11 @@ int slos_launch_sq_loss(const void *, uint64_t, const int64_t *, int64_t, const 
 {
     return no_launch();
 }
+int slos_launch_sq_loss_seed(const void *, uint64_t, const int64_t *, const double *, int64_t, const double *, void *,
+                             uint64_t, double *, int, int, void *)
+{
+    return no_launch();
+}
 int slos_launch_layer(const LayerParams &, const LayerLaunch &, void *) { return no_launch(); }
 int slos_launch_reduce(const double *, int64_t, double *, double *, void *, int, int64_t) { return no_launch(); }
 int slos_launch_sample(const void *, int, int64_t, const double *, const double *, int64_t, int64_t *, void *)

@@ -191,3 +191,33 @@ def test_backward_is_deterministic():
     G1, _ = gpu_grad_U(T, U, S, w, "c64")
     G2, _ = gpu_grad_U(T, U, S, w, "c64")
     assert np.array_equal(G1, G2)
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("m,T,batch", [(12, [1] * 6 + [0] * 6, 5), (7, [2, 0, 1, 1, 0, 0, 0], 3), (3, [1, 0, 0], 2)])
+def test_fused_loss_backward_equals_two_calls(dtype, m, T, batch):
+    """slos_sq_loss_backward_many against slos_sq_loss_grad_many followed by
+    slos_backward_many: grad_U and the losses bit for bit, on distinct target
+    ranks plus two outside the output set (ignored by both)."""
+    n = sum(T)
+    cdt = torch.complex64 if dtype == "c64" else torch.complex128
+    plan = slos.Plan(T, dtype, keep_layers=True, options={"max_batch": batch})
+    M = plan.num_outputs
+    U = torch.from_numpy(np.stack([inputs.haar_unitary(m, 300 + b) for b in range(batch)])).to(cdt).cuda()
+    a = plan.amplitudes_many(U)
+    rng = np.random.default_rng(301)
+    ranks = rng.choice(M, size=min(M, 200), replace=False).astype(np.int64)
+    ranks = np.concatenate([ranks, [-1, M]])
+    p_t = torch.from_numpy(rng.random((batch, ranks.size)) / M).cuda()
+    r_d = torch.from_numpy(ranks).cuda()
+    g_a, loss2 = plan.sq_loss_grad_many(a, r_d, p_t)
+    G2 = plan.backward_many(U, g_a)
+    scales = torch.from_numpy(plan.output_scales(ranks)).cuda()
+    G1, loss1 = plan.sq_loss_backward_many(U, a, r_d, scales, p_t)
+    torch.cuda.synchronize()
+    assert n >= 1
+    assert torch.equal(loss1, loss2)
+    assert torch.equal(G1, G2)
+    # a second call through the same plan buffers gives the same again
+    G3, _ = plan.sq_loss_backward_many(U, a, r_d, scales, p_t)
+    assert torch.equal(G3, G2)

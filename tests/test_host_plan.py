@@ -247,6 +247,36 @@ def test_many_calls_validate_arguments():
     assert L.slos_probs_many(p._h, 2, None, None, None, None) == -1
 
 
+@pytest.mark.parametrize("T", [[1, 1, 1, 0, 0, 0], [2, 0, 1, 0], [1] * 6 + [0] * 6, [3, 0, 0]])
+def test_output_scales_are_the_normalisation(T):
+    # c_S = sqrt(prod_j s_j!) / sqrt(prod_i t_i!): a(S) = perm(U_{S,T}) / sqrt(prod s! prod t!)
+    # (Eq. eqperm) while the recurrence's A_n[S] = perm(U_{S,T}) / prod_j s_j!
+    p = slos.Plan(T, "c64", host_only=True, options={"leaf_max": 64})
+    M = p.num_outputs
+    rng = np.random.default_rng(7)
+    ranks = np.unique(np.concatenate([[0, M - 1], rng.integers(0, M, size=min(M, 300))])).astype(np.int64)
+    sc = p.output_scales(ranks)
+    tfac = math.prod(math.factorial(t) for t in T)
+    for r, c in zip(ranks, sc):
+        s = p.unrank(int(r))
+        sfac = math.prod(math.factorial(v) for v in s)
+        assert c == pytest.approx(math.sqrt(sfac) / math.sqrt(tfac), rel=4e-16), (r, s)
+
+
+def test_output_scales_and_fused_loss_validate_arguments():
+    L = slos.lib()
+    p = slos.Plan([1, 1, 0], "c64", host_only=True, options={"max_batch": 4})
+    # ranks outside [0, M) get 0; a negative count or missing arrays are errors
+    sc = p.output_scales(np.array([-1, 0, 6, 5], dtype=np.int64))
+    assert sc[0] == 0.0 and sc[2] == 0.0 and sc[1] > 0.0 and sc[3] > 0.0
+    assert L.slos_output_scales(p._h, None, -1, None) == -1
+    assert L.slos_output_scales(p._h, None, 3, None) == -1
+    assert L.slos_output_scales(None, None, 0, None) == -1
+    assert L.slos_sq_loss_backward_many(None, 1, None, None, None, None, 0, None, None, None, None) == -1
+    # device call on a host-only plan
+    assert L.slos_sq_loss_backward_many(p._h, 1, None, None, None, None, 0, None, None, None, None) == -1
+
+
 def test_select_validates_arguments():
     L = slos.lib()
     assert L.slos_select(None, None, None, 1, None, None) == -1
