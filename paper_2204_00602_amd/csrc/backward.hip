@@ -235,8 +235,12 @@ __global__ __launch_bounds__(256) void sq_loss_kernel(const typename Cb<T>::type
 // The same loss with the seed of the adjoint fused in: g_n[b] = c_S grad_a[b]
 // at the targets (c_S = scale[t], the normalisation a(S) = c_S A_n[S]) and 0
 // elsewhere, written straight into the last layer's gradient buffer (row b at
-// b * gn_stride).  The target values are formed exactly as the loss kernel and
-// the seed kernel form them one after the other, so the result is the same.
+// b * gn_stride).  Workgroup (x, b) owns states [x * SLOS_SEED_SLICE, ...) of
+// row b: it zeroes them, then writes the targets among them; workgroup 0 of
+// the row also forms the loss over all targets.  The values are formed
+// exactly as the loss kernel and the seed kernel form them one after the
+// other, and the loss in the same order, so the results are the same.
+#define SLOS_SEED_SLICE 2048u
 template <typename T>
 __global__ __launch_bounds__(256) void sq_loss_seed_kernel(const typename Cb<T>::type *__restrict__ a, uint64_t M,
                                                             const int64_t *__restrict__ ranks,
@@ -247,26 +251,33 @@ __global__ __launch_bounds__(256) void sq_loss_seed_kernel(const typename Cb<T>:
 {
     using C = typename Cb<T>::type;
     __shared__ double sh[256];
-    const uint64_t b = blockIdx.x;
+    const uint64_t b = blockIdx.y;
     a += b * M;
     gn += b * gn_stride;
     p_target += b * (uint64_t)count;
-    for (uint64_t r = threadIdx.x; r < M; r += 256) gn[r] = C{(T)0, (T)0};
+    const uint64_t lo = (uint64_t)blockIdx.x * SLOS_SEED_SLICE;
+    const uint64_t hi = lo + SLOS_SEED_SLICE < M ? lo + SLOS_SEED_SLICE : M;
+    for (uint64_t r = lo + threadIdx.x; r < hi; r += 256) gn[r] = C{(T)0, (T)0};
     __builtin_amdgcn_s_waitcnt(0);  // this wave's zeros have reached memory
     __syncthreads();
     double s = 0.0;
     for (int64_t t = threadIdx.x; t < count; t += 256) {
         const int64_t r = ranks[t];
         if (r < 0 || (uint64_t)r >= M) continue;  // outside the output set: ignored
+        const bool mine = (uint64_t)r >= lo && (uint64_t)r < hi;
+        if (!mine && blockIdx.x != 0) continue;
         const C v = a[r];
         const double P = (double)v.x * (double)v.x + (double)v.y * (double)v.y;
         const double d = P - p_target[t];
         s += d * d;
-        const T f = (T)(4.0 * d);
-        const C ga{f * v.x, f * v.y};
-        const double c = scale[t];
-        gn[r] = C{(T)(c * (double)ga.x), (T)(c * (double)ga.y)};
+        if (mine) {
+            const T f = (T)(4.0 * d);
+            const C ga{f * v.x, f * v.y};
+            const double c = scale[t];
+            gn[r] = C{(T)(c * (double)ga.x), (T)(c * (double)ga.y)};
+        }
     }
+    if (blockIdx.x != 0) return;
     sh[threadIdx.x] = s;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
@@ -538,12 +549,13 @@ int slos_launch_sq_loss_seed(const void *a, uint64_t M, const int64_t *ranks, co
                              const double *p_target, void *gn, uint64_t gn_stride, double *loss, int batch, int c64,
                              void *stream)
 {
+    const dim3 g((unsigned)((M + SLOS_SEED_SLICE - 1) / SLOS_SEED_SLICE), (unsigned)batch);
     if (c64)
-        hipLaunchKernelGGL(sq_loss_seed_kernel<float>, dim3(batch), dim3(256), 0, (hipStream_t)stream,
-                           (const float2 *)a, M, ranks, scale, count, p_target, (float2 *)gn, gn_stride, loss);
+        hipLaunchKernelGGL(sq_loss_seed_kernel<float>, g, dim3(256), 0, (hipStream_t)stream, (const float2 *)a, M,
+                           ranks, scale, count, p_target, (float2 *)gn, gn_stride, loss);
     else
-        hipLaunchKernelGGL(sq_loss_seed_kernel<double>, dim3(batch), dim3(256), 0, (hipStream_t)stream,
-                           (const double2 *)a, M, ranks, scale, count, p_target, (double2 *)gn, gn_stride, loss);
+        hipLaunchKernelGGL(sq_loss_seed_kernel<double>, g, dim3(256), 0, (hipStream_t)stream, (const double2 *)a, M,
+                           ranks, scale, count, p_target, (double2 *)gn, gn_stride, loss);
     return (int)hipGetLastError();
 }
 
