@@ -430,16 +430,17 @@ __device__ __forceinline__ void tile_compute(const TileIn<T, RT> &in, const Laye
     constexpr int kHS = TileIn<T, RT>::kHS, kCS = TileIn<T, RT>::kCS;
     const uint32_t *__restrict__ pred = p.pred + L.pred_off;
 
-    // Visit every term (output i, mode j, predecessor value) of the tile:
-    // high groups from registers (or, past kHS groups, straight from memory),
-    // low terms from the staged block.
-    // low-block element of a table entry: its 24-bit index times the element
+    // Low-block element of a table entry: its 24-bit index times the element
     // size with one 24-bit multiply-add, which ignores the mode byte on top
     // (the size is hidden from the optimiser, which would otherwise turn the
-    // multiply into a shift and a mask)
+    // multiply into a shift and a mask).
     uint32_t esz = (uint32_t)sizeof(C);
     asm volatile("" : "+v"(esz));
     auto low_at = [&](uint32_t e) -> C { return *(const C *)((const char *)lowbuf + __umul24(e, esz)); };
+
+    // Visit every term (output i, mode j, predecessor value) of the tile:
+    // high groups from registers (or, past kHS groups, straight from memory),
+    // low terms from the staged block.
     auto terms = [&](auto &&f) {
 #pragma unroll
         for (int g = 0; g < kHS; ++g) {
