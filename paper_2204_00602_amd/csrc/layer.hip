@@ -162,7 +162,9 @@ template <> struct Acc<float, SLOS_COMP_F64> {
     __device__ __forceinline__ double im() const { return i; }
 };
 
-// cache-policy operand of the global-to-LDS copy: bit 1 = non-temporal
+// cache-policy operand of the global-to-LDS copy: 0 = default, bit 1 =
+// non-temporal
+#define SLOS_CPOL_DEFAULT 0
 #define SLOS_CPOL_NT 2
 
 // ---- cross-lane helpers (wave64) -------------------------------------------
@@ -310,7 +312,14 @@ __device__ __forceinline__ uint32_t ld_buf_u32(const void *base, uint32_t off, u
 // instruction).  The copy starts at the 16-byte boundary at or below the
 // block, so the block begins `skew` bytes into the slice; up to 1 KiB past
 // the block is read as well (the layer buffers carry that slack).
-template <typename C>
+//
+// Cache policy CPOL: each input element is staged once per layer, but a low
+// block is also read whole as a high-mode block by the leaves one photon up
+// (high part h + e_j, one low photon fewer), so intermediate layers and the
+// batch kernel stage with the default policy, which keeps it in L2 for them;
+// the last layer of a large pass stages non-temporally (measured slightly
+// faster there, where the high-mode blocks fill the L2).
+template <typename C, int CPOL = SLOS_CPOL_DEFAULT>
 __device__ __forceinline__ const C *stage_low(const C *__restrict__ X, const Leaf &L, unsigned char *slice,
                                               int lane)
 {
@@ -318,13 +327,11 @@ __device__ __forceinline__ const C *stage_low(const C *__restrict__ X, const Lea
     const uintptr_t a0 = sa & ~(uintptr_t)15;
     const uint32_t skew = (uint32_t)(sa - a0);
     const uint32_t nbytes = skew + L.low_size * (uint32_t)sizeof(C);
-    // each input element is staged exactly once per layer, so the copy is
-    // non-temporal (cache policy NT) and leaves the L2 to the high-mode blocks
     for (uint32_t done = 0; done < nbytes; done += 1024u) {
         if (done + 16u * (uint32_t)lane < nbytes) {
             const void *src = (const void *)(a0 + done + 16u * (uint32_t)lane);
             __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void *)(slice + done), 16, 0,
-                                             SLOS_CPOL_NT);
+                                             CPOL);
         }
     }
     return (const C *)(slice + skew);
@@ -530,8 +537,8 @@ template <typename T, int MODE> constexpr uint32_t kStoreAlign()
 }
 
 // Stage the low block with all waves of the workgroup: 1 KiB chunk c of the
-// copy is issued by wave c % W.
-template <typename C>
+// copy is issued by wave c % W (cache policy as for stage_low).
+template <typename C, int CPOL>
 __device__ __forceinline__ const C *stage_low_team(const C *__restrict__ X, const Leaf &L, unsigned char *slice,
                                                    int lane, int wv, int W)
 {
@@ -543,7 +550,7 @@ __device__ __forceinline__ const C *stage_low_team(const C *__restrict__ X, cons
         if (done + 16u * (uint32_t)lane < nbytes) {
             const void *src = (const void *)(a0 + done + 16u * (uint32_t)lane);
             __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void *)(slice + done), 16, 0,
-                                             SLOS_CPOL_NT);
+                                             CPOL);
         }
     }
     return (const C *)(slice + skew);
@@ -634,7 +641,8 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? (RR == 2 ? 6 : 3) : (RR <= 2 
 
     while (li < p.nleaves) {
         const Leaf L = decode_head<WIDE>(cur);
-        const C *lowbuf = stage_low_team<C>(X, L, slice, lane, wv, W);
+        const C *lowbuf =
+            stage_low_team<C, MODE == SLOS_MODE_MID ? SLOS_CPOL_DEFAULT : SLOS_CPOL_NT>(X, L, slice, lane, wv, W);
         const bool refill = bat_next >= bat_end;
         // Refills alternate between the two slots starting with slot 1: the
         // slot written in iteration it is read after this iteration's barrier
