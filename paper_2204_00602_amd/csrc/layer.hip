@@ -426,8 +426,11 @@ __device__ __forceinline__ void tile_load(TileIn<T, RT> &in, const LayerParams &
 
 // sigma: the bias of the compensated mode (see Acc<float, SLOS_COMP_BIASED>).
 // omax collects max |Re a| + |Im a| over the complex64 outputs of a mid layer,
-// the input bound of a compensated next layer.
-template <typename T, int MODE, int COMP, int RT, bool WIDE>
+// the input bound of a compensated next layer.  CACHED_MID: a mid layer's
+// outputs are stored with the default cache policy instead of non-temporally
+// (the batch kernel, whose small layers are read back from the L2 by the next
+// layer; a large pass's layers outgrow the L2 and stream).
+template <typename T, int MODE, int COMP, int RT, bool WIDE, bool CACHED_MID = false>
 __device__ __forceinline__ void tile_compute(const TileIn<T, RT> &in, const LayerParams &p, const DescRegs<WIDE> &dr,
                                              const Leaf &L, const typename Cx<T>::type *__restrict__ X,
                                              const typename Cx<T>::type *u_lds, const typename Cx<T>::type *lowbuf,
@@ -496,8 +499,12 @@ __device__ __forceinline__ void tile_compute(const TileIn<T, RT> &in, const Laye
             const C a = acc[i].value();
             if (sizeof(T) == 4) omax = fmaxf(omax, (float)(fabs(a.x) + fabs(a.y)));
             T *y = (T *)((char *)Yb + in.off[i]);
-            __builtin_nontemporal_store(a.x, y);
-            __builtin_nontemporal_store(a.y, y + 1);
+            if (CACHED_MID) {
+                *(C *)y = a;
+            } else {
+                __builtin_nontemporal_store(a.x, y);
+                __builtin_nontemporal_store(a.y, y + 1);
+            }
         } else {
             const double f = L.fac_hi * in.lf[i];
             const double ar = acc[i].re() * f;
@@ -527,7 +534,7 @@ __device__ __forceinline__ void tile(const LayerParams &p, const DescRegs<WIDE> 
     TileIn<T, RT> in;
     constexpr bool comp = COMP != SLOS_COMP_NONE;
     tile_load<T, MODE, RT, WIDE, comp, comp || BATCH>(in, p, dr, L, X, t0, lane);
-    tile_compute<T, MODE, COMP, RT, WIDE>(in, p, dr, L, X, u_lds, lowbuf, sigma, t0, lane, psum, omax);
+    tile_compute<T, MODE, COMP, RT, WIDE, BATCH>(in, p, dr, L, X, u_lds, lowbuf, sigma, t0, lane, psum, omax);
 }
 
 // Outputs per 64-byte sector: complex values, or probabilities in MODE_PROB.
