@@ -214,14 +214,22 @@ struct DescRegs {
     uint32_t b;
 };
 
-template <bool WIDE>
+// A pass reads each descriptor once, non-temporally; the batch kernel
+// (CACHED) reads one (m, k) descriptor set for every instance of that m, so
+// it keeps them in the L2.
+template <bool WIDE, bool CACHED = false>
 __device__ __forceinline__ DescRegs<WIDE> load_desc(const void *descs, uint64_t li, int lane)
 {
     const uint32_t *w = (const uint32_t *)((const char *)descs + li * sizeof(typename DescT<WIDE>::type));
     DescRegs<WIDE> r;
     constexpr int nd = DescT<WIDE>::kDwords;
-    r.a = lane < nd ? __builtin_nontemporal_load(&w[lane]) : 0u;
-    r.b = (WIDE && lane + 64 < nd) ? __builtin_nontemporal_load(&w[64 + lane]) : 0u;
+    if (CACHED) {
+        r.a = lane < nd ? w[lane] : 0u;
+        r.b = (WIDE && lane + 64 < nd) ? w[64 + lane] : 0u;
+    } else {
+        r.a = lane < nd ? __builtin_nontemporal_load(&w[lane]) : 0u;
+        r.b = (WIDE && lane + 64 < nd) ? __builtin_nontemporal_load(&w[64 + lane]) : 0u;
+    }
     return r;
 }
 
@@ -739,7 +747,7 @@ __device__ __forceinline__ void batch_layer_leaves(const BatchParams &bp, const 
     lp.lowfac = bp.lowfac;
     const uint32_t nl = I.nleaves[k - 1];
     for (uint32_t li = first; li < nl; li += step) {
-        const DescRegs<false> d = load_desc<false>(bp.desc, (uint64_t)I.desc_off[k - 1] + li, lane);
+        const DescRegs<false> d = load_desc<false, true>(bp.desc, (uint64_t)I.desc_off[k - 1] + li, lane);
         const Leaf L = decode_head<false>(d);
         const C *lowbuf = stage_low<C>(X, L, slice, lane);
         __builtin_amdgcn_s_waitcnt(0);
