@@ -391,7 +391,7 @@ typedef struct slos_batch_s *slos_batch_t;
  * the big instances more waves), grid_blocks (workgroups, default 1024),
  * outputs_per_lane (default 2); other fields are ignored.
  * The whole batch runs in one kernel launch.  An instance whose last layer has
- * at least two tiles per wave runs on a whole workgroup (its waves share each
+ * at least four tiles per wave runs on a whole workgroup (its waves share each
  * layer, a barrier between layers); every other instance runs on a single
  * wave.  The host assigns both kinds largest-first to the least loaded
  * workgroup or wave, so no workgroup waits on another.

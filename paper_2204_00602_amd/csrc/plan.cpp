@@ -2041,14 +2041,14 @@ int slos_batch_plan(int count, const int32_t *ms, const int32_t *inputs, int fla
             cost[i] = c + 64.0 * n;
             pos += m;
         }
-        // Instances whose last layer has at least two tiles per wave run
+        // Instances whose last layer has at least four tiles per wave run
         // cooperatively on a workgroup; the rest run on single waves.  Both
         // lists are filled largest first, each instance to the least loaded
         // workgroup (load in wave time: cost / W) or wave slot (whose load
         // starts at its workgroup's cooperative load).
         const int G = std::min(o.grid_blocks, count);
         const int W = o.block_threads / 64;
-        const uint64_t coop_min = 2ull * (uint64_t)W * 64u * (uint64_t)o.outputs_per_lane;
+        const uint64_t coop_min = 4ull * (uint64_t)W * 64u * (uint64_t)o.outputs_per_lane;
         std::vector<int> order(count);
         for (int i = 0; i < count; ++i) order[i] = i;
         std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
