@@ -13,6 +13,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <tuple>
 #include <unordered_map>
 #include <new>
 #include <queue>
@@ -1988,6 +1989,7 @@ int slos_batch_plan(int count, const int32_t *ms, const int32_t *inputs, int fla
         b->out_off.assign(count + 1, 0);
         b->u_off.assign(count + 1, 0);
         uint32_t low_max = 0;
+        std::map<std::tuple<int, int, double>, std::pair<uint32_t, uint32_t>> shared;  // descriptor sets
         std::vector<double> cost(count);
         std::vector<uint64_t> inter(count, 0), last(count, 1);  // largest layer below n, layer n
         pos = 0;
@@ -2012,12 +2014,24 @@ int slos_batch_plan(int count, const int32_t *ms, const int32_t *inputs, int fla
             I.out_off = (uint64_t)b->out_off[i];
             double c = 0.0;
             for (int k = 1; k <= n; ++k) {
+                I.col[k - 1] = (uint8_t)photons[k - 1];
+                // A layer's descriptors depend on (m, k) only, except the last
+                // layer's normalisation, which also takes 1/sqrt(prod t!):
+                // instances that agree on those share one descriptor set.
+                const auto key = std::make_tuple(m, k, k == n ? P.norm_t : -1.0);
+                const auto hit = shared.find(key);
+                if (hit != shared.end()) {
+                    I.desc_off[k - 1] = hit->second.first;
+                    I.nleaves[k - 1] = hit->second.second;
+                }
                 std::vector<LeafRec> lv;
                 std::vector<uint8_t> hm;
-                P.gen_leaves(k, m - 1, k, (uint64_t)o.leaf_max, hm, lv);
-                I.col[k - 1] = (uint8_t)photons[k - 1];
-                I.desc_off[k - 1] = (uint32_t)b->desc.size();
-                I.nleaves[k - 1] = (uint32_t)lv.size();
+                if (hit == shared.end()) {
+                    P.gen_leaves(k, m - 1, k, (uint64_t)o.leaf_max, hm, lv);
+                    I.desc_off[k - 1] = (uint32_t)b->desc.size();
+                    I.nleaves[k - 1] = (uint32_t)lv.size();
+                    shared[key] = {I.desc_off[k - 1], I.nleaves[k - 1]};
+                }
                 std::vector<uint64_t> deltas;
                 std::vector<uint8_t> modes;
                 for (const LeafRec &L : lv) {
