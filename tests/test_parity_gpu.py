@@ -302,6 +302,41 @@ def test_config3_m24_n12_c128_sampled():
     torch.cuda.empty_cache()
 
 
+def _bunched_headline_input(kind):
+    if kind == "pairs":
+        return np.array([2] * 6 + [0] * 18, np.int32)  # 1/sqrt(prod t!) = 1/8
+    return inputs.random_input(24, 12, np.random.default_rng(105))  # <= 2 photons per mode
+
+
+@pytest.mark.parametrize("kind", ["pairs", "random"])
+@pytest.mark.parametrize("dtype,comp", [("c64", True), ("c128", False)])
+def test_headline_size_bunched_inputs_sampled(kind, dtype, comp):
+    """The m=24, n=12 pass with bunched inputs (repeated photon modes, the
+    1/sqrt(prod t!) factor of Eq. eqperm in every last-layer leaf) through the
+    launch shapes the benchmark uses: 2,000 uniform seeded outputs and the
+    100 most bunched vs the oracle's permanents, at the c64 and c128 bars."""
+    m, n = 24, 12
+    T = _bunched_headline_input(kind)
+    assert T.sum() == n and T.max() == 2
+    U = inputs.haar_unitary(m, 3)
+    p = slos.Plan(T, dtype, compensated=comp)
+    s = torch.zeros(1, dtype=torch.float64, device="cuda")
+    out = p.amplitudes(dev_u(U, dtype), sum_p=s)
+    torch.cuda.synchronize()
+    assert abs(float(s.item()) - 1.0) <= (1e-12 if dtype == "c128" else 1e-6)
+    S = np.concatenate([inputs.uniform_fock_states(m, n, 2000, 106), inputs.bunched_fock_states(m, n, 100)])
+    a = gather(p, out, S)
+    ref = oracle.amplitudes(U, T, S)
+    if dtype == "c128":
+        err = check_c128(a, ref, p.num_outputs)
+    else:
+        a = a.astype(np.complex128)
+        err = check_c64_probs(np.abs(a) ** 2, np.abs(ref) ** 2, p.num_outputs)
+    print(f"bunched headline {kind} {dtype}: max floored rel err {err:.3e}")
+    del out
+    torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("dtype,comp", [("c64", True), ("c64", "fp64"), ("c128", False)])
 def test_leaf_order_leaves_outputs_bit_identical(dtype, comp):
     """Each output is one thread's fixed-order sum, so the order in which the
