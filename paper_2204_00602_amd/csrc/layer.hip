@@ -458,14 +458,27 @@ __device__ __forceinline__ void tile_compute(const TileIn<T, RT> &in, const Laye
 
     // Visit every term (output i, mode j, predecessor value) of the tile:
     // high groups from registers (or, past kHS groups, straight from memory),
-    // low terms from the staged block.
-    auto terms = [&](auto &&f) {
+    // low terms from the staged block.  f takes the mode (coefficient from
+    // the U column in LDS), fu a coefficient already loaded.
+    auto terms = [&](auto &&f, auto &&fu) {
 #pragma unroll
         for (int g = 0; g < kHS; ++g) {
             if (g < L.nh) {
                 const int j = group_mode<WIDE>(dr, g);
+                if constexpr (COMP != SLOS_COMP_NONE && !CACHED_MID) {
+                    // a group's coefficient U[j, i_k] is the same for the whole
+                    // wave: read it through the scalar cache (constant address
+                    // space; U is not written while the kernel runs) straight
+                    // into an SGPR operand of the multiply-adds
+                    typedef __attribute__((address_space(4))) const T ConstT;
+                    const ConstT *q = (const ConstT *)p.U + 2 * ((size_t)j * p.m + p.col);
+                    const C uj{q[0], q[1]};
 #pragma unroll
-                for (int i = 0; i < RT; ++i) f(i, j, in.v[g][i]);
+                    for (int i = 0; i < RT; ++i) fu(i, uj, in.v[g][i]);
+                } else {
+#pragma unroll
+                    for (int i = 0; i < RT; ++i) f(i, j, in.v[g][i]);
+                }
             }
         }
         for (int g = kHS; g < L.nh; ++g) {  // leaves with more than kHS high groups
@@ -496,7 +509,8 @@ __device__ __forceinline__ void tile_compute(const TileIn<T, RT> &in, const Laye
     for (int i = 0; i < RT; ++i) acc[i].zero();
 #pragma unroll
     for (int i = 0; i < RT; ++i) acc[i].start(sigma);
-    terms([&](int i, int j, const C x) { acc[i].mac(u_lds[j], x); });
+    terms([&](int i, int j, const C x) { acc[i].mac(u_lds[j], x); },
+          [&](int i, const C uj, const C x) { acc[i].mac(uj, x); });
 
     // ---- store (through the leaf's wave-uniform output base)
     T *Yb = (T *)p.Y + (MODE == SLOS_MODE_PROB ? 1u : 2u) * L.out_base;
