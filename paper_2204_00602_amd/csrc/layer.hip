@@ -465,11 +465,13 @@ __device__ __forceinline__ void tile_compute(const TileIn<T, RT> &in, const Laye
         for (int g = 0; g < kHS; ++g) {
             if (g < L.nh) {
                 const int j = group_mode<WIDE>(dr, g);
-                if constexpr (COMP != SLOS_COMP_NONE && !CACHED_MID) {
+                if constexpr ((COMP == SLOS_COMP_BIASED || COMP == SLOS_COMP_TWOSUM) && !CACHED_MID) {
                     // a group's coefficient U[j, i_k] is the same for the whole
                     // wave: read it through the scalar cache (constant address
                     // space; U is not written while the kernel runs) straight
-                    // into an SGPR operand of the multiply-adds
+                    // into an SGPR operand of the multiply-adds (the two-sum
+                    // layers, which are issue-bound; the others keep the LDS
+                    // column)
                     typedef __attribute__((address_space(4))) const T ConstT;
                     const ConstT *q = (const ConstT *)p.U + 2 * ((size_t)j * p.m + p.col);
                     const C uj{q[0], q[1]};
